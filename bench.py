@@ -1,0 +1,154 @@
+"""Benchmark of the tactile MLS-MPM hot path on one MI355X.
+
+One step = one tactile frame of the GelSight-sized press: S explicit MLS-MPM
+substeps of the 1.6M-particle block (block sort, P2G, grid update with the
+rigid-indenter contact, G2P with the neo-Hookean update), then the 200 x 200
+depth map and the 480 x 640 Phong image. The metric is particle-substeps/s
+over the timed frames. Inputs are synthetic and resident on the GPU before
+the timed region starts.
+
+Prints ONE JSON line. With --gpus above 1 it exits: this build runs on one
+GPU (the contacts and the block are independent per GPU; see the sharding
+notes of the design document).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E nameplate, GB/s
+
+# Algorithmic bytes (FP32) per unit, see the kernel table of the design notes:
+#   P2G: perm 4 + u 12 + v 12 + A 36 per particle; mass+momentum flush 16 per active node
+#   G2P: perm 4 + u 12 + H 36 read, u 12 + v 12 + H 36 + A 36 + key 4 written per particle;
+#        velocity 12 per active node
+BYTES_PER_PARTICLE = {"p2g": 64, "g2p": 152}
+BYTES_PER_NODE = {"p2g": 16, "g2p": 12}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed frames")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed frames")
+    ap.add_argument("--substeps", type=int, default=50, help="MPM substeps per frame")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, budget_s):
+    """The FP64 oracle (single thread) on the same workload for as many
+    substeps as fit in about `budget_s` seconds."""
+    import oracle
+    oracle.build(force=False)
+    sim = oracle.OracleSim(wl["cfg"], wl["poses"][0])
+    n = int(sim.N)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        st = sim.step(wl["poses"][k + 1], wl["dt"])
+        if st != 0:
+            raise RuntimeError(f"oracle failed with status {st}")
+        k += 1
+        if time.perf_counter() - t0 > budget_s or k + 1 >= len(wl["poses"]):
+            break
+    el = time.perf_counter() - t0
+    return {"value": n * k / el, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {k} substeps of the same {n}-particle press, FP64, one thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2301_08343_amd import workloads as W
+    from paper_2301_08343_amd.sim import Sim
+
+    S = args.substeps
+    total_sub = (args.warmup + args.steps) * S
+    wl = W.gelsight_contact(seed=args.seed, steps=total_sub)
+    cfg, poses, dt, rp = wl["cfg"], wl["poses"], wl["dt"], wl["render"]
+    torch.cuda.set_device(0)
+    sim = Sim(cfg, poses[0], precision="f32", tile=args.tile)
+    N = sim.N
+
+    def frame(f):
+        sim.run(poses[f * S + 1:(f + 1) * S + 1], dt)
+        sim.heightmap()
+        return sim.render(rp)
+
+    for f in range(args.warmup):
+        frame(f)
+    sim.sync()
+    sim.timing_enable(("p2g", "g2p"))
+    sim.timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(args.warmup, args.warmup + args.steps):
+        img = frame(f)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timing = sim.timing_read(reset=True)
+    sim.timing_enable(())
+    sim.sync()
+    # active nodes of the final state (outside the timed region)
+    sim.p2g(dt)
+    M, _ = sim.read_grid(0)
+    active = int((M > 0).sum().item())
+    sim.grid_update(poses[-1], dt)
+    sim.g2p(dt)
+    sim.sync()
+    assert bool(torch.isfinite(img).all())
+
+    value = N * S * args.steps / el
+    k_ms = {k: timing[k][0] / max(1, timing[k][1]) for k in ("p2g", "g2p")}
+    dom = max(k_ms, key=lambda k: timing[k][0])
+    algo_bytes = BYTES_PER_PARTICLE[dom] * N + BYTES_PER_NODE[dom] * active
+    achieved = algo_bytes / (k_ms[dom] * 1e-3) / 1e9
+    out = {
+        "metric": "MPM particle-substeps/s",
+        "value": value,
+        "unit": "particle-substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"gelsight_press_{W.SHAPE_NAMES[cfg['shape']]}_1.6M_fp32",
+                   "particles": N, "lattice": list(cfg["n"]), "grid": list(cfg["gn"]),
+                   "substeps_per_step": S, "dt": dt, "depth_m": wl["depth"],
+                   "heightmap": [cfg["n"][1], cfg["n"][0]], "image": [rp["h"], rp["w"]],
+                   "tile": args.tile},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": k_ms[dom], "algorithmic_bytes_per_launch": algo_bytes,
+                     "active_nodes": active},
+        "kernel_ms": {k: v[0] / max(1, v[1]) for k, v in timing.items() if v[1]},
+    }
+    if not args.no_cpu_baseline:
+        wl_cpu = W.gelsight_contact(seed=args.seed, steps=2000)
+        out["cpu_baseline"] = cpu_baseline(wl_cpu, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * tacchi.h -- C ABI of the MI355X (gfx950) tactile elastomer simulator.
+ *
+ * The library simulates an optical tactile sensor's elastomer pressed by a
+ * rigid indenter with the explicit MLS-MPM substep of the Tacchi paper
+ * (Sec. III-A, Eqs. 1-11) and turns the deformed top surface into a depth map
+ * and a Phong-shaded tactile image (Sec. III-B, Eqs. 12-14). The calls follow
+ * the paper's statement of the problem (Sec. III-C, Fig. 3): the elastomer is
+ * a particle block with Young's modulus and Poisson's ratio (Sec. III-D,
+ * Sec. IV-B); each simulation step the host simulator supplies the indenter
+ * pose; the outputs are the depth map and the tactile image.
+ *
+ * Conventions shared by every call
+ *  - SI units (m, s, kg, Pa). World frame; the sensor looks along +z at the
+ *    elastomer from below, the indenter comes from +z.
+ *  - Memory: the caller owns all device memory. `tacchi_workspace_bytes`
+ *    sizes one device buffer; `tacchi_create` carves every array out of it
+ *    (256-byte aligned base required) and allocates no device memory. The
+ *    workspace must outlive the handle. Host-side inputs are copied.
+ *  - Streams: every device operation of a handle is enqueued on the HIP
+ *    stream given at creation (NULL = the legacy default stream).
+ *    Calls are asynchronous unless stated otherwise.
+ *  - Errors: no exception crosses the ABI. Each call returns a tacchi_status;
+ *    the message of the last failure on the calling thread is in
+ *    `tacchi_last_error()`. Device-side faults (non-finite state, inverted
+ *    elements under neo-Hookean, particles leaving the grid) set a device
+ *    error word that is reported by the next synchronising call
+ *    (`tacchi_sync`, `tacchi_heightmap`, `tacchi_render`, `tacchi_read_*`,
+ *    `tacchi_indenter_force`); the handle keeps working but its state is
+ *    then undefined until rewritten with `tacchi_write_particles`.
+ *  - Particle p of the lattice (i, j, k), i fastest, is p = i + n0*(j + n1*k);
+ *    k = 0 is the bottom layer (bonded to the sensor), k = n2-1 the contact
+ *    surface. Particle arrays are structure-of-arrays in the simulation
+ *    precision: x[3][N], v[3][N], C[9][N], F[9][N] (row-major 3x3, entry
+ *    (r, c) at [3r+c][N]).
+ *  - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef TACCHI_H
+#define TACCHI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tacchi_status;
+enum {
+    TACCHI_OK = 0,
+    TACCHI_E_ARG = -1,          /* invalid argument or configuration */
+    TACCHI_E_WORKSPACE = -2,    /* workspace missing, too small or misaligned */
+    TACCHI_E_DEVICE = -3,       /* a HIP call failed */
+    TACCHI_E_UNSTABLE = -4,     /* non-finite state, J <= 0 (neo-Hookean), dt above the CFL limit */
+    TACCHI_E_OUT_OF_GRID = -5,  /* a particle's 3x3x3 stencil left the grid */
+    TACCHI_E_STATE = -6         /* call not valid in the handle's current state */
+};
+
+enum { TACCHI_F64 = 0, TACCHI_F32 = 1 };
+enum { TACCHI_NEOHOOKEAN = 0, TACCHI_COROTATED = 1 };
+enum { TACCHI_NO_INDENTER = -1, TACCHI_SPHERE = 0, TACCHI_CYLINDER = 1, TACCHI_CONE = 2,
+       TACCHI_EDGE = 3, TACCHI_TEXTURED_PLATE = 4 };
+
+/* Elastomer block sampled by a cell-centred particle lattice: particle
+ * (i, j, k) rests at origin + ((i, j, k) + 1/2) * size / n. */
+typedef struct { double origin[3], size[3]; int32_t n[3]; } tacchi_block;
+/* Background grid: node (a, b, c) at origin + (a, b, c) * dx, n nodes per axis. */
+typedef struct { double origin[3]; double dx; int32_t n[3]; } tacchi_grid;
+/* Hyperelastic material: E [Pa], nu, rho [kg/m^3], model TACCHI_NEOHOOKEAN or
+ * TACCHI_COROTATED. */
+typedef struct { double E, nu, rho; int32_t model; } tacchi_material;
+/* Rigid indenter, described in its own frame (lowest point at the origin,
+ * +z away from the gel):
+ *   SPHERE          p[0] = radius
+ *   CYLINDER        p[0] = radius of a flat circular punch
+ *   CONE            p[0] = half-angle [rad], p[1] = tip rounding radius
+ *   EDGE            p[0] = half-angle [rad], p[1] = tip rounding radius;
+ *                   a wedge whose edge runs along the indenter y axis
+ *   TEXTURED_PLATE  p[0] = half-width of a square punch, p[1] = amplitude,
+ *                   p[2] = wavelength of the gradient noise on its bottom face
+ *                   (noise lattice hashed from `seed`) */
+typedef struct { int32_t shape; double p[8]; uint64_t seed; } tacchi_indenter;
+/* Indenter pose: position of the indenter-frame origin and unit quaternion
+ * (w, x, y, z) rotating indenter-frame vectors into the world frame. */
+typedef struct { double pos[3], quat[4]; } tacchi_pose;
+
+typedef struct {
+    tacchi_block block;
+    tacchi_grid grid;
+    tacchi_material mat;
+    tacchi_indenter ind;
+    tacchi_pose pose0;          /* indenter pose at t = 0 */
+    double gravity[3];          /* m/s^2 */
+    int32_t n_fixed_layers;     /* bottom lattice layers held at v = 0 (Eq. 10), >= 1 */
+    int32_t precision;          /* TACCHI_F64 or TACCHI_F32 */
+    int32_t tile;               /* grid block edge in nodes: 4 or 8; 0 picks 8 */
+} tacchi_config;
+
+/* Phong shading constants (Eq. 12): ambient ka*ia, diffuse kd, specular ks,
+ * shininess alpha; three distant lights (red, green, blue channel) at
+ * elevation light_elev_deg toward the camera and azimuths light_azim_deg;
+ * pitch = metres per pixel (the r of Eq. 14). */
+typedef struct {
+    double ka_ia, kd, ks, alpha, light_elev_deg, light_azim_deg[3], pitch;
+} tacchi_render_params;
+
+typedef struct tacchi_sim tacchi_sim;   /* opaque, host memory owned by the library */
+
+/* Bytes of device workspace a handle for `cfg` needs (0 if cfg is invalid;
+ * the reason is then in tacchi_last_error()). */
+size_t tacchi_workspace_bytes(const tacchi_config *cfg);
+
+/* Validate `cfg` (Sec. III-D guidelines: the grid encloses the block with at
+ * least 3 nodes of margin on every side; the bottom face lies on a node plane;
+ * dx >= lattice spacing; n_fixed_layers >= 1; E > 0; 0 <= nu < 0.5; rho > 0),
+ * carve the workspace and initialise the particles (Eq. 1: rest lattice,
+ * v = 0, C = 0, F = I). `hip_stream` is a hipStream_t (may be NULL).
+ * Errors: E_ARG, E_WORKSPACE, E_DEVICE. */
+tacchi_status tacchi_create(const tacchi_config *cfg, void *dev_ws, size_t ws_bytes,
+                            void *hip_stream, tacchi_sim **out);
+
+/* One explicit substep from the current indenter pose to `pose_end` over dt
+ * (Sec. III-A: particle-to-grid Eqs. 2-5, grid velocity Eq. 6 with the rigid
+ * indenter contact, grid-to-particle Eqs. 7-9, special cases Eq. 10 and
+ * advection Eq. 11). Sorting particles into grid blocks is part of the step.
+ * Asynchronous. Errors: E_ARG (dt <= 0), E_UNSTABLE (dt * c_p / dx > 1 with
+ * c_p = sqrt((lambda + 2 mu)/rho)), E_DEVICE. */
+tacchi_status tacchi_step(tacchi_sim *sim, const tacchi_pose *pose_end, double dt);
+
+/* `n` substeps of size dt; substep s ends at poses[s]. Asynchronous. */
+tacchi_status tacchi_run(tacchi_sim *sim, const tacchi_pose *poses, int32_t n, double dt);
+
+/* The three phases of tacchi_step, for callers that inspect the grid:
+ * tacchi_p2g (sort + particle-to-grid), tacchi_grid_update (grid velocity and
+ * contact toward `pose_end`), tacchi_g2p (grid-to-particle; commits
+ * `pose_end` as the current pose). They must be called in this order;
+ * otherwise E_STATE. */
+tacchi_status tacchi_p2g(tacchi_sim *sim, double dt);
+tacchi_status tacchi_grid_update(tacchi_sim *sim, const tacchi_pose *pose_end, double dt);
+tacchi_status tacchi_g2p(tacchi_sim *sim, double dt);
+
+/* Dense copy of the grid in node order (a fastest): after tacchi_p2g,
+ * which = 0 gives node mass M[n] and momentum P[3][n] (kg, kg m/s); after
+ * tacchi_grid_update, which = 1 gives M[n] unset and velocity V[3][n] (m/s).
+ * Buffers are in the simulation precision, on device if on_device != 0.
+ * Synchronises. */
+tacchi_status tacchi_read_grid(tacchi_sim *sim, int32_t which, void *M, void *vec,
+                               int32_t on_device);
+
+/* Depth map of the contact surface (Sec. III-B): out[j][i] = world z of
+ * top-layer particle (i, j, n2-1), n1 x n0 values in the simulation
+ * precision. Synchronises (and reports the device error word). */
+tacchi_status tacchi_heightmap(tacchi_sim *sim, void *out, int32_t out_on_device);
+
+/* Tactile image (Sec. III-B, Eqs. 12-14): an h x w crop centred on the top
+ * face at `pitch` m/pixel; the depth map is resampled bilinearly at the pixel
+ * centres (rest coordinates), normals come from central differences
+ * [-1, 0, 1]/(2 pitch) with replicated borders, each channel is lit by its
+ * light with Phong's model (dot products clamped at 0, specular only where
+ * the light faces the surface, result clamped to [0, 1]). rgb is float32
+ * [h][w][3]. Synchronises. */
+tacchi_status tacchi_render(tacchi_sim *sim, const tacchi_render_params *rp, float *rgb,
+                            int32_t h, int32_t w, int32_t out_on_device);
+
+/* Particle state in SoA layout (see the conventions); any pointer may be
+ * NULL to skip that array. Synchronises. */
+tacchi_status tacchi_read_particles(tacchi_sim *sim, void *x, void *v, void *C, void *F,
+                                    int32_t on_device);
+/* Overwrite the particle state (all four arrays required); used to restore a
+ * checkpoint or inject a state. Clears the device error word. */
+tacchi_status tacchi_write_particles(tacchi_sim *sim, const void *x, const void *v,
+                                     const void *C, const void *F, int32_t on_device);
+
+/* Reaction force [N] on the indenter over the last substep: sum over contact
+ * nodes of M (V_before - V_indenter) / dt. Synchronises. */
+tacchi_status tacchi_indenter_force(tacchi_sim *sim, double f[3]);
+
+/* Current indenter pose (host copy, no sync). */
+tacchi_status tacchi_get_pose(const tacchi_sim *sim, tacchi_pose *pose);
+
+/* Number of particles N of the handle. */
+int64_t tacchi_num_particles(const tacchi_sim *sim);
+
+/* Drain the handle's stream and report the device error word:
+ * E_UNSTABLE, E_OUT_OF_GRID or OK. */
+tacchi_status tacchi_sync(tacchi_sim *sim);
+
+/* Kernel timing with HIP events on the handle's stream. Kernel classes:
+ * 0 scan of the block counts, 1 particle scatter, 2 P2G, 3 grid update,
+ * 4 G2P, 5 depth map, 6 render. tacchi_timing_enable brackets every later
+ * launch of the classes set in `class_mask` (bit k = class k; 0 disables)
+ * with a pair of events; tacchi_timing_read synchronises and returns, per
+ * class, the summed elapsed milliseconds and the launch count since the last
+ * reset (reset != 0 clears them afterwards). ms and counts hold
+ * TACCHI_NUM_KERNEL_CLASSES entries. */
+#define TACCHI_NUM_KERNEL_CLASSES 7
+tacchi_status tacchi_timing_enable(tacchi_sim *sim, uint32_t class_mask);
+tacchi_status tacchi_timing_read(tacchi_sim *sim, double *ms, int64_t *counts, int32_t reset);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+void tacchi_destroy(tacchi_sim *sim);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *tacchi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TACCHI_H */

@@ -1,0 +1,942 @@
+// Host side of libtacchi: configuration checks, workspace carving, per-step
+// indenter kinematics and kernel launches on the caller's HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tacchi.h"
+#include "sim_kernels.hpp"
+
+using namespace tacchi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tacchi_status fail(tacchi_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define TC_HIP(expr)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(TACCHI_E_DEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TC_LAUNCHED()                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = hipGetLastError();                                                       \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(TACCHI_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Sizes and material constants derived from a validated configuration.
+struct Derived {
+    int64_t N = 0;
+    int n[3] = {0, 0, 0};
+    int g[3] = {0, 0, 0};
+    int B = 8;
+    int nb[3] = {0, 0, 0};
+    int nblk = 0;
+    int64_t nodes = 0;
+    double dx = 0, h[3] = {0, 0, 0}, m = 0, V0 = 0, mu = 0, lambda = 0, cp = 0;
+    double xr[3] = {0, 0, 0};
+    int floor_node = 0;
+    size_t es = 8;
+};
+
+struct Layout {
+    size_t u, v, H, A, key, perm, cnt, off, cursor, MP, V, err, force, fallback, hmap, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const Derived &d)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    const size_t N = (size_t)d.N, es = d.es;
+    L.u = take(3 * N * es);
+    L.v = take(3 * N * es);
+    L.H = take(9 * N * es);
+    L.A = take(9 * N * es);
+    L.key = take(N * 4);
+    L.perm = take(N * 4);
+    L.cnt = take((size_t)d.nblk * 4);
+    L.off = take(((size_t)d.nblk + 1) * 4);
+    L.cursor = take((size_t)d.nblk * 4);
+    L.MP = take((size_t)d.nodes * 4 * es);
+    L.V = take((size_t)d.nodes * 4 * es);
+    L.err = take(64);
+    L.force = take(64);
+    L.fallback = take(64);
+    L.hmap = take((size_t)d.n[0] * d.n[1] * es);
+    L.total = o;
+    return L;
+}
+
+tacchi_status check_indenter(const tacchi_indenter &ind)
+{
+    switch (ind.shape) {
+    case TACCHI_NO_INDENTER:
+        return TACCHI_OK;
+    case TACCHI_SPHERE:
+    case TACCHI_CYLINDER:
+        if (!(ind.p[0] > 0)) return fail(TACCHI_E_ARG, "indenter radius must be > 0");
+        return TACCHI_OK;
+    case TACCHI_CONE:
+    case TACCHI_EDGE:
+        if (!(ind.p[0] > 0 && ind.p[0] < 0.5 * kPi)) return fail(TACCHI_E_ARG, "half-angle must be in (0, pi/2)");
+        if (!(ind.p[1] >= 0)) return fail(TACCHI_E_ARG, "tip radius must be >= 0");
+        return TACCHI_OK;
+    case TACCHI_TEXTURED_PLATE:
+        if (!(ind.p[0] > 0 && ind.p[2] > 0 && ind.p[1] >= 0))
+            return fail(TACCHI_E_ARG, "plate needs half-width > 0, amplitude >= 0, wavelength > 0");
+        return TACCHI_OK;
+    default:
+        return fail(TACCHI_E_ARG, "unknown indenter shape");
+    }
+}
+
+tacchi_status derive(const tacchi_config *c, Derived *d)
+{
+    if (!c) return fail(TACCHI_E_ARG, "config is NULL");
+    if (c->precision != TACCHI_F64 && c->precision != TACCHI_F32) return fail(TACCHI_E_ARG, "bad precision");
+    if (c->mat.model != TACCHI_NEOHOOKEAN && c->mat.model != TACCHI_COROTATED)
+        return fail(TACCHI_E_ARG, "bad material model");
+    if (c->tile != 0 && c->tile != 4 && c->tile != 8) return fail(TACCHI_E_ARG, "tile must be 0, 4 or 8");
+    if (!(c->mat.E > 0) || !(c->mat.nu >= 0 && c->mat.nu < 0.5) || !(c->mat.rho > 0))
+        return fail(TACCHI_E_ARG, "material needs E > 0, 0 <= nu < 0.5, rho > 0");
+    if (!(c->grid.dx > 0)) return fail(TACCHI_E_ARG, "grid dx must be > 0");
+    const double dx = c->grid.dx;
+    int64_t N = 1, nodes = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (c->block.n[a] < 2) return fail(TACCHI_E_ARG, "lattice needs >= 2 particles per axis");
+        if (c->grid.n[a] < 7) return fail(TACCHI_E_ARG, "grid needs >= 7 nodes per axis");
+        if (!(c->block.size[a] > 0)) return fail(TACCHI_E_ARG, "block size must be > 0");
+        N *= c->block.n[a];
+        nodes *= c->grid.n[a];
+        d->h[a] = c->block.size[a] / c->block.n[a];
+        if (dx < d->h[a] * (1 - 1e-9)) return fail(TACCHI_E_ARG, "grid spacing must be >= lattice spacing");
+        const double lo = (c->block.origin[a] - c->grid.origin[a]) / dx;
+        const double hi = (c->block.origin[a] + c->block.size[a] - c->grid.origin[a]) / dx;
+        if (lo < 3 - 1e-9 || hi > (c->grid.n[a] - 1 - 3) + 1e-9)
+            return fail(TACCHI_E_ARG, "grid must enclose the block with >= 3 nodes of margin on every side");
+        d->n[a] = c->block.n[a];
+        d->g[a] = c->grid.n[a];
+        d->xr[a] = lo + 0.5 * d->h[a] / dx;
+    }
+    if (N >= (int64_t)1 << 31) return fail(TACCHI_E_ARG, "too many particles (limit 2^31 - 1)");
+    const double z0 = (c->block.origin[2] - c->grid.origin[2]) / dx;
+    if (std::fabs(z0 - std::round(z0)) > 1e-6) return fail(TACCHI_E_ARG, "block bottom face must lie on a grid node plane");
+    if (c->n_fixed_layers < 1 || c->n_fixed_layers > c->block.n[2])
+        return fail(TACCHI_E_ARG, "n_fixed_layers must be in [1, n2]");
+    tacchi_status st = check_indenter(c->ind);
+    if (st != TACCHI_OK) return st;
+    const double *q = c->pose0.quat;
+    if (!(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] > 0)) return fail(TACCHI_E_ARG, "pose0 quaternion is zero");
+    d->N = N;
+    d->dx = dx;
+    d->B = c->tile == 0 ? 8 : c->tile;
+    d->nblk = 1;
+    for (int a = 0; a < 3; ++a) {
+        d->nb[a] = (d->g[a] + d->B - 1) / d->B;
+        d->nblk *= d->nb[a];
+    }
+    d->nodes = (int64_t)d->nblk * d->B * d->B * d->B;
+    d->V0 = d->h[0] * d->h[1] * d->h[2];
+    d->m = c->mat.rho * d->V0;
+    d->mu = c->mat.E / (2 * (1 + c->mat.nu));
+    d->lambda = c->mat.E * c->mat.nu / ((1 + c->mat.nu) * (1 - 2 * c->mat.nu));
+    d->cp = std::sqrt((d->lambda + 2 * d->mu) / c->mat.rho);
+    d->floor_node = (int)std::lround(z0);
+    d->es = c->precision == TACCHI_F64 ? 8 : 4;
+    (void)nodes;
+    return TACCHI_OK;
+}
+
+void quat_normalise(const double q[4], double out[4])
+{
+    const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) out[k] = q[k] / n;
+}
+
+void quat_matrix(const double qin[4], double R[9])
+{
+    double q[4];
+    quat_normalise(qin, q);
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Angular velocity of the rigid rotation taking q0 to q1 over dt (shortest arc).
+void angular_velocity(const double q0in[4], const double q1in[4], double dt, double om[3])
+{
+    double a[4], b[4];
+    quat_normalise(q0in, a);
+    quat_normalise(q1in, b);
+    // r = b * conj(a)
+    const double rw = b[0] * a[0] + b[1] * a[1] + b[2] * a[2] + b[3] * a[3];
+    const double rx = -b[0] * a[1] + b[1] * a[0] - b[2] * a[3] + b[3] * a[2];
+    const double ry = -b[0] * a[2] + b[1] * a[3] + b[2] * a[0] - b[3] * a[1];
+    const double rz = -b[0] * a[3] - b[1] * a[2] + b[2] * a[1] + b[3] * a[0];
+    double s = rw < 0 ? -1.0 : 1.0;
+    const double vx = s * rx, vy = s * ry, vz = s * rz, w = s * rw;
+    const double vn = std::sqrt(vx * vx + vy * vy + vz * vz);
+    if (vn == 0.0) {
+        om[0] = om[1] = om[2] = 0.0;
+        return;
+    }
+    const double ang = 2.0 * std::atan2(vn, w);
+    om[0] = vx / vn * ang / dt;
+    om[1] = vy / vn * ang / dt;
+    om[2] = vz / vn * ang / dt;
+}
+
+template <typename T>
+IndenterDev<T> make_indenter(const tacchi_config &cfg, const double pose0[7], const double pose1[7], double dt)
+{
+    IndenterDev<T> I{};
+    const tacchi_indenter &ind = cfg.ind;
+    I.shape = ind.shape;
+    I.seed = ind.seed;
+    for (int k = 0; k < 4; ++k) I.p[k] = T(0);
+    if (ind.shape == TACCHI_CONE || ind.shape == TACCHI_EDGE) {
+        I.p[0] = T(std::sin(ind.p[0]));
+        I.p[1] = T(std::cos(ind.p[0]));
+        I.p[2] = T(ind.p[1]);
+    } else {
+        for (int k = 0; k < 3; ++k) I.p[k] = T(ind.p[k]);
+    }
+    const double dx = cfg.grid.dx;
+    I.dx = T(dx);
+    double R[9], om[3];
+    quat_matrix(pose0 + 3, R);
+    angular_velocity(pose0 + 3, pose1 + 3, dt, om);
+    for (int k = 0; k < 9; ++k) I.R[k] = T(R[k]);
+    for (int a = 0; a < 3; ++a) {
+        I.tip[a] = T((pose0[a] - cfg.grid.origin[a]) / dx);
+        I.vc[a] = T((pose1[a] - pose0[a]) / dt / dx);
+        I.om[a] = T(om[a]);
+    }
+    return I;
+}
+
+}  // namespace
+
+struct tacchi_sim {
+    tacchi_config cfg;
+    Derived d;
+    Layout L;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    double pose[7];
+    double pending[7];
+    int phase = 0;        // 0: ready for P2G, 1: P2G done, 2: grid updated
+    double dtA = 0.0;     // dt the stored affine matrices were formed with
+    double dt_phase = 0.0;
+    SimDev<float> sf;
+    SimDev<double> sd;
+    void *stage = nullptr;  // pinned host staging for host-side arguments
+    size_t stage_bytes = 0;
+    // kernel timing (see tacchi_timing_enable)
+    uint32_t timing_mask = 0;
+    struct Pending { int cls; hipEvent_t a, b; };
+    std::vector<Pending> timed;
+    std::vector<hipEvent_t> event_pool;
+    double timing_ms[TACCHI_NUM_KERNEL_CLASSES] = {0};
+    int64_t timing_n[TACCHI_NUM_KERNEL_CLASSES] = {0};
+};
+
+namespace {
+
+enum { KC_SCAN = 0, KC_SCATTER = 1, KC_P2G = 2, KC_GRID = 3, KC_G2P = 4, KC_HEIGHT = 5, KC_RENDER = 6 };
+
+hipEvent_t pool_event(tacchi_sim *s)
+{
+    if (!s->event_pool.empty()) {
+        hipEvent_t e = s->event_pool.back();
+        s->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel launch with events when its class is being timed.
+struct KernelTimer {
+    tacchi_sim *s;
+    int cls;
+    hipEvent_t a = nullptr;
+    KernelTimer(tacchi_sim *s_, int cls_) : s(s_), cls(cls_)
+    {
+        if (s->timing_mask & (1u << cls)) {
+            a = pool_event(s);
+            if (a) (void)hipEventRecord(a, s->stream);
+        }
+    }
+    ~KernelTimer()
+    {
+        if (!a) return;
+        hipEvent_t b = pool_event(s);
+        if (!b) return;
+        (void)hipEventRecord(b, s->stream);
+        s->timed.push_back({cls, a, b});
+    }
+};
+
+template <typename T>
+SimDev<T> make_simdev(tacchi_sim *s)
+{
+    const Derived &d = s->d;
+    const Layout &L = s->L;
+    SimDev<T> S{};
+    S.N = d.N;
+    S.n0 = d.n[0]; S.n1 = d.n[1]; S.n2 = d.n[2];
+    S.g0 = d.g[0]; S.g1 = d.g[1]; S.g2 = d.g[2];
+    S.nb0 = d.nb[0]; S.nb1 = d.nb[1]; S.nb2 = d.nb[2];
+    S.nblk = d.nblk;
+    S.div_n0 = make_fastdiv((uint32_t)d.n[0]);
+    S.div_n1 = make_fastdiv((uint32_t)d.n[1]);
+    for (int a = 0; a < 3; ++a) {
+        S.xr[a] = T(d.xr[a]);
+        S.hr[a] = T(d.h[a] / d.dx);
+        S.grav[a] = T(s->cfg.gravity[a] / d.dx);
+    }
+    S.m = T(d.m);
+    S.vcoef = T(d.V0 * 4.0 / (d.dx * d.dx));
+    S.mu = T(d.mu);
+    S.lambda = T(d.lambda);
+    S.floor_node = d.floor_node;
+    S.wall = 3;
+    S.fixed_count = (int64_t)s->cfg.n_fixed_layers * d.n[0] * d.n[1];
+    char *w = s->ws;
+    S.u = (T *)(w + L.u);
+    S.v = (T *)(w + L.v);
+    S.H = (T *)(w + L.H);
+    S.A = (T *)(w + L.A);
+    S.key = (int *)(w + L.key);
+    S.perm = (int *)(w + L.perm);
+    S.cnt = (int *)(w + L.cnt);
+    S.off = (int *)(w + L.off);
+    S.cursor = (int *)(w + L.cursor);
+    S.MP = (T *)(w + L.MP);
+    S.V = (T *)(w + L.V);
+    S.err = (int *)(w + L.err);
+    S.force = (double *)(w + L.force);
+    S.fallback = (unsigned int *)(w + L.fallback);
+    return S;
+}
+
+unsigned grid1d(int64_t n) { return (unsigned)((n + kWG - 1) / kWG); }
+
+template <typename T>
+SimDev<T> &sdev(tacchi_sim *s);
+template <>
+SimDev<float> &sdev<float>(tacchi_sim *s) { return s->sf; }
+template <>
+SimDev<double> &sdev<double>(tacchi_sim *s) { return s->sd; }
+
+template <typename T>
+tacchi_status zero_bytes(tacchi_sim *s, void *p, size_t bytes)
+{
+    // fill kernel (not hipMemsetAsync) so the sequence stays safe to capture
+    const int64_t n = (int64_t)(bytes / 4);
+    hipLaunchKernelGGL(k_fill<int>, dim3(grid1d(n)), dim3(kWG), 0, s->stream, (int *)p, n, 0);
+    TC_LAUNCHED();
+    return TACCHI_OK;
+}
+
+template <typename T>
+tacchi_status launch_bin(tacchi_sim *s)
+{
+    SimDev<T> &S = sdev<T>(s);
+    tacchi_status st = zero_bytes<T>(s, S.cnt, (size_t)S.nblk * 4);
+    if (st) return st;
+    if (s->d.B == 4)
+        hipLaunchKernelGGL((k_bin<T, 4>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S);
+    else
+        hipLaunchKernelGGL((k_bin<T, 8>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S);
+    TC_LAUNCHED();
+    return TACCHI_OK;
+}
+
+template <typename T, int B, bool FIX>
+void launch_p2g_model(tacchi_sim *s, T fix)
+{
+    SimDev<T> &S = sdev<T>(s);
+    if (s->cfg.mat.model == TACCHI_NEOHOOKEAN)
+        hipLaunchKernelGGL((k_p2g<T, B, FIX, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix);
+    else
+        hipLaunchKernelGGL((k_p2g<T, B, FIX, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix);
+}
+
+template <typename T, int B>
+void launch_p2g_b(tacchi_sim *s, bool fix_dt, T fix)
+{
+    if (fix_dt)
+        launch_p2g_model<T, B, true>(s, fix);
+    else
+        launch_p2g_model<T, B, false>(s, fix);
+}
+
+template <typename T>
+tacchi_status do_p2g(tacchi_sim *s, double dt)
+{
+    SimDev<T> &S = sdev<T>(s);
+    {
+        KernelTimer t(s, KC_SCAN);
+        hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s->stream, S.cnt, S.off, S.cursor, S.nblk, S.force);
+    }
+    TC_LAUNCHED();
+    {
+        KernelTimer t(s, KC_SCATTER);
+        hipLaunchKernelGGL(k_scatter, dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, (const int *)S.key, S.cursor,
+                           S.perm, S.N);
+    }
+    TC_LAUNCHED();
+    const bool fix_dt = dt != s->dtA;
+    const T fix = T((dt - s->dtA) * s->d.V0 * 4.0 / (s->d.dx * s->d.dx));
+    KernelTimer t(s, KC_P2G);
+    if (s->d.B == 4)
+        launch_p2g_b<T, 4>(s, fix_dt, fix);
+    else
+        launch_p2g_b<T, 8>(s, fix_dt, fix);
+    TC_LAUNCHED();
+    return TACCHI_OK;
+}
+
+template <typename T>
+tacchi_status do_grid(tacchi_sim *s, const double pose_end[7], double dt)
+{
+    SimDev<T> &S = sdev<T>(s);
+    IndenterDev<T> I = make_indenter<T>(s->cfg, s->pose, pose_end, dt);
+    KernelTimer t(s, KC_GRID);
+    if (s->d.B == 4)
+        hipLaunchKernelGGL((k_grid<T, 4>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, I, T(dt));
+    else
+        hipLaunchKernelGGL((k_grid<T, 8>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, I, T(dt));
+    TC_LAUNCHED();
+    return TACCHI_OK;
+}
+
+template <typename T>
+tacchi_status do_g2p(tacchi_sim *s, double dt)
+{
+    SimDev<T> &S = sdev<T>(s);
+    const T coef = T(dt * s->d.V0 * 4.0 / (s->d.dx * s->d.dx));
+    const bool neo = s->cfg.mat.model == TACCHI_NEOHOOKEAN;
+    KernelTimer t(s, KC_G2P);
+    if (s->d.B == 4) {
+        if (neo)
+            hipLaunchKernelGGL((k_g2p<T, 4, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
+        else
+            hipLaunchKernelGGL((k_g2p<T, 4, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
+    } else {
+        if (neo)
+            hipLaunchKernelGGL((k_g2p<T, 8, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
+        else
+            hipLaunchKernelGGL((k_g2p<T, 8, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
+    }
+    TC_LAUNCHED();
+    return TACCHI_OK;
+}
+
+tacchi_status set_device(tacchi_sim *s)
+{
+    int cur = -1;
+    TC_HIP(hipGetDevice(&cur));
+    if (cur != s->device) TC_HIP(hipSetDevice(s->device));
+    return TACCHI_OK;
+}
+
+tacchi_status check_dt(tacchi_sim *s, double dt)
+{
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(TACCHI_E_ARG, "dt must be finite and > 0");
+    const double cfl = dt * s->d.cp / s->d.dx;
+    if (cfl > 1.0) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "dt above the CFL limit: dt*c_p/dx = %.4g > 1", cfl);
+        return fail(TACCHI_E_UNSTABLE, buf);
+    }
+    return TACCHI_OK;
+}
+
+tacchi_status read_error_word(tacchi_sim *s)
+{
+    int h_err = 0;
+    TC_HIP(hipMemcpyAsync(&h_err, s->ws + s->L.err, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    TC_HIP(hipStreamSynchronize(s->stream));
+    if (h_err & ERR_OUT_OF_GRID) return fail(TACCHI_E_OUT_OF_GRID, "a particle's stencil left the grid");
+    if (h_err & ERR_INVERTED) return fail(TACCHI_E_UNSTABLE, "an element inverted (J <= 0) under neo-Hookean");
+    if (h_err & ERR_NONFINITE) return fail(TACCHI_E_UNSTABLE, "non-finite particle state");
+    return TACCHI_OK;
+}
+
+tacchi_status staging(tacchi_sim *s, size_t bytes, void **out)
+{
+    if (bytes > s->stage_bytes) {
+        if (s->stage) TC_HIP(hipHostFree(s->stage));
+        s->stage = nullptr;
+        s->stage_bytes = 0;
+        TC_HIP(hipHostMalloc(&s->stage, bytes, hipHostMallocDefault));
+        s->stage_bytes = bytes;
+    }
+    *out = s->stage;
+    return TACCHI_OK;
+}
+
+template <typename T>
+tacchi_status init_state(tacchi_sim *s)
+{
+    SimDev<T> &S = sdev<T>(s);
+    hipLaunchKernelGGL(k_init_particles<T>, dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S);
+    TC_LAUNCHED();
+    tacchi_status st = zero_bytes<T>(s, S.MP, (size_t)s->d.nodes * 4 * sizeof(T));
+    if (st) return st;
+    st = zero_bytes<T>(s, S.err, 64);
+    if (st) return st;
+    st = zero_bytes<T>(s, S.force, 64);
+    if (st) return st;
+    st = zero_bytes<T>(s, S.fallback, 64);
+    if (st) return st;
+    return launch_bin<T>(s);
+}
+
+template <typename T>
+tacchi_status read_particles_t(tacchi_sim *s, void *x, void *v, void *C, void *F, int on_device)
+{
+    SimDev<T> &S = sdev<T>(s);
+    const size_t N = (size_t)S.N;
+    void *dst[4] = {x, v, C, F};
+    const size_t cnt[4] = {3 * N, 3 * N, 9 * N, 9 * N};
+    T *tgt[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t offs[4] = {0, 0, 0, 0}, total = 0;
+    for (int k = 0; k < 4; ++k) {
+        offs[k] = total;
+        if (dst[k]) total += cnt[k] * sizeof(T);
+    }
+    void *stage = nullptr;
+    if (!on_device && total) {
+        tacchi_status st = staging(s, total, &stage);
+        if (st) return st;
+    }
+    for (int k = 0; k < 4; ++k)
+        if (dst[k]) tgt[k] = on_device ? (T *)dst[k] : (T *)((char *)stage + offs[k]);
+    const T dtA_coef = T(s->dtA * s->d.V0 * 4.0 / (s->d.dx * s->d.dx));
+    const double *o = s->cfg.grid.origin;
+    if (s->cfg.mat.model == TACCHI_NEOHOOKEAN)
+        hipLaunchKernelGGL((k_read_particles<T, 0>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]),
+                           T(o[1]), T(o[2]), T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
+    else
+        hipLaunchKernelGGL((k_read_particles<T, 1>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]),
+                           T(o[1]), T(o[2]), T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
+    TC_LAUNCHED();
+    TC_HIP(hipStreamSynchronize(s->stream));
+    if (!on_device)
+        for (int k = 0; k < 4; ++k)
+            if (dst[k]) std::memcpy(dst[k], (char *)stage + offs[k], cnt[k] * sizeof(T));
+    return read_error_word(s);
+}
+
+template <typename T>
+tacchi_status write_particles_t(tacchi_sim *s, const void *x, const void *v, const void *C, const void *F,
+                                int on_device)
+{
+    SimDev<T> &S = sdev<T>(s);
+    const size_t N = (size_t)S.N;
+    const void *src[4] = {x, v, C, F};
+    const size_t cnt[4] = {3 * N, 3 * N, 9 * N, 9 * N};
+    const T *in[4];
+    if (on_device) {
+        for (int k = 0; k < 4; ++k) in[k] = (const T *)src[k];
+    } else {
+        void *stage = nullptr;
+        tacchi_status st = staging(s, 24 * N * sizeof(T), &stage);
+        if (st) return st;
+        TC_HIP(hipStreamSynchronize(s->stream));  // staging may still feed an earlier write
+        size_t o = 0;
+        for (int k = 0; k < 4; ++k) {
+            std::memcpy((char *)stage + o, src[k], cnt[k] * sizeof(T));
+            in[k] = (const T *)((char *)stage + o);
+            o += cnt[k] * sizeof(T);
+        }
+    }
+    const double *o = s->cfg.grid.origin;
+    hipLaunchKernelGGL(k_write_particles<T>, dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]), T(o[1]),
+                       T(o[2]), T(1.0 / s->d.dx), in[0], in[1], in[2], in[3]);
+    TC_LAUNCHED();
+    tacchi_status st = zero_bytes<T>(s, S.err, 64);
+    if (st) return st;
+    s->dtA = 0.0;
+    st = launch_bin<T>(s);
+    if (st) return st;
+    if (!on_device) TC_HIP(hipStreamSynchronize(s->stream));
+    return TACCHI_OK;
+}
+
+template <typename T>
+tacchi_status heightmap_t(tacchi_sim *s, void *out, int on_device, bool relative)
+{
+    SimDev<T> &S = sdev<T>(s);
+    T *hm = (T *)(s->ws + s->L.hmap);
+    const int nxy = s->d.n[0] * s->d.n[1];
+    // relative maps hold only dx * u_z (the rest height is a constant that
+    // drops out of the image's normals), which keeps FP32 differences exact
+    const T zoff = relative ? T(0) : T(s->cfg.grid.origin[2]);
+    SimDev<T> Sr = S;
+    if (relative) Sr.xr[2] = T(0), Sr.hr[2] = T(0);
+    {
+        KernelTimer t(s, KC_HEIGHT);
+        hipLaunchKernelGGL(k_heightmap<T>, dim3(grid1d(nxy)), dim3(kWG), 0, s->stream, Sr, zoff, T(s->d.dx), hm);
+    }
+    TC_LAUNCHED();
+    if (out) {
+        TC_HIP(hipMemcpyAsync(out, hm, nxy * sizeof(T), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              s->stream));
+    }
+    return TACCHI_OK;
+}
+
+template <typename T>
+tacchi_status render_t(tacchi_sim *s, const tacchi_render_params *rp, float *rgb, int h, int w, int on_device)
+{
+    tacchi_status st = heightmap_t<T>(s, nullptr, 1, true);
+    if (st) return st;
+    RenderDev<T> R{};
+    const tacchi_config &c = s->cfg;
+    R.n0 = s->d.n[0];
+    R.n1 = s->d.n[1];
+    R.h = h;
+    R.w = w;
+    R.hx = T(s->d.h[0]);
+    R.hy = T(s->d.h[1]);
+    R.x0 = T(c.block.origin[0] + 0.5 * s->d.h[0]);
+    R.y0 = T(c.block.origin[1] + 0.5 * s->d.h[1]);
+    R.cx = T(c.block.origin[0] + 0.5 * c.block.size[0]);
+    R.cy = T(c.block.origin[1] + 0.5 * c.block.size[1]);
+    R.pitch = T(rp->pitch);
+    R.ka = T(rp->ka_ia);
+    R.kd = T(rp->kd);
+    R.ks = T(rp->ks);
+    R.alpha = T(rp->alpha);
+    const double el = rp->light_elev_deg * kPi / 180.0;
+    for (int ch = 0; ch < 3; ++ch) {
+        const double az = rp->light_azim_deg[ch] * kPi / 180.0;
+        R.L[ch][0] = T(std::cos(el) * std::cos(az));
+        R.L[ch][1] = T(std::cos(el) * std::sin(az));
+        R.L[ch][2] = T(-std::sin(el));
+    }
+    float *dst = rgb;
+    void *stage = nullptr;
+    const size_t bytes = (size_t)h * w * 3 * sizeof(float);
+    if (!on_device) {
+        st = staging(s, bytes, &stage);
+        if (st) return st;
+        dst = (float *)stage;
+    }
+    {
+        KernelTimer t(s, KC_RENDER);
+        hipLaunchKernelGGL(k_render<T>, dim3(grid1d((int64_t)h * w)), dim3(kWG), 0, s->stream,
+                           (const T *)(s->ws + s->L.hmap), R, dst);
+    }
+    TC_LAUNCHED();
+    TC_HIP(hipStreamSynchronize(s->stream));
+    if (!on_device) std::memcpy(rgb, stage, bytes);
+    return read_error_word(s);
+}
+
+template <typename T>
+tacchi_status read_grid_t(tacchi_sim *s, int which, void *M, void *vec, int on_device)
+{
+    SimDev<T> &S = sdev<T>(s);
+    const int64_t n = (int64_t)S.g0 * S.g1 * S.g2;
+    T *m_out = (T *)M, *v_out = (T *)vec;
+    void *stage = nullptr;
+    if (!on_device) {
+        tacchi_status st = staging(s, (size_t)n * 4 * sizeof(T), &stage);
+        if (st) return st;
+        m_out = M ? (T *)stage : nullptr;
+        v_out = (T *)stage + n;
+    }
+    if (s->d.B == 4)
+        hipLaunchKernelGGL((k_read_grid<T, 4>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, which, T(s->d.dx),
+                           m_out, v_out);
+    else
+        hipLaunchKernelGGL((k_read_grid<T, 8>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, which, T(s->d.dx),
+                           m_out, v_out);
+    TC_LAUNCHED();
+    TC_HIP(hipStreamSynchronize(s->stream));
+    if (!on_device) {
+        if (M && which == 0) std::memcpy(M, stage, n * sizeof(T));
+        std::memcpy(vec, (T *)stage + n, 3 * n * sizeof(T));
+    }
+    return TACCHI_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char *tacchi_last_error(void) { return g_last_error.c_str(); }
+
+size_t tacchi_workspace_bytes(const tacchi_config *cfg)
+{
+    Derived d;
+    if (derive(cfg, &d) != TACCHI_OK) return 0;
+    return make_layout(d).total;
+}
+
+tacchi_status tacchi_create(const tacchi_config *cfg, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                            tacchi_sim **out)
+{
+    if (!out) return fail(TACCHI_E_ARG, "out is NULL");
+    *out = nullptr;
+    Derived d;
+    tacchi_status st = derive(cfg, &d);
+    if (st) return st;
+    Layout L = make_layout(d);
+    if (!dev_ws) return fail(TACCHI_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)dev_ws & 255) != 0) return fail(TACCHI_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(TACCHI_E_WORKSPACE, "workspace too small");
+    tacchi_sim *s = new (std::nothrow) tacchi_sim();
+    if (!s) return fail(TACCHI_E_ARG, "out of host memory");
+    s->cfg = *cfg;
+    s->d = d;
+    s->L = L;
+    s->ws = (char *)dev_ws;
+    s->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(TACCHI_E_DEVICE, "hipGetDevice failed");
+    }
+    std::memcpy(s->pose, cfg->pose0.pos, 3 * sizeof(double));
+    std::memcpy(s->pose + 3, cfg->pose0.quat, 4 * sizeof(double));
+    s->sf = make_simdev<float>(s);
+    s->sd = make_simdev<double>(s);
+    st = cfg->precision == TACCHI_F64 ? init_state<double>(s) : init_state<float>(s);
+    if (st) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_p2g(tacchi_sim *s, double dt)
+{
+    if (!s) return fail(TACCHI_E_ARG, "sim is NULL");
+    if (s->phase != 0) return fail(TACCHI_E_STATE, "tacchi_p2g called out of order");
+    tacchi_status st = check_dt(s, dt);
+    if (st) return st;
+    st = set_device(s);
+    if (st) return st;
+    st = s->cfg.precision == TACCHI_F64 ? do_p2g<double>(s, dt) : do_p2g<float>(s, dt);
+    if (st) return st;
+    s->phase = 1;
+    s->dt_phase = dt;
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_grid_update(tacchi_sim *s, const tacchi_pose *pose_end, double dt)
+{
+    if (!s || !pose_end) return fail(TACCHI_E_ARG, "NULL argument");
+    if (s->phase != 1) return fail(TACCHI_E_STATE, "tacchi_grid_update called out of order");
+    if (dt != s->dt_phase) return fail(TACCHI_E_ARG, "dt differs from the one given to tacchi_p2g");
+    const double *q = pose_end->quat;
+    if (!(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3] > 0)) return fail(TACCHI_E_ARG, "zero quaternion");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    double pe[7];
+    std::memcpy(pe, pose_end->pos, 3 * sizeof(double));
+    std::memcpy(pe + 3, pose_end->quat, 4 * sizeof(double));
+    st = s->cfg.precision == TACCHI_F64 ? do_grid<double>(s, pe, dt) : do_grid<float>(s, pe, dt);
+    if (st) return st;
+    std::memcpy(s->pending, pe, sizeof pe);
+    s->phase = 2;
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_g2p(tacchi_sim *s, double dt)
+{
+    if (!s) return fail(TACCHI_E_ARG, "sim is NULL");
+    if (s->phase != 2) return fail(TACCHI_E_STATE, "tacchi_g2p called out of order");
+    if (dt != s->dt_phase) return fail(TACCHI_E_ARG, "dt differs from the one given to tacchi_p2g");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    st = s->cfg.precision == TACCHI_F64 ? do_g2p<double>(s, dt) : do_g2p<float>(s, dt);
+    if (st) return st;
+    std::memcpy(s->pose, s->pending, sizeof s->pose);
+    s->dtA = dt;
+    s->phase = 0;
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_step(tacchi_sim *s, const tacchi_pose *pose_end, double dt)
+{
+    tacchi_status st = tacchi_p2g(s, dt);
+    if (st) return st;
+    st = tacchi_grid_update(s, pose_end, dt);
+    if (st) return st;
+    return tacchi_g2p(s, dt);
+}
+
+tacchi_status tacchi_run(tacchi_sim *s, const tacchi_pose *poses, int32_t n, double dt)
+{
+    if (!s || (!poses && n > 0) || n < 0) return fail(TACCHI_E_ARG, "bad arguments to tacchi_run");
+    for (int32_t k = 0; k < n; ++k) {
+        tacchi_status st = tacchi_step(s, poses + k, dt);
+        if (st) return st;
+    }
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_read_grid(tacchi_sim *s, int32_t which, void *M, void *vec, int32_t on_device)
+{
+    if (!s || !vec) return fail(TACCHI_E_ARG, "NULL argument");
+    if (which != 0 && which != 1) return fail(TACCHI_E_ARG, "which must be 0 or 1");
+    if ((which == 0 && s->phase != 1) || (which == 1 && s->phase != 2))
+        return fail(TACCHI_E_STATE, "grid contents not available in this phase");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    return s->cfg.precision == TACCHI_F64 ? read_grid_t<double>(s, which, M, vec, on_device)
+                                          : read_grid_t<float>(s, which, M, vec, on_device);
+}
+
+tacchi_status tacchi_heightmap(tacchi_sim *s, void *out, int32_t on_device)
+{
+    if (!s || !out) return fail(TACCHI_E_ARG, "NULL argument");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    st = s->cfg.precision == TACCHI_F64 ? heightmap_t<double>(s, out, on_device, false)
+                                        : heightmap_t<float>(s, out, on_device, false);
+    if (st) return st;
+    return read_error_word(s);
+}
+
+tacchi_status tacchi_render(tacchi_sim *s, const tacchi_render_params *rp, float *rgb, int32_t h, int32_t w,
+                            int32_t on_device)
+{
+    if (!s || !rp || !rgb) return fail(TACCHI_E_ARG, "NULL argument");
+    if (h < 1 || w < 1 || !(rp->pitch > 0)) return fail(TACCHI_E_ARG, "image size and pitch must be positive");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    return s->cfg.precision == TACCHI_F64 ? render_t<double>(s, rp, rgb, h, w, on_device)
+                                          : render_t<float>(s, rp, rgb, h, w, on_device);
+}
+
+tacchi_status tacchi_read_particles(tacchi_sim *s, void *x, void *v, void *C, void *F, int32_t on_device)
+{
+    if (!s) return fail(TACCHI_E_ARG, "sim is NULL");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    return s->cfg.precision == TACCHI_F64 ? read_particles_t<double>(s, x, v, C, F, on_device)
+                                          : read_particles_t<float>(s, x, v, C, F, on_device);
+}
+
+tacchi_status tacchi_write_particles(tacchi_sim *s, const void *x, const void *v, const void *C, const void *F,
+                                     int32_t on_device)
+{
+    if (!s || !x || !v || !C || !F) return fail(TACCHI_E_ARG, "all four particle arrays are required");
+    if (s->phase != 0) return fail(TACCHI_E_STATE, "cannot write particles in the middle of a substep");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    return s->cfg.precision == TACCHI_F64 ? write_particles_t<double>(s, x, v, C, F, on_device)
+                                          : write_particles_t<float>(s, x, v, C, F, on_device);
+}
+
+tacchi_status tacchi_indenter_force(tacchi_sim *s, double f[3])
+{
+    if (!s || !f) return fail(TACCHI_E_ARG, "NULL argument");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    TC_HIP(hipMemcpyAsync(f, s->ws + s->L.force, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    return read_error_word(s);
+}
+
+tacchi_status tacchi_get_pose(const tacchi_sim *s, tacchi_pose *pose)
+{
+    if (!s || !pose) return fail(TACCHI_E_ARG, "NULL argument");
+    std::memcpy(pose->pos, s->pose, 3 * sizeof(double));
+    std::memcpy(pose->quat, s->pose + 3, 4 * sizeof(double));
+    return TACCHI_OK;
+}
+
+int64_t tacchi_num_particles(const tacchi_sim *s) { return s ? s->d.N : 0; }
+
+tacchi_status tacchi_sync(tacchi_sim *s)
+{
+    if (!s) return fail(TACCHI_E_ARG, "sim is NULL");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    return read_error_word(s);
+}
+
+tacchi_status tacchi_timing_enable(tacchi_sim *s, uint32_t class_mask)
+{
+    if (!s) return fail(TACCHI_E_ARG, "sim is NULL");
+    if (class_mask >> TACCHI_NUM_KERNEL_CLASSES) return fail(TACCHI_E_ARG, "unknown kernel class in mask");
+    s->timing_mask = class_mask;
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_timing_read(tacchi_sim *s, double *ms, int64_t *counts, int32_t reset)
+{
+    if (!s) return fail(TACCHI_E_ARG, "sim is NULL");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    TC_HIP(hipStreamSynchronize(s->stream));
+    for (auto &p : s->timed) {
+        float e = 0.0f;
+        TC_HIP(hipEventElapsedTime(&e, p.a, p.b));
+        s->timing_ms[p.cls] += e;
+        s->timing_n[p.cls] += 1;
+        s->event_pool.push_back(p.a);
+        s->event_pool.push_back(p.b);
+    }
+    s->timed.clear();
+    for (int k = 0; k < TACCHI_NUM_KERNEL_CLASSES; ++k) {
+        if (ms) ms[k] = s->timing_ms[k];
+        if (counts) counts[k] = s->timing_n[k];
+        if (reset) {
+            s->timing_ms[k] = 0.0;
+            s->timing_n[k] = 0;
+        }
+    }
+    return TACCHI_OK;
+}
+
+void tacchi_destroy(tacchi_sim *s)
+{
+    if (!s) return;
+    if (s->stage) (void)hipHostFree(s->stage);
+    for (auto &p : s->timed) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    delete s;
+}
+
+}  // extern "C"

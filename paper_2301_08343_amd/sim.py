@@ -1,0 +1,134 @@
+"""Sim: one elastomer contact simulated by libtacchi on the current GPU.
+
+PyTorch supplies the device memory (one workspace tensor, output tensors)
+and the HIP stream; all computation happens in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import native as N
+
+
+class Sim:
+    def __init__(self, cfg: dict, pose0, precision: str = "f64", tile: int = 0, device="cuda"):
+        self.cfg = cfg
+        self.precision = N.F64 if precision == "f64" else N.F32
+        self.dtype = torch.float64 if self.precision == N.F64 else torch.float32
+        self.device = torch.device(device)
+        self._c = N.make_config(cfg, pose0, self.precision, tile)
+        L = N.lib()
+        nbytes = L.tacchi_workspace_bytes(ctypes.byref(self._c))
+        if nbytes == 0:
+            raise N.TacchiError(N.E_ARG, L.tacchi_last_error().decode())
+        self.ws_bytes = nbytes
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        shift = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self._ws_ptr = raw.data_ptr() + shift
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        N.check(L.tacchi_create(ctypes.byref(self._c), ctypes.c_void_p(self._ws_ptr), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.N = int(L.tacchi_num_particles(h))
+        self.n = tuple(cfg["n"])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.lib().tacchi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ------------------------------------------------------------ stepping
+    def step(self, pose_end, dt: float):
+        N.check(N.lib().tacchi_step(self._h, ctypes.byref(N.make_pose(pose_end)), dt))
+
+    def run(self, poses, dt: float):
+        arr = N.make_poses(poses)
+        N.check(N.lib().tacchi_run(self._h, arr, len(poses), dt))
+
+    def p2g(self, dt: float):
+        N.check(N.lib().tacchi_p2g(self._h, dt))
+
+    def grid_update(self, pose_end, dt: float):
+        N.check(N.lib().tacchi_grid_update(self._h, ctypes.byref(N.make_pose(pose_end)), dt))
+
+    def g2p(self, dt: float):
+        N.check(N.lib().tacchi_g2p(self._h, dt))
+
+    def sync(self):
+        N.check(N.lib().tacchi_sync(self._h))
+
+    # ------------------------------------------------------------ outputs
+    def _empty(self, *shape, dtype=None):
+        return torch.empty(*shape, dtype=dtype or self.dtype, device=self.device)
+
+    def heightmap(self) -> torch.Tensor:
+        out = self._empty(self.n[1], self.n[0])
+        N.check(N.lib().tacchi_heightmap(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def render(self, rp: dict) -> torch.Tensor:
+        out = self._empty(rp["h"], rp["w"], 3, dtype=torch.float32)
+        r = N.make_render(rp)
+        N.check(N.lib().tacchi_render(self._h, ctypes.byref(r), ctypes.c_void_p(out.data_ptr()),
+                                      rp["h"], rp["w"], 1))
+        return out
+
+    def read_particles(self):
+        """(x[3][N], v[3][N], C[9][N], F[9][N]) device tensors, SI units."""
+        x, v = self._empty(3, self.N), self._empty(3, self.N)
+        C, F = self._empty(9, self.N), self._empty(9, self.N)
+        N.check(N.lib().tacchi_read_particles(self._h, *(ctypes.c_void_p(t.data_ptr()) for t in (x, v, C, F)), 1))
+        return x, v, C, F
+
+    def write_particles(self, x, v, C, F):
+        ts = [torch.as_tensor(a, dtype=self.dtype).to(self.device).contiguous() for a in (x, v, C, F)]
+        assert ts[0].shape == (3, self.N) and ts[1].shape == (3, self.N)
+        assert ts[2].shape == (9, self.N) and ts[3].shape == (9, self.N)
+        N.check(N.lib().tacchi_write_particles(self._h, *(ctypes.c_void_p(t.data_ptr()) for t in ts), 1))
+        self.stream.synchronize()
+
+    def read_grid(self, which: int):
+        g = self.cfg["gn"]
+        n = g[0] * g[1] * g[2]
+        M = self._empty(n)
+        vec = self._empty(3, n)
+        N.check(N.lib().tacchi_read_grid(self._h, which, ctypes.c_void_p(M.data_ptr()),
+                                         ctypes.c_void_p(vec.data_ptr()), 1))
+        return M, vec
+
+    def force(self) -> np.ndarray:
+        f = (ctypes.c_double * 3)()
+        N.check(N.lib().tacchi_indenter_force(self._h, f))
+        return np.array(list(f))
+
+    def timing_enable(self, classes=()):
+        mask = 0
+        for c in classes:
+            mask |= 1 << N.KERNEL_CLASSES.index(c)
+        N.check(N.lib().tacchi_timing_enable(self._h, mask))
+
+    def timing_read(self, reset=True) -> dict:
+        ms = (ctypes.c_double * N.NUM_KERNEL_CLASSES)()
+        cnt = (ctypes.c_int64 * N.NUM_KERNEL_CLASSES)()
+        N.check(N.lib().tacchi_timing_read(self._h, ms, cnt, 1 if reset else 0))
+        return {name: (ms[k], cnt[k]) for k, name in enumerate(N.KERNEL_CLASSES)}
+
+    def pose(self) -> np.ndarray:
+        p = N.Pose()
+        N.check(N.lib().tacchi_get_pose(self._h, ctypes.byref(p)))
+        return np.array(list(p.pos) + list(p.quat))
+
+
+def aos_to_soa(x, v, C, F):
+    """Oracle AoS arrays ([N][3], [N][3], [N][3][3], [N][3][3]) to the ABI's SoA."""
+    n = len(x)
+    return (np.ascontiguousarray(np.asarray(x).T), np.ascontiguousarray(np.asarray(v).T),
+            np.ascontiguousarray(np.asarray(C).reshape(n, 9).T), np.ascontiguousarray(np.asarray(F).reshape(n, 9).T))
