@@ -55,6 +55,7 @@ struct SimDev {
     T xr[3];               // rest position of lattice particle (0,0,0), grid units
     T hr[3];               // lattice spacing / dx
     T m;                   // particle mass [kg]
+    T m_floor;             // grid nodes lighter than this get V = 0 (see k_grid)
     T vcoef;               // V0 * 4 / dx^2 [m]
     T mu, lambda;          // Lame parameters [Pa]
     int floor_node, wall;
@@ -62,7 +63,7 @@ struct SimDev {
     T grav[3];             // gravity [cells/s^2]
     T *u, *v, *H, *A;      // SoA: u[3][N], v[3][N], H[9][N], A[9][N]
     int *key, *perm, *cnt, *off, *cursor;
-    T *MP;                 // [nodes][4]: mass, momentum (kg, kg cells/s), accumulated by P2G
+    T *tiles;              // [blocks][(B+2)^3][4]: per-block P2G tiles of mass, momentum (kg, kg cells/s)
     T *V;                  // [nodes][4]: velocity (cells/s), 4th lane unused
     int *err;
     double *force;         // [3] contact reaction on the indenter [N]

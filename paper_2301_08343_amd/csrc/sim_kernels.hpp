@@ -86,24 +86,58 @@ __global__ void __launch_bounds__(kWG) k_bin(SimDev<T> S)
 
 // ---------------------------------------------------------------- P2G
 
+// LDS accumulation slot of one tile channel. FP64 adds natively
+// (ds_add_f64). FP32 accumulates 64-bit fixed point with ds_add_u64: the
+// contributions are pre-scaled so that one particle mass is 2^40 units and one
+// momentum unit m/dt (a particle crossing a cell per substep) is 2^40 units,
+// converted to integers and summed exactly, so the sum does not depend on the
+// order of the atomics; gfx950 also executes ds_add_u64 about 25x faster than
+// ds_add_f32.
+template <typename T>
+struct TileAcc;
+
+template <>
+struct TileAcc<double> {
+    using Slot = double;
+    static constexpr bool kFixed = false;
+    __device__ static void add(Slot *s, double v) { atomicAdd(s, v); }
+    __device__ static double value(Slot s) { return s; }
+};
+
+template <>
+struct TileAcc<float> {
+    using Slot = unsigned long long;
+    static constexpr bool kFixed = true;
+    __device__ static void add(Slot *s, float v) { atomicAdd(s, (unsigned long long)(long long)v); }
+    __device__ static float value(Slot s) { return (float)(double)(long long)s; }
+};
+
+constexpr float kFixedOne = 1099511627776.0f;    // 2^40
+constexpr float kFixedLimit = 3.6028797e16f;     // 2^55: largest accepted scaled contribution
+
 // One workgroup per grid block: particles binned to the block scatter mass
-// and momentum (Eqs. 2-5) into a (B+2)^3 LDS tile with LDS atomics; the tile
-// is then added to the global grid with one atomic per nonzero node and
-// channel. FIXDT rebuilds the stress part of A when the substep's dt differs
-// from the dt A was formed with: A += (dt_A - dt) V0 (4/dx^2) tau.
+// and momentum (Eqs. 2-5) into a (B+2)^3 LDS tile; the whole tile is then
+// stored (plain stores, no global atomics) in the block's slot of the tile
+// buffer, where the grid update gathers it. FIXDT rebuilds the stress part of
+// A when the substep's dt differs from the dt A was formed with:
+// A += (dt_A - dt) V0 (4/dx^2) tau. mscale/pscale scale mass and momentum
+// into accumulator units (1 in FP64); munit/punit scale back.
 template <typename T, int B, bool FIXDT, int MODEL>
-__global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef)
+__global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, T pscale, T munit, T punit)
 {
+    using Acc = TileAcc<T>;
+    using Slot = typename Acc::Slot;
     constexpr int TB = B + 2, TN = TB * TB * TB;
-    __shared__ T tile[4 * TN];
+    __shared__ Slot tile[4 * TN];
     const int b = blockIdx.x;
     const int beg = S.off[b], end = S.off[b + 1];
     if (beg >= end) return;
-    for (int i = threadIdx.x; i < 4 * TN; i += kWG) tile[i] = T(0);
+    for (int i = threadIdx.x; i < 4 * TN; i += kWG) tile[i] = Slot(0);
     __syncthreads();
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     const int lo0 = bx * B, lo1 = by * B, lo2 = bz * B;
     const int64_t N = S.N;
+    const T m = S.m * mscale;
     for (int i = beg + threadIdx.x; i < end; i += kWG) {
         const int p = S.perm[i];
         T xr[3];
@@ -141,12 +175,23 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef)
 #pragma unroll
             for (int k = 0; k < 9; ++k) Am[k] -= fix_coef * tau[k];
         }
-        // momentum at node offset o: m v + A (o - f) = q + A o
+        // momentum at node offset o: m v + A (o - f) = q + A o, in accumulator units
         T q[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            q[r] = S.m * S.v[r * N + p] - (Am[r * 3 + 0] * f[0] + Am[r * 3 + 1] * f[1] + Am[r * 3 + 2] * f[2]);
-        const T m = S.m;
+            q[r] = pscale * (S.m * S.v[r * N + p] - (Am[r * 3 + 0] * f[0] + Am[r * 3 + 1] * f[1] + Am[r * 3 + 2] * f[2]));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Am[k] *= pscale;
+        if (Acc::kFixed) {
+            T big = T(0);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                big = fmax(big, fabs(q[r]) + T(2) * (fabs(Am[r * 3]) + fabs(Am[r * 3 + 1]) + fabs(Am[r * 3 + 2])));
+            if (!(big < T(kFixedLimit))) {
+                atomicOr(S.err, ERR_NONFINITE);
+                continue;
+            }
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -159,25 +204,48 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef)
                 for (int c = 0; c < 3; ++c) {
                     const T wt = wab * wz[c];
                     const int li = ((l2 + c) * TB + (l1 + bb)) * TB + (l0 + a);
-                    atomicAdd(&tile[li], wt * m);
-                    atomicAdd(&tile[TN + li], wt * (qa[0] + Am[2] * T(c)));
-                    atomicAdd(&tile[2 * TN + li], wt * (qa[1] + Am[5] * T(c)));
-                    atomicAdd(&tile[3 * TN + li], wt * (qa[2] + Am[8] * T(c)));
+                    Acc::add(&tile[li], wt * m);
+                    Acc::add(&tile[TN + li], wt * (qa[0] + Am[2] * T(c)));
+                    Acc::add(&tile[2 * TN + li], wt * (qa[1] + Am[5] * T(c)));
+                    Acc::add(&tile[3 * TN + li], wt * (qa[2] + Am[8] * T(c)));
                 }
             }
     }
     __syncthreads();
+    T *dst = S.tiles + (int64_t)b * TN * 4;
     for (int li = threadIdx.x; li < TN; li += kWG) {
-        const T mm = tile[li];
-        if (mm == T(0)) continue;
-        const int x = li % TB, yz = li / TB, y = yz % TB, z = yz / TB;
-        const int gx = lo0 + x, gy = lo1 + y, gz = lo2 + z;
-        if (gx >= S.g0 || gy >= S.g1 || gz >= S.g2) continue;
-        T *dst = S.MP + 4 * node_addr<B>(S.nb0, S.nb1, gx, gy, gz);
-        unsafeAtomicAdd(dst + 0, mm);
-        unsafeAtomicAdd(dst + 1, tile[TN + li]);
-        unsafeAtomicAdd(dst + 2, tile[2 * TN + li]);
-        unsafeAtomicAdd(dst + 3, tile[3 * TN + li]);
+        T *d = dst + 4 * li;
+        d[0] = Acc::value(tile[li]) * munit;
+        d[1] = Acc::value(tile[TN + li]) * punit;
+        d[2] = Acc::value(tile[2 * TN + li]) * punit;
+        d[3] = Acc::value(tile[3 * TN + li]) * punit;
+    }
+}
+
+// Mass and momentum of grid node (block (bx,by,bz), local (lx,ly,lz)): the sum,
+// in a fixed order, of the tiles of the up-to-8 blocks whose (B+2)^3 tile
+// covers it (the block itself and, where the node lies in the first two
+// layers, its lower neighbours). Blocks without particles wrote no tile.
+template <typename T, int B>
+__device__ __forceinline__ void gather_node(const SimDev<T> &S, int bx, int by, int bz, int lx, int ly, int lz,
+                                            T out[4])
+{
+    constexpr int TB = B + 2, TN = TB * TB * TB;
+    out[0] = out[1] = out[2] = out[3] = T(0);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+        if ((ox && lx > 1) || (oy && ly > 1) || (oz && lz > 1)) continue;
+        const int cx = bx - ox, cy = by - oy, cz = bz - oz;
+        if (cx < 0 || cy < 0 || cz < 0) continue;
+        const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
+        if (S.off[c + 1] <= S.off[c]) continue;
+        const int ti = ((lz + oz * B) * TB + (ly + oy * B)) * TB + (lx + ox * B);
+        const T *src = S.tiles + ((int64_t)c * TN + ti) * 4;
+        out[0] += src[0];
+        out[1] += src[1];
+        out[2] += src[2];
+        out[3] += src[3];
     }
 }
 
@@ -192,13 +260,17 @@ __device__ __forceinline__ T wave_sum(T x)
 }
 
 // One workgroup per grid block that can hold mass (the block or one of its
-// seven lower neighbours has particles). Per node: V = P/M + dt g (Eq. 6);
+// seven lower neighbours has particles). Per node with mass above S.m_floor
+// (0 in FP64; in FP32 2^-30 of a particle's mass, below which P/M is
+// dominated by fixed-point quantisation and the node's weight in any particle
+// is under FP32 resolution): V = P/M + dt g (Eq. 6);
 // inside the indenter V takes the rigid indenter velocity (sticky contact;
 // the reaction M (V_before - V_indenter)/dt is summed into the force);
-// floor nodes are held; wall nodes drop their outward component. The
-// accumulation buffer is cleared for the next P2G.
+// floor nodes are held; wall nodes drop their outward component. The inside test and the
+// rigid velocity are evaluated in FP64 in both precisions, so the discrete
+// contact decision does not depend on the simulation precision.
 template <typename T, int B>
-__global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<T> I, T dt)
+__global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
 {
     constexpr int B3 = B * B * B;
     const int b = blockIdx.x;
@@ -217,28 +289,29 @@ __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<T> I, T d
         const int lx = l % B, ly = (l / B) % B, lz = l / (B * B);
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
         const int64_t addr = (int64_t)b * B3 + l;
-        T *mp = S.MP + 4 * addr;
+        T mp[4];
+        gather_node<T, B>(S, bx, by, bz, lx, ly, lz, mp);
         const T m = mp[0];
         T V0 = T(0), V1 = T(0), V2 = T(0);
-        if (m > T(0) && gx < S.g0 && gy < S.g1 && gz < S.g2) {
+        if (m > S.m_floor && gx < S.g0 && gy < S.g1 && gz < S.g2) {
             const T im = T(1) / m;
             V0 = mp[1] * im + dt * S.grav[0];
             V1 = mp[2] * im + dt * S.grav[1];
             V2 = mp[3] * im + dt * S.grav[2];
             if (I.shape >= 0) {
                 // node relative to the indenter origin, metres, then indenter frame
-                const T r0 = (T(gx) - I.tip[0]) * I.dx, r1 = (T(gy) - I.tip[1]) * I.dx,
-                        r2 = (T(gz) - I.tip[2]) * I.dx;
-                const T px = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
-                const T py = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
-                const T pz = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
-                if (indenter_phi<T>(I, px, py, pz) <= T(0)) {
+                const double r0 = ((double)gx - I.tip[0]) * I.dx, r1 = ((double)gy - I.tip[1]) * I.dx,
+                             r2 = ((double)gz - I.tip[2]) * I.dx;
+                const double px = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
+                const double py = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
+                const double pz = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
+                if (indenter_phi<double>(I, px, py, pz) <= 0.0) {
                     // rigid velocity v_c + omega x r, converted to cells/s
-                    const T ir = T(1) / I.dx;
-                    const T w0 = I.vc[0] + (I.om[1] * r2 - I.om[2] * r1) * ir;
-                    const T w1 = I.vc[1] + (I.om[2] * r0 - I.om[0] * r2) * ir;
-                    const T w2 = I.vc[2] + (I.om[0] * r1 - I.om[1] * r0) * ir;
-                    const T s = m * I.dx * inv_dt;
+                    const double ir = 1.0 / I.dx;
+                    const T w0 = T(I.vc[0] + (I.om[1] * r2 - I.om[2] * r1) * ir);
+                    const T w1 = T(I.vc[1] + (I.om[2] * r0 - I.om[0] * r2) * ir);
+                    const T w2 = T(I.vc[2] + (I.om[0] * r1 - I.om[1] * r0) * ir);
+                    const T s = m * T(I.dx) * inv_dt;
                     fx += (double)(s * (V0 - w0));
                     fy += (double)(s * (V1 - w1));
                     fz += (double)(s * (V2 - w2));
@@ -252,7 +325,6 @@ __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<T> I, T d
         }
         T *vv = S.V + 4 * addr;
         vv[0] = V0; vv[1] = V1; vv[2] = V2; vv[3] = T(0);
-        mp[0] = T(0); mp[1] = T(0); mp[2] = T(0); mp[3] = T(0);
     }
     if (I.shape >= 0) {
         __shared__ double red[3][kWG / 64];
@@ -560,9 +632,23 @@ __global__ void __launch_bounds__(kWG) k_read_grid(SimDev<T> S, int which, T sca
     const int64_t t = q / S.g0;
     const int gy = (int)(t % S.g1), gz = (int)(t / S.g1);
     const int64_t a = node_addr<B>(S.nb0, S.nb1, gx, gy, gz);
-    const T *src = (which == 0 ? S.MP : S.V) + 4 * a;
+    T mp[4];
+    constexpr int LB0 = (B == 4) ? 2 : 3;
+    gather_node<T, B>(S, gx >> LB0, gy >> LB0, gz >> LB0, gx & (B - 1), gy & (B - 1), gz & (B - 1), mp);
+    const T *src = which == 0 ? mp : S.V + 4 * a;
     if (M && which == 0) M[q] = src[0];
-    for (int r = 0; r < 3; ++r) vec[r * n + q] = scale * src[1 - which + r];
+    // velocities exist only in blocks the last grid update visited (a block
+    // or one of its seven lower neighbours holds particles); elsewhere V = 0
+    bool live = which == 0;
+    constexpr int LB = (B == 4) ? 2 : 3;
+    const int bx = gx >> LB, by = gy >> LB, bz = gz >> LB;
+    for (int o = 0; o < 8 && !live; ++o) {
+        const int cx = bx - (o & 1), cy = by - ((o >> 1) & 1), cz = bz - (o >> 2);
+        if (cx < 0 || cy < 0 || cz < 0) continue;
+        const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
+        if (S.off[c + 1] > S.off[c]) live = true;
+    }
+    for (int r = 0; r < 3; ++r) vec[r * n + q] = live ? scale * src[1 - which + r] : T(0);
 }
 
 }  // namespace tacchi

@@ -56,7 +56,7 @@ struct Derived {
 };
 
 struct Layout {
-    size_t u, v, H, A, key, perm, cnt, off, cursor, MP, V, err, force, fallback, hmap, total;
+    size_t u, v, H, A, key, perm, cnt, off, cursor, tiles, V, err, force, fallback, hmap, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -80,7 +80,8 @@ Layout make_layout(const Derived &d)
     L.cnt = take((size_t)d.nblk * 4);
     L.off = take(((size_t)d.nblk + 1) * 4);
     L.cursor = take((size_t)d.nblk * 4);
-    L.MP = take((size_t)d.nodes * 4 * es);
+    const size_t tb = (size_t)d.B + 2;
+    L.tiles = take((size_t)d.nblk * tb * tb * tb * 4 * es);
     L.V = take((size_t)d.nodes * 4 * es);
     L.err = take(64);
     L.force = take(64);
@@ -323,6 +324,11 @@ SimDev<T> make_simdev(tacchi_sim *s)
         S.grav[a] = T(s->cfg.gravity[a] / d.dx);
     }
     S.m = T(d.m);
+    // FP32 grid nodes lighter than 2^-30 particle masses (1024 units of the
+    // fixed-point P2G accumulator) are treated as empty: their P/M is dominated
+    // by quantisation, and the weight they carry into any particle is below
+    // 27 * 2^-30, about FP32 resolution.
+    S.m_floor = sizeof(T) == 4 ? T(d.m * 9.313225746154785e-10) : T(0);
     S.vcoef = T(d.V0 * 4.0 / (d.dx * d.dx));
     S.mu = T(d.mu);
     S.lambda = T(d.lambda);
@@ -339,7 +345,7 @@ SimDev<T> make_simdev(tacchi_sim *s)
     S.cnt = (int *)(w + L.cnt);
     S.off = (int *)(w + L.off);
     S.cursor = (int *)(w + L.cursor);
-    S.MP = (T *)(w + L.MP);
+    S.tiles = (T *)(w + L.tiles);
     S.V = (T *)(w + L.V);
     S.err = (int *)(w + L.err);
     S.force = (double *)(w + L.force);
@@ -380,23 +386,40 @@ tacchi_status launch_bin(tacchi_sim *s)
     return TACCHI_OK;
 }
 
+// Accumulator units of P2G: FP32 tiles count one particle mass and one
+// momentum unit m/dt as 2^40 (fixed point, see TileAcc); FP64 accumulates in
+// SI/grid units directly.
+struct P2GScales {
+    double mscale, pscale, munit, punit;
+};
+
+P2GScales p2g_scales(const tacchi_sim *s, double dt)
+{
+    if (s->cfg.precision == TACCHI_F64) return {1.0, 1.0, 1.0, 1.0};
+    const double one = 1099511627776.0;  // 2^40
+    const double m = s->d.m;
+    return {one / m, one * dt / m, m / one, m / (one * dt)};
+}
+
 template <typename T, int B, bool FIX>
-void launch_p2g_model(tacchi_sim *s, T fix)
+void launch_p2g_model(tacchi_sim *s, T fix, const P2GScales &k)
 {
     SimDev<T> &S = sdev<T>(s);
     if (s->cfg.mat.model == TACCHI_NEOHOOKEAN)
-        hipLaunchKernelGGL((k_p2g<T, B, FIX, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix);
+        hipLaunchKernelGGL((k_p2g<T, B, FIX, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix, T(k.mscale),
+                           T(k.pscale), T(k.munit), T(k.punit));
     else
-        hipLaunchKernelGGL((k_p2g<T, B, FIX, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix);
+        hipLaunchKernelGGL((k_p2g<T, B, FIX, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix, T(k.mscale),
+                           T(k.pscale), T(k.munit), T(k.punit));
 }
 
 template <typename T, int B>
-void launch_p2g_b(tacchi_sim *s, bool fix_dt, T fix)
+void launch_p2g_b(tacchi_sim *s, bool fix_dt, T fix, const P2GScales &k)
 {
     if (fix_dt)
-        launch_p2g_model<T, B, true>(s, fix);
+        launch_p2g_model<T, B, true>(s, fix, k);
     else
-        launch_p2g_model<T, B, false>(s, fix);
+        launch_p2g_model<T, B, false>(s, fix, k);
 }
 
 template <typename T>
@@ -416,11 +439,12 @@ tacchi_status do_p2g(tacchi_sim *s, double dt)
     TC_LAUNCHED();
     const bool fix_dt = dt != s->dtA;
     const T fix = T((dt - s->dtA) * s->d.V0 * 4.0 / (s->d.dx * s->d.dx));
+    const P2GScales k = p2g_scales(s, dt);
     KernelTimer t(s, KC_P2G);
     if (s->d.B == 4)
-        launch_p2g_b<T, 4>(s, fix_dt, fix);
+        launch_p2g_b<T, 4>(s, fix_dt, fix, k);
     else
-        launch_p2g_b<T, 8>(s, fix_dt, fix);
+        launch_p2g_b<T, 8>(s, fix_dt, fix, k);
     TC_LAUNCHED();
     return TACCHI_OK;
 }
@@ -429,7 +453,7 @@ template <typename T>
 tacchi_status do_grid(tacchi_sim *s, const double pose_end[7], double dt)
 {
     SimDev<T> &S = sdev<T>(s);
-    IndenterDev<T> I = make_indenter<T>(s->cfg, s->pose, pose_end, dt);
+    IndenterDev<double> I = make_indenter<double>(s->cfg, s->pose, pose_end, dt);
     KernelTimer t(s, KC_GRID);
     if (s->d.B == 4)
         hipLaunchKernelGGL((k_grid<T, 4>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, I, T(dt));
@@ -511,7 +535,7 @@ tacchi_status init_state(tacchi_sim *s)
     SimDev<T> &S = sdev<T>(s);
     hipLaunchKernelGGL(k_init_particles<T>, dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S);
     TC_LAUNCHED();
-    tacchi_status st = zero_bytes<T>(s, S.MP, (size_t)s->d.nodes * 4 * sizeof(T));
+    tacchi_status st = zero_bytes<T>(s, S.V, (size_t)s->d.nodes * 4 * sizeof(T));
     if (st) return st;
     st = zero_bytes<T>(s, S.err, 64);
     if (st) return st;
