@@ -27,7 +27,9 @@
  *    error word that is reported by the next synchronising call
  *    (`tacchi_sync`, `tacchi_heightmap`, `tacchi_render`, `tacchi_read_*`,
  *    `tacchi_indenter_force`); the handle keeps working but its state is
- *    then undefined until rewritten with `tacchi_write_particles`.
+ *    then undefined until rewritten with `tacchi_write_particles`. A grid
+ *    block that collects more than 2.5x its rest particle count (a local
+ *    compression below J = 0.4) is reported as E_UNSTABLE.
  *  - Particle p of the lattice (i, j, k), i fastest, is p = i + n0*(j + n1*k);
  *    k = 0 is the bottom layer (bonded to the sensor), k = n2-1 the contact
  *    surface. Particle arrays are structure-of-arrays in the simulation
@@ -186,14 +188,15 @@ int64_t tacchi_num_particles(const tacchi_sim *sim);
 tacchi_status tacchi_sync(tacchi_sim *sim);
 
 /* Kernel timing with HIP events on the handle's stream. Kernel classes:
- * 0 scan of the block counts, 1 particle scatter, 2 P2G, 3 grid update,
- * 4 G2P, 5 depth map, 6 render. tacchi_timing_enable brackets every later
+ * 0 binning of all particles (after creation or a state write), 1 P2G,
+ * 2 grid update, 3 G2P (which also bins the particles for the next
+ * substep), 4 depth map, 5 render. tacchi_timing_enable brackets every later
  * launch of the classes set in `class_mask` (bit k = class k; 0 disables)
  * with a pair of events; tacchi_timing_read synchronises and returns, per
  * class, the summed elapsed milliseconds and the launch count since the last
  * reset (reset != 0 clears them afterwards). ms and counts hold
  * TACCHI_NUM_KERNEL_CLASSES entries. */
-#define TACCHI_NUM_KERNEL_CLASSES 7
+#define TACCHI_NUM_KERNEL_CLASSES 6
 tacchi_status tacchi_timing_enable(tacchi_sim *sim, uint32_t class_mask);
 tacchi_status tacchi_timing_read(tacchi_sim *sim, double *ms, int64_t *counts, int32_t reset);
 

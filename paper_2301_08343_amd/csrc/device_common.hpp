@@ -18,7 +18,7 @@ namespace tacchi {
 
 constexpr int kWG = 256;
 
-enum : int { ERR_NONFINITE = 1, ERR_INVERTED = 2, ERR_OUT_OF_GRID = 4 };
+enum : int { ERR_NONFINITE = 1, ERR_INVERTED = 2, ERR_OUT_OF_GRID = 4, ERR_CAPACITY = 8 };
 
 // Division by a runtime constant via a precomputed multiplier (round-up
 // method of Granlund and Montgomery, 1994): valid for n < 2^31.
@@ -44,14 +44,30 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
 }
 
 // Everything a kernel needs to know about one elastomer contact.
+//
+// Particle storage: the lattice is cut into tiles of B x B x B particles,
+// shifted so that at rest each tile holds exactly the particles whose grid
+// cell lies in one grid block; tiles are stored contiguously (B^3 slots each,
+// slots outside the lattice stay unused). A grid block's particles are then
+// one contiguous run of slots, which keeps the transfers' loads and stores
+// coalesced.
+//
+// Binning: each grid block owns `cap` entries of a bin list; G2P appends each
+// updated particle to the list of the block holding its new stencil base
+// (a counting sort whose offsets are fixed), so the next substep's P2G and
+// G2P find a block's particles without a global scan.
 template <typename T>
 struct SimDev {
-    int64_t N;
+    int64_t N;             // particles
+    int64_t Ns;            // particle slots
     int n0, n1, n2;        // particle lattice
     int g0, g1, g2;        // grid nodes per axis
     int nb0, nb1, nb2;     // grid blocks per axis
     int nblk;
-    FastDiv div_n0, div_n1;
+    int ts0, ts1, ts2;     // lattice index i lies in tile (i + ts) / B
+    int nt0, nt1, nt2;     // tiles per axis
+    FastDiv div_nt0, div_nt1, div_n0, div_n1;
+    int cap;               // bin-list entries per grid block
     T xr[3];               // rest position of lattice particle (0,0,0), grid units
     T hr[3];               // lattice spacing / dx
     T m;                   // particle mass [kg]
@@ -59,11 +75,12 @@ struct SimDev {
     T vcoef;               // V0 * 4 / dx^2 [m]
     T mu, lambda;          // Lame parameters [Pa]
     int floor_node, wall;
-    int64_t fixed_count;   // particles p < fixed_count belong to the bonded bottom layers
+    int n_fixed;           // lattice layers k < n_fixed are bonded to the sensor
     T grav[3];             // gravity [cells/s^2]
-    T *u, *v, *H, *A;      // SoA: u[3][N], v[3][N], H[9][N], A[9][N]
-    int *key, *perm, *cnt, *off, *cursor;
-    T *tiles;              // [blocks][(B+2)^3][4]: per-block P2G tiles of mass, momentum (kg, kg cells/s)
+    T *u, *v, *H, *A;      // SoA over slots: u[3][Ns], v[3][Ns], H[9][Ns], A[9][Ns]
+    int *cnt_cur, *cnt_next;    // [nblk] particles per block (this / next substep)
+    int *perm_cur, *perm_next;  // [nblk][cap] particle slots per block
+    T *tiles;              // [blocks][(B+3)^3][4]: per-block P2G tiles of mass, momentum (kg, kg cells/s)
     T *V;                  // [nodes][4]: velocity (cells/s), 4th lane unused
     int *err;
     double *force;         // [3] contact reaction on the indenter [N]
@@ -94,14 +111,52 @@ __device__ __forceinline__ bool finite3(T a, T b, T c)
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-// Rest position (grid units) of lattice particle p.
-template <typename T>
-__device__ __forceinline__ void rest_position(const SimDev<T> &S, uint32_t p, T xr[3])
+template <int B>
+struct Log2B {
+    static constexpr int v = (B == 4) ? 2 : 3;
+};
+
+// Lattice index (i, j, k) of a particle slot; false for unused slots.
+template <typename T, int B>
+__device__ __forceinline__ bool slot_lattice(const SimDev<T> &S, uint32_t slot, int &i, int &j, int &k)
 {
-    uint32_t q = fdiv(p, S.div_n0);
-    uint32_t i = p - q * (uint32_t)S.n0;
-    uint32_t k = fdiv(q, S.div_n1);
-    uint32_t j = q - k * (uint32_t)S.n1;
+    constexpr int LB = Log2B<B>::v;
+    const uint32_t blk = slot >> (3 * LB), loc = slot & (B * B * B - 1);
+    const uint32_t t1 = fdiv(blk, S.div_nt0);
+    const int tx = (int)(blk - t1 * (uint32_t)S.nt0);
+    const uint32_t tz = fdiv(t1, S.div_nt1);
+    const int ty = (int)(t1 - tz * (uint32_t)S.nt1);
+    i = tx * B + (int)(loc & (B - 1)) - S.ts0;
+    j = ty * B + (int)((loc >> LB) & (B - 1)) - S.ts1;
+    k = (int)tz * B + (int)(loc >> (2 * LB)) - S.ts2;
+    return (unsigned)i < (unsigned)S.n0 && (unsigned)j < (unsigned)S.n1 && (unsigned)k < (unsigned)S.n2;
+}
+
+// Slot of lattice particle (i, j, k).
+template <typename T, int B>
+__device__ __forceinline__ uint32_t lattice_slot(const SimDev<T> &S, int i, int j, int k)
+{
+    constexpr int LB = Log2B<B>::v;
+    const int a = i + S.ts0, b = j + S.ts1, c = k + S.ts2;
+    const uint32_t tile = ((uint32_t)(c >> LB) * S.nt1 + (uint32_t)(b >> LB)) * S.nt0 + (uint32_t)(a >> LB);
+    return (tile << (3 * LB)) + (uint32_t)((((c & (B - 1)) << LB) + (b & (B - 1))) << LB) + (uint32_t)(a & (B - 1));
+}
+
+// Lattice index of the API's particle order p = i + n0 (j + n1 k).
+template <typename T>
+__device__ __forceinline__ void api_lattice(const SimDev<T> &S, uint32_t p, int &i, int &j, int &k)
+{
+    const uint32_t q = fdiv(p, S.div_n0);
+    i = (int)(p - q * (uint32_t)S.n0);
+    const uint32_t kk = fdiv(q, S.div_n1);
+    j = (int)(q - kk * (uint32_t)S.n1);
+    k = (int)kk;
+}
+
+// Rest position (grid units) of lattice particle (i, j, k).
+template <typename T>
+__device__ __forceinline__ void rest_position(const SimDev<T> &S, int i, int j, int k, T xr[3])
+{
     xr[0] = S.xr[0] + T(i) * S.hr[0];
     xr[1] = S.xr[1] + T(j) * S.hr[1];
     xr[2] = S.xr[2] + T(k) * S.hr[2];
@@ -137,57 +192,69 @@ __device__ __forceinline__ void stencil_base(const T xr[3], const T uu[3], int b
 template <int B>
 __device__ __forceinline__ int64_t node_addr(int nb0, int nb1, int x, int y, int z)
 {
-    constexpr int LB = (B == 4) ? 2 : 3;
+    constexpr int LB = Log2B<B>::v;
     int bx = x >> LB, by = y >> LB, bz = z >> LB;
     int lx = x & (B - 1), ly = y & (B - 1), lz = z & (B - 1);
     int64_t blk = ((int64_t)bz * nb1 + by) * nb0 + bx;
     return blk * (B * B * B) + ((lz * B + ly) * B + lx);
 }
 
-// Block key of a particle: the grid block holding its stencil base node.
-// Out-of-grid or non-finite particles are flagged and clamped to a valid
-// block (the transfer kernels then skip them).
+// Block key of a particle: the grid block holding the grid cell the particle
+// lies in (floor(x/dx)). Binning by cell rather than by stencil base keeps
+// particles that sit exactly at a cell centre -- every particle of a rest
+// lattice with one particle per cell -- from flipping between blocks under
+// rounding-level motion; the transfer tiles carry one extra lower layer for
+// the stencil base (floor(x/dx - 1/2)) one below the cell. Out-of-grid or
+// non-finite particles are flagged and clamped to a valid block (the
+// transfer kernels then skip them).
 template <typename T, int B>
 __device__ __forceinline__ int block_key(const SimDev<T> &S, const T xr[3], const T uu[3])
 {
-    constexpr int LB = (B == 4) ? 2 : 3;
+    constexpr int LB = Log2B<B>::v;
     if (!finite3(uu[0], uu[1], uu[2])) {
         atomicOr(S.err, ERR_NONFINITE);
         return 0;
     }
-    int base[3];
-    T f[3];
-    stencil_base(xr, uu, base, f);
     const int gn[3] = {S.g0, S.g1, S.g2};
+    const int nb[3] = {S.nb0, S.nb1, S.nb2};
+    int blk[3];
     bool oog = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (base[a] < 0) { base[a] = 0; oog = true; }
-        if (base[a] > gn[a] - 3) { base[a] = gn[a] - 3; oog = true; }
+        const T s = xr[a] + uu[a];
+        const int base = (int)tfloor<T>(s - T(0.5));
+        if (base < 0 || base > gn[a] - 3) oog = true;
+        int cell = (int)tfloor<T>(s);
+        cell = cell < 0 ? 0 : (cell > gn[a] - 1 ? gn[a] - 1 : cell);
+        blk[a] = min(cell >> LB, nb[a] - 1);
     }
     if (oog) atomicOr(S.err, ERR_OUT_OF_GRID);
-    return ((base[2] >> LB) * S.nb1 + (base[1] >> LB)) * S.nb0 + (base[0] >> LB);
+    return (blk[2] * S.nb1 + blk[1]) * S.nb0 + blk[0];
 }
 
-// Wave-level run aggregation: lanes of one wave64 whose `key` equals their
-// left neighbour's form a run; the run's first lane performs one atomicAdd of
-// the run length on counter[key] and every lane gets its slot
-// (old value + rank in the run). Lanes with key < 0 take no slot. All 64
-// lanes must execute this together.
+// Wave-level aggregation of counter increments: the lanes of one wave64 that
+// carry the same key take one atomicAdd per distinct key (issued by the
+// lowest such lane) and consecutive slots in lane order. Keys are handled one
+// distinct value per iteration, so a wave whose particles straddle a block
+// boundary costs a couple of atomics instead of one per lane. Lanes with
+// key < 0 take no slot. All 64 lanes must execute this together.
 __device__ __forceinline__ int wave_run_slot(int *counter, int key)
 {
     const int lane = __lane_id();
-    const int prev = __shfl_up(key, 1);
-    const bool head = (lane == 0) || (prev != key);
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-    const int start = 63 - __clzll(heads & upto);
-    const unsigned long long above = heads & ~upto;
-    const int next = above ? (__ffsll((long long)above) - 1) : 64;
-    int base = 0;
-    if (head && key >= 0) base = atomicAdd(&counter[key], next - start);
-    base = __shfl(base, start);
-    return base + (lane - start);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long remaining = __ballot(key >= 0);
+    int slot = 0;
+    while (remaining) {
+        const int leader = __ffsll((long long)remaining) - 1;
+        const int k = __shfl(key, leader);
+        const unsigned long long same = __ballot(key == k) & remaining;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counter[k], __popcll(same));
+        base = __shfl(base, leader);
+        if ((same >> lane) & 1ull) slot = base + __popcll(same & below);
+        remaining &= ~same;
+    }
+    return slot;
 }
 
 // ---------------------------------------------------------------- constitutive models

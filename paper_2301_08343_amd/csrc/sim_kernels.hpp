@@ -1,87 +1,46 @@
 // MLS-MPM substep kernels for one elastomer contact (gfx950, wave64).
 //
-// Per substep (Sec. III-A): block sort of the particles (histogram kept by
-// the previous G2P -> scan -> scatter), P2G into an LDS tile per grid block
-// flushed with one global atomic per tile node (Eqs. 2-5), the grid update
-// fused with gravity, rigid-indenter contact, floor and walls (Eq. 6,
-// Eq. 10), and G2P fused with the constitutive update and advection
-// (Eqs. 7-11), which also bins each particle for the next substep.
+// Per substep (Sec. III-A): P2G into an LDS tile per grid block, stored per
+// block (Eqs. 2-5); the grid update, which gathers the tiles covering each
+// node and applies gravity, rigid-indenter contact, floor and walls (Eq. 6,
+// Eq. 10); and G2P fused with the constitutive update and advection
+// (Eqs. 7-11), which also bins each particle into its block's list for the
+// next substep (the per-substep counting sort).
 #pragma once
 #include "device_common.hpp"
 
 namespace tacchi {
 
-// ---------------------------------------------------------------- sort
+// ---------------------------------------------------------------- binning
 
-// Exclusive scan of the per-block particle counts into offsets and scatter
-// cursors; clears the counts for the next histogram and the force
-// accumulator of the coming grid update. One workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan_bins(int *cnt, int *off, int *cursor, int nblk,
-                                                    double *force)
+// Appends particle `slot` with block key `key` (< 0: none) to the bin lists,
+// one atomic per run of equal keys in the wave. All 64 lanes must call it.
+template <typename T>
+__device__ __forceinline__ void bin_append(const SimDev<T> &S, int *cnt, int *perm, int key, uint32_t slot)
 {
-    __shared__ int sh[1024];
-    constexpr int IT = 8;
-    const int tid = threadIdx.x;
-    if (tid < 3 && force) force[tid] = 0.0;
-    int carry = 0;
-    for (int base = 0; base < nblk; base += 1024 * IT) {
-        int vals[IT];
-        int s = 0;
-#pragma unroll
-        for (int j = 0; j < IT; ++j) {
-            const int idx = base + tid * IT + j;
-            vals[j] = idx < nblk ? cnt[idx] : 0;
-            s += vals[j];
-        }
-        sh[tid] = s;
-        __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
-            const int t = tid >= d ? sh[tid - d] : 0;
-            __syncthreads();
-            sh[tid] += t;
-            __syncthreads();
-        }
-        int run = sh[tid] - s + carry;
-#pragma unroll
-        for (int j = 0; j < IT; ++j) {
-            const int idx = base + tid * IT + j;
-            if (idx < nblk) {
-                off[idx] = run;
-                cursor[idx] = run;
-                cnt[idx] = 0;
-            }
-            run += vals[j];
-        }
-        carry += sh[1023];
-        __syncthreads();
+    const int pos = wave_run_slot(cnt, key);
+    if (key >= 0) {
+        if (pos < S.cap)
+            perm[(int64_t)key * S.cap + pos] = (int)slot;
+        else
+            atomicOr(S.err, ERR_CAPACITY);
     }
-    if (tid == 0) off[nblk] = carry;
 }
 
-// perm[cursor[key[p]]++] = p, one atomic per run of equal keys in a wave.
-__global__ void __launch_bounds__(kWG) k_scatter(const int *key, int *cursor, int *perm, int64_t N)
-{
-    const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    const int k = p < N ? key[p] : -1;
-    const int slot = wave_run_slot(cursor, k);
-    if (p < N) perm[slot] = (int)p;
-}
-
-// Block keys and histogram of the current positions (after init or a state
-// write).
+// Bins every particle by its current position (after init or a state write);
+// the counts must be zero.
 template <typename T, int B>
 __global__ void __launch_bounds__(kWG) k_bin(SimDev<T> S)
 {
-    const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    int k = -1;
-    if (p < S.N) {
+    const int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    int key = -1, i, j, k;
+    if (s < S.Ns && slot_lattice<T, B>(S, (uint32_t)s, i, j, k)) {
         T xr[3];
-        rest_position(S, (uint32_t)p, xr);
-        const T uu[3] = {S.u[p], S.u[S.N + p], S.u[2 * S.N + p]};
-        k = block_key<T, B>(S, xr, uu);
-        S.key[p] = k;
+        rest_position(S, i, j, k, xr);
+        const T uu[3] = {S.u[s], S.u[S.Ns + s], S.u[2 * S.Ns + s]};
+        key = block_key<T, B>(S, xr, uu);
     }
-    wave_run_slot(S.cnt, k);
+    bin_append(S, S.cnt_cur, S.perm_cur, key, (uint32_t)s);
 }
 
 // ---------------------------------------------------------------- P2G
@@ -116,7 +75,7 @@ constexpr float kFixedOne = 1099511627776.0f;    // 2^40
 constexpr float kFixedLimit = 3.6028797e16f;     // 2^55: largest accepted scaled contribution
 
 // One workgroup per grid block: particles binned to the block scatter mass
-// and momentum (Eqs. 2-5) into a (B+2)^3 LDS tile; the whole tile is then
+// and momentum (Eqs. 2-5) into a (B+3)^3 LDS tile; the whole tile is then
 // stored (plain stores, no global atomics) in the block's slot of the tile
 // buffer, where the grid update gathers it. FIXDT rebuilds the stress part of
 // A when the substep's dt differs from the dt A was formed with:
@@ -127,21 +86,31 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, 
 {
     using Acc = TileAcc<T>;
     using Slot = typename Acc::Slot;
-    constexpr int TB = B + 2, TN = TB * TB * TB;
+    constexpr int TB = B + 3, TN = TB * TB * TB;
     __shared__ Slot tile[4 * TN];
     const int b = blockIdx.x;
-    const int beg = S.off[b], end = S.off[b + 1];
-    if (beg >= end) return;
+    // the next substep's bin counts start from zero; the force of the coming
+    // grid update too
+    if (threadIdx.x == 0) S.cnt_next[b] = 0;
+    if (b == 0 && threadIdx.x < 3) S.force[threadIdx.x] = 0.0;
+    // a block that overflowed its list keeps only `cap` entries (flagged)
+    const int count = min(S.cnt_cur[b], S.cap);
+    if (count == 0) return;
+    const int *plist = S.perm_cur + (int64_t)b * S.cap;
     for (int i = threadIdx.x; i < 4 * TN; i += kWG) tile[i] = Slot(0);
     __syncthreads();
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
-    const int lo0 = bx * B, lo1 = by * B, lo2 = bz * B;
-    const int64_t N = S.N;
+    // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
+    // whose cell lies in the block, so their stencil base is lo-1 .. lo+B-1
+    const int lo0 = bx * B - 1, lo1 = by * B - 1, lo2 = bz * B - 1;
+    const int64_t N = S.Ns;
     const T m = S.m * mscale;
-    for (int i = beg + threadIdx.x; i < end; i += kWG) {
-        const int p = S.perm[i];
+    for (int i = threadIdx.x; i < count; i += kWG) {
+        const int p = plist[i];
+        int li0, li1, li2;
+        slot_lattice<T, B>(S, (uint32_t)p, li0, li1, li2);
         T xr[3];
-        rest_position(S, (uint32_t)p, xr);
+        rest_position(S, li0, li1, li2, xr);
         const T uu[3] = {S.u[p], S.u[N + p], S.u[2 * N + p]};
         if (!finite3(uu[0], uu[1], uu[2])) {
             atomicOr(S.err, ERR_NONFINITE);
@@ -151,8 +120,8 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, 
         T f[3];
         stencil_base(xr, uu, base, f);
         const int l0 = base[0] - lo0, l1 = base[1] - lo1, l2 = base[2] - lo2;
-        if ((unsigned)l0 >= (unsigned)B || (unsigned)l1 >= (unsigned)B || (unsigned)l2 >= (unsigned)B ||
-            base[0] > S.g0 - 3 || base[1] > S.g1 - 3 || base[2] > S.g2 - 3) {
+        if ((unsigned)l0 > (unsigned)B || (unsigned)l1 > (unsigned)B || (unsigned)l2 > (unsigned)B ||
+            base[0] < 0 || base[1] < 0 || base[2] < 0 || base[0] > S.g0 - 3 || base[1] > S.g1 - 3 || base[2] > S.g2 - 3) {
             atomicOr(S.err, ERR_OUT_OF_GRID);
             continue;
         }
@@ -223,30 +192,53 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, 
 }
 
 // Mass and momentum of grid node (block (bx,by,bz), local (lx,ly,lz)): the sum,
-// in a fixed order, of the tiles of the up-to-8 blocks whose (B+2)^3 tile
-// covers it (the block itself and, where the node lies in the first two
-// layers, its lower neighbours). Blocks without particles wrote no tile.
+// in a fixed order, of the tiles of the blocks whose (B+3)^3 tile covers it.
+// Block c's tile spans nodes lo_c - 1 .. lo_c + B + 1, so along each axis the
+// node is covered by its own block, by the lower neighbour when l <= 1 and by
+// the upper neighbour when l = B-1. Blocks without particles wrote no tile.
 template <typename T, int B>
 __device__ __forceinline__ void gather_node(const SimDev<T> &S, int bx, int by, int bz, int lx, int ly, int lz,
                                             T out[4])
 {
-    constexpr int TB = B + 2, TN = TB * TB * TB;
+    constexpr int TB = B + 3, TN = TB * TB * TB;
     out[0] = out[1] = out[2] = out[3] = T(0);
+    const int l[3] = {lx, ly, lz};
+    int lo[3], hi[3];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-        if ((ox && lx > 1) || (oy && ly > 1) || (oz && lz > 1)) continue;
-        const int cx = bx - ox, cy = by - oy, cz = bz - oz;
-        if (cx < 0 || cy < 0 || cz < 0) continue;
-        const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
-        if (S.off[c + 1] <= S.off[c]) continue;
-        const int ti = ((lz + oz * B) * TB + (ly + oy * B)) * TB + (lx + ox * B);
-        const T *src = S.tiles + ((int64_t)c * TN + ti) * 4;
-        out[0] += src[0];
-        out[1] += src[1];
-        out[2] += src[2];
-        out[3] += src[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = l[a] <= 1 ? -1 : 0;
+        hi[a] = l[a] == B - 1 ? 1 : 0;
     }
+    for (int oz = lo[2]; oz <= hi[2]; ++oz)
+        for (int oy = lo[1]; oy <= hi[1]; ++oy)
+            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                const int cx = bx + ox, cy = by + oy, cz = bz + oz;
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= S.nb0 || cy >= S.nb1 || cz >= S.nb2) continue;
+                const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
+                if (S.cnt_cur[c] == 0) continue;
+                // tile index of the node in block c's tile (origin lo_c - 1)
+                const int ti = ((lz - oz * B + 1) * TB + (ly - oy * B + 1)) * TB + (lx - ox * B + 1);
+                const T *src = S.tiles + ((int64_t)c * TN + ti) * 4;
+                out[0] += src[0];
+                out[1] += src[1];
+                out[2] += src[2];
+                out[3] += src[3];
+            }
+}
+
+// True when a G2P tile may read this block's velocities: one of the 27
+// blocks around it (itself included) holds particles.
+template <typename T>
+__device__ __forceinline__ bool block_live(const SimDev<T> &S, int bx, int by, int bz)
+{
+    for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int cx = bx + ox, cy = by + oy, cz = bz + oz;
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= S.nb0 || cy >= S.nb1 || cz >= S.nb2) continue;
+                if (S.cnt_cur[(cz * S.nb1 + cy) * S.nb0 + cx] > 0) return true;
+            }
+    return false;
 }
 
 // ---------------------------------------------------------------- grid update
@@ -259,8 +251,8 @@ __device__ __forceinline__ T wave_sum(T x)
     return x;
 }
 
-// One workgroup per grid block that can hold mass (the block or one of its
-// seven lower neighbours has particles). Per node with mass above S.m_floor
+// One workgroup per grid block that a G2P tile may read (the block or one of
+// its 26 neighbours has particles). Per node with mass above S.m_floor
 // (0 in FP64; in FP32 2^-30 of a particle's mass, below which P/M is
 // dominated by fixed-point quantisation and the node's weight in any particle
 // is under FP32 resolution): V = P/M + dt g (Eq. 6);
@@ -275,13 +267,7 @@ __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I
     constexpr int B3 = B * B * B;
     const int b = blockIdx.x;
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
-    bool live = false;
-    for (int o = 0; o < 8; ++o) {
-        const int cx = bx - (o & 1), cy = by - ((o >> 1) & 1), cz = bz - (o >> 2);
-        if (cx < 0 || cy < 0 || cz < 0) continue;
-        const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
-        if (S.off[c + 1] > S.off[c]) live = true;
-    }
+    const bool live = block_live(S, bx, by, bz);
     if (!live) return;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const T inv_dt = T(1) / dt;
@@ -342,26 +328,30 @@ __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I
 
 // ---------------------------------------------------------------- G2P
 
-// One workgroup per grid block: the block's (B+2)^3 velocity tile is staged
+// One workgroup per grid block: the block's (B+3)^3 velocity tile is staged
 // in LDS; each particle gathers v and C (Eqs. 7-8, with the grid velocities
 // in Eq. 8), updates F (Eq. 9), forms the stress and the affine momentum
 // A = m C - dt V0 (4/dx^2) tau for the next P2G, applies the bonded bottom
-// layers (Eq. 10), advects (Eq. 11) and bins itself for the next substep.
+// layers (Eq. 10), advects (Eq. 11) and appends itself to the bin list of
+// the block holding its new stencil base.
 template <typename T, int B, int MODEL>
 __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
 {
-    constexpr int TB = B + 2, TN = TB * TB * TB;
+    constexpr int TB = B + 3, TN = TB * TB * TB;
     __shared__ T tile[3 * TN];
     const int b = blockIdx.x;
-    const int beg = S.off[b], end = S.off[b + 1];
-    if (beg >= end) return;
+    const int count = min(S.cnt_cur[b], S.cap);
+    if (count == 0) return;
+    const int *plist = S.perm_cur + (int64_t)b * S.cap;
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
-    const int lo0 = bx * B, lo1 = by * B, lo2 = bz * B;
+    // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
+    // whose cell lies in the block, so their stencil base is lo-1 .. lo+B-1
+    const int lo0 = bx * B - 1, lo1 = by * B - 1, lo2 = bz * B - 1;
     for (int li = threadIdx.x; li < TN; li += kWG) {
         const int x = li % TB, yz = li / TB, y = yz % TB, z = yz / TB;
         const int gx = lo0 + x, gy = lo1 + y, gz = lo2 + z;
         T a0 = T(0), a1 = T(0), a2 = T(0);
-        if (gx < S.g0 && gy < S.g1 && gz < S.g2) {
+        if ((unsigned)gx < (unsigned)S.g0 && (unsigned)gy < (unsigned)S.g1 && (unsigned)gz < (unsigned)S.g2) {
             const T *src = S.V + 4 * node_addr<B>(S.nb0, S.nb1, gx, gy, gz);
             a0 = src[0]; a1 = src[1]; a2 = src[2];
         }
@@ -370,14 +360,17 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
         tile[2 * TN + li] = a2;
     }
     __syncthreads();
-    const int64_t N = S.N;
-    for (int i0 = beg; i0 < end; i0 += kWG) {
+    const int64_t N = S.Ns;
+    for (int i0 = 0; i0 < count; i0 += kWG) {
         const int i = i0 + threadIdx.x;
         int newkey = -1;
-        if (i < end) {
-            const int p = S.perm[i];
+        int p = 0;
+        if (i < count) {
+            p = plist[i];
+            int li0, li1, li2;
+            slot_lattice<T, B>(S, (uint32_t)p, li0, li1, li2);
             T xr[3];
-            rest_position(S, (uint32_t)p, xr);
+            rest_position(S, li0, li1, li2, xr);
             T uu[3] = {S.u[p], S.u[N + p], S.u[2 * N + p]};
             int base[3] = {0, 0, 0};
             T f[3];
@@ -386,11 +379,11 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
             const int l0 = base[0] - lo0, l1 = base[1] - lo1, l2 = base[2] - lo2;
             if (!fin) {
                 atomicOr(S.err, ERR_NONFINITE);
-                newkey = S.key[p];
-            } else if ((unsigned)l0 >= (unsigned)B || (unsigned)l1 >= (unsigned)B || (unsigned)l2 >= (unsigned)B ||
-                base[0] > S.g0 - 3 || base[1] > S.g1 - 3 || base[2] > S.g2 - 3) {
+                newkey = b;
+            } else if ((unsigned)l0 > (unsigned)B || (unsigned)l1 > (unsigned)B || (unsigned)l2 > (unsigned)B ||
+                       base[0] < 0 || base[1] < 0 || base[2] < 0 || base[0] > S.g0 - 3 || base[1] > S.g1 - 3 || base[2] > S.g2 - 3) {
                 atomicOr(S.err, ERR_OUT_OF_GRID);
-                newkey = S.key[p];
+                newkey = b;
             } else {
                 T wx[3], wy[3], wz[3];
                 bspline3(f[0], wx);
@@ -406,25 +399,27 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
                 T sz[3] = {T(0), T(0), T(0)};
                 T sr[3] = {T(0), T(0), T(0)};       // sum w (V - vr)
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int bb = 0; bb < 3; ++bb)
+                    for (int bb = 0; bb < 3; ++bb) {
+                        const T wbc = wy[bb] * wz[c];
+                        const int lrow = ((l2 + c) * TB + (l1 + bb)) * TB + l0;
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const T wt = wx[a] * wy[bb] * wz[c];
-                            const int li = ((l2 + c) * TB + (l1 + bb)) * TB + (l0 + a);
-                            const T Vn[3] = {tile[li], tile[TN + li], tile[2 * TN + li]};
+                        for (int a = 0; a < 3; ++a) {
+                            const T wt = wx[a] * wbc;
+                            const int li = lrow + a;
 #pragma unroll
                             for (int r = 0; r < 3; ++r) {
-                                const T wv = wt * Vn[r];
-                                const T wd = wt * (Vn[r] - vr[r]);
-                                s0[r] += wv;
+                                const T Vn = tile[r * TN + li];
+                                const T wd = wt * (Vn - vr[r]);
+                                s0[r] += wt * Vn;
                                 sr[r] += wd;
                                 sx[r] += wd * T(a);
                                 sy[r] += wd * T(bb);
                                 sz[r] += wd * T(c);
                             }
                         }
+                    }
                 // C = (4/dx^2) sum w V (X_i - x_p)^T, in 1/s with grid-unit offsets
                 T Cm[9];
 #pragma unroll
@@ -433,18 +428,29 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
                     Cm[r * 3 + 1] = T(4) * (sy[r] - sr[r] * f[1]);
                     Cm[r * 3 + 2] = T(4) * (sz[r] - sr[r] * f[2]);
                 }
-                // F <- (I + dt C) F, i.e. H <- H + dt (C + C H)
-                T Hm[9];
+                T vn[3] = {s0[0], s0[1], s0[2]};
+                if (li2 < S.n_fixed) vn[0] = vn[1] = vn[2] = T(0);
 #pragma unroll
-                for (int k = 0; k < 9; ++k) Hm[k] = S.H[k * N + p];
+                for (int r = 0; r < 3; ++r) {
+                    S.v[r * N + p] = vn[r];
+                    uu[r] += dt * vn[r];
+                    S.u[r * N + p] = uu[r];
+                }
+                // F <- (I + dt C) F, i.e. H <- H + dt (C + C H), one column at a time
                 T Hn[9];
 #pragma unroll
-                for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    const T h0 = S.H[(0 * 3 + c) * N + p], h1 = S.H[(1 * 3 + c) * N + p],
+                            h2 = S.H[(2 * 3 + c) * N + p];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        Hn[r * 3 + c] = Hm[r * 3 + c] +
-                                        dt * (Cm[r * 3 + c] + Cm[r * 3 + 0] * Hm[0 * 3 + c] +
-                                              Cm[r * 3 + 1] * Hm[1 * 3 + c] + Cm[r * 3 + 2] * Hm[2 * 3 + c]);
+                    for (int r = 0; r < 3; ++r) {
+                        const T hrc = r == 0 ? h0 : (r == 1 ? h1 : h2);
+                        Hn[r * 3 + c] = hrc + dt * (Cm[r * 3 + c] + Cm[r * 3 + 0] * h0 + Cm[r * 3 + 1] * h1 +
+                                                    Cm[r * 3 + 2] * h2);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 9; ++k) S.H[k * N + p] = Hn[k];
                 T tau[9];
                 if (!kirchhoff<T, MODEL>(S, Hn, tau)) {
                     atomicOr(S.err, MODEL == 0 ? ERR_INVERTED : ERR_NONFINITE);
@@ -452,38 +458,26 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
                     for (int k = 0; k < 9; ++k) tau[k] = T(0);
                 }
 #pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    S.H[k * N + p] = Hn[k];
-                    S.A[k * N + p] = S.m * Cm[k] - stress_coef * tau[k];
-                }
-                T vn[3] = {s0[0], s0[1], s0[2]};
-                if (p < S.fixed_count) vn[0] = vn[1] = vn[2] = T(0);
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    S.v[r * N + p] = vn[r];
-                    uu[r] += dt * vn[r];
-                    S.u[r * N + p] = uu[r];
-                }
+                for (int k = 0; k < 9; ++k) S.A[k * N + p] = S.m * Cm[k] - stress_coef * tau[k];
                 newkey = block_key<T, B>(S, xr, uu);
-                S.key[p] = newkey;
             }
         }
-        wave_run_slot(S.cnt, newkey);
+        bin_append(S, S.cnt_next, S.perm_next, newkey, (uint32_t)p);
     }
 }
 
 // ---------------------------------------------------------------- outputs
 
 // out[j][i] = world z of top-layer particle (i, j).
-template <typename T>
+template <typename T, int B>
 __global__ void __launch_bounds__(kWG) k_heightmap(SimDev<T> S, T origin_z, T dx, T *out)
 {
     const int idx = blockIdx.x * kWG + threadIdx.x;
-    const int nxy = S.n0 * S.n1;
-    if (idx >= nxy) return;
-    const int64_t p = (int64_t)(S.n2 - 1) * nxy + idx;
+    if (idx >= S.n0 * S.n1) return;
+    const int j = idx / S.n0, i = idx - j * S.n0;
+    const uint32_t s = lattice_slot<T, B>(S, i, j, S.n2 - 1);
     const T zr = S.xr[2] + T(S.n2 - 1) * S.hr[2];
-    out[idx] = origin_z + dx * (zr + S.u[2 * S.N + p]);
+    out[idx] = origin_z + dx * (zr + S.u[2 * S.Ns + s]);
 }
 
 template <typename T>
@@ -547,69 +541,76 @@ __global__ void __launch_bounds__(kWG) k_render(const T *Hm, RenderDev<T> R, flo
 
 // ---------------------------------------------------------------- state conversion
 
-template <typename T, int MODEL>
+// Particle state in the ABI's order and units (SoA over p = i + n0 (j + n1 k)).
+template <typename T, int B, int MODEL>
 __global__ void __launch_bounds__(kWG) k_read_particles(SimDev<T> S, T ox, T oy, T oz, T dx, T dtA_coef,
                                                         T *x, T *v, T *C, T *F)
 {
     const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (p >= S.N) return;
-    const int64_t N = S.N;
+    const int64_t N = S.N, Ns = S.Ns;
+    int i, j, k;
+    api_lattice(S, (uint32_t)p, i, j, k);
+    const int64_t s = lattice_slot<T, B>(S, i, j, k);
     T xr[3];
-    rest_position(S, (uint32_t)p, xr);
+    rest_position(S, i, j, k, xr);
     if (x) {
-        x[p] = ox + dx * (xr[0] + S.u[p]);
-        x[N + p] = oy + dx * (xr[1] + S.u[N + p]);
-        x[2 * N + p] = oz + dx * (xr[2] + S.u[2 * N + p]);
+        x[p] = ox + dx * (xr[0] + S.u[s]);
+        x[N + p] = oy + dx * (xr[1] + S.u[Ns + s]);
+        x[2 * N + p] = oz + dx * (xr[2] + S.u[2 * Ns + s]);
     }
     if (v)
-        for (int r = 0; r < 3; ++r) v[r * N + p] = dx * S.v[r * N + p];
+        for (int r = 0; r < 3; ++r) v[r * N + p] = dx * S.v[r * Ns + s];
     T Hm[9];
-    for (int k = 0; k < 9; ++k) Hm[k] = S.H[k * N + p];
+    for (int q = 0; q < 9; ++q) Hm[q] = S.H[q * Ns + s];
     if (F)
-        for (int k = 0; k < 9; ++k) F[k * N + p] = Hm[k] + ((k % 4 == 0) ? T(1) : T(0));
+        for (int q = 0; q < 9; ++q) F[q * N + p] = Hm[q] + ((q % 4 == 0) ? T(1) : T(0));
     if (C) {
         T tau[9];
         if (dtA_coef == T(0) || !kirchhoff<T, MODEL>(S, Hm, tau))
-            for (int k = 0; k < 9; ++k) tau[k] = T(0);
-        for (int k = 0; k < 9; ++k) C[k * N + p] = (S.A[k * N + p] + dtA_coef * tau[k]) / S.m;
+            for (int q = 0; q < 9; ++q) tau[q] = T(0);
+        for (int q = 0; q < 9; ++q) C[q * N + p] = (S.A[q * Ns + s] + dtA_coef * tau[q]) / S.m;
     }
 }
 
 // Writes a state given in SI/world terms; A is stored as m C (the stress part
 // is added by the next P2G, which sees dt_A = 0).
-template <typename T>
+template <typename T, int B>
 __global__ void __launch_bounds__(kWG) k_write_particles(SimDev<T> S, T ox, T oy, T oz, T inv_dx,
                                                          const T *x, const T *v, const T *C, const T *F)
 {
     const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (p >= S.N) return;
-    const int64_t N = S.N;
+    const int64_t N = S.N, Ns = S.Ns;
+    int i, j, k;
+    api_lattice(S, (uint32_t)p, i, j, k);
+    const int64_t s = lattice_slot<T, B>(S, i, j, k);
     T xr[3];
-    rest_position(S, (uint32_t)p, xr);
+    rest_position(S, i, j, k, xr);
     const T o[3] = {ox, oy, oz};
     for (int r = 0; r < 3; ++r) {
-        S.u[r * N + p] = (x[r * N + p] - o[r]) * inv_dx - xr[r];
-        S.v[r * N + p] = v[r * N + p] * inv_dx;
+        S.u[r * Ns + s] = (x[r * N + p] - o[r]) * inv_dx - xr[r];
+        S.v[r * Ns + s] = v[r * N + p] * inv_dx;
     }
-    for (int k = 0; k < 9; ++k) {
-        S.H[k * N + p] = F[k * N + p] - ((k % 4 == 0) ? T(1) : T(0));
-        S.A[k * N + p] = S.m * C[k * N + p];
+    for (int q = 0; q < 9; ++q) {
+        S.H[q * Ns + s] = F[q * N + p] - ((q % 4 == 0) ? T(1) : T(0));
+        S.A[q * Ns + s] = S.m * C[q * N + p];
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_init_particles(SimDev<T> S)
 {
-    const int64_t p = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (p >= S.N) return;
-    const int64_t N = S.N;
+    const int64_t s = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (s >= S.Ns) return;
+    const int64_t Ns = S.Ns;
     for (int r = 0; r < 3; ++r) {
-        S.u[r * N + p] = T(0);
-        S.v[r * N + p] = T(0);
+        S.u[r * Ns + s] = T(0);
+        S.v[r * Ns + s] = T(0);
     }
-    for (int k = 0; k < 9; ++k) {
-        S.H[k * N + p] = T(0);
-        S.A[k * N + p] = T(0);
+    for (int q = 0; q < 9; ++q) {
+        S.H[q * Ns + s] = T(0);
+        S.A[q * Ns + s] = T(0);
     }
 }
 
@@ -633,21 +634,14 @@ __global__ void __launch_bounds__(kWG) k_read_grid(SimDev<T> S, int which, T sca
     const int gy = (int)(t % S.g1), gz = (int)(t / S.g1);
     const int64_t a = node_addr<B>(S.nb0, S.nb1, gx, gy, gz);
     T mp[4];
-    constexpr int LB0 = (B == 4) ? 2 : 3;
+    constexpr int LB0 = Log2B<B>::v;
     gather_node<T, B>(S, gx >> LB0, gy >> LB0, gz >> LB0, gx & (B - 1), gy & (B - 1), gz & (B - 1), mp);
     const T *src = which == 0 ? mp : S.V + 4 * a;
     if (M && which == 0) M[q] = src[0];
     // velocities exist only in blocks the last grid update visited (a block
     // or one of its seven lower neighbours holds particles); elsewhere V = 0
-    bool live = which == 0;
-    constexpr int LB = (B == 4) ? 2 : 3;
-    const int bx = gx >> LB, by = gy >> LB, bz = gz >> LB;
-    for (int o = 0; o < 8 && !live; ++o) {
-        const int cx = bx - (o & 1), cy = by - ((o >> 1) & 1), cz = bz - (o >> 2);
-        if (cx < 0 || cy < 0 || cz < 0) continue;
-        const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
-        if (S.off[c + 1] > S.off[c]) live = true;
-    }
+    constexpr int LB = Log2B<B>::v;
+    const bool live = which == 0 || block_live(S, gx >> LB, gy >> LB, gz >> LB);
     for (int r = 0; r < 3; ++r) vec[r * n + q] = live ? scale * src[1 - which + r] : T(0);
 }
 

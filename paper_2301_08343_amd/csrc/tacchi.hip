@@ -53,10 +53,14 @@ struct Derived {
     double xr[3] = {0, 0, 0};
     int floor_node = 0;
     size_t es = 8;
+    int ts[3] = {0, 0, 0};   // lattice tile shift (see SimDev)
+    int nt[3] = {0, 0, 0};   // lattice tiles per axis
+    int64_t Ns = 0;          // particle slots
+    int cap = 0;             // bin-list entries per grid block
 };
 
 struct Layout {
-    size_t u, v, H, A, key, perm, cnt, off, cursor, tiles, V, err, force, fallback, hmap, total;
+    size_t u, v, H, A, cnt[2], perm[2], tiles, V, err, force, fallback, hmap, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -70,17 +74,16 @@ Layout make_layout(const Derived &d)
         o = align256(o + bytes);
         return r;
     };
-    const size_t N = (size_t)d.N, es = d.es;
-    L.u = take(3 * N * es);
-    L.v = take(3 * N * es);
-    L.H = take(9 * N * es);
-    L.A = take(9 * N * es);
-    L.key = take(N * 4);
-    L.perm = take(N * 4);
-    L.cnt = take((size_t)d.nblk * 4);
-    L.off = take(((size_t)d.nblk + 1) * 4);
-    L.cursor = take((size_t)d.nblk * 4);
-    const size_t tb = (size_t)d.B + 2;
+    const size_t Ns = (size_t)d.Ns, es = d.es;
+    L.u = take(3 * Ns * es);
+    L.v = take(3 * Ns * es);
+    L.H = take(9 * Ns * es);
+    L.A = take(9 * Ns * es);
+    for (int k = 0; k < 2; ++k) {
+        L.cnt[k] = take((size_t)d.nblk * 4);
+        L.perm[k] = take((size_t)d.nblk * d.cap * 4);
+    }
+    const size_t tb = (size_t)d.B + 3;
     L.tiles = take((size_t)d.nblk * tb * tb * tb * 4 * es);
     L.V = take((size_t)d.nodes * 4 * es);
     L.err = take(64);
@@ -167,6 +170,21 @@ tacchi_status derive(const tacchi_config *c, Derived *d)
     d->cp = std::sqrt((d->lambda + 2 * d->mu) / c->mat.rho);
     d->floor_node = (int)std::lround(z0);
     d->es = c->precision == TACCHI_F64 ? 8 : 4;
+    // particle tiles aligned with the grid blocks at rest
+    d->Ns = 1;
+    double ppc = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        const long cell0 = (long)std::floor(d->xr[a]);  // grid cell of lattice index 0 at rest
+        d->ts[a] = (int)(((cell0 % d->B) + d->B) % d->B);
+        d->nt[a] = (d->n[a] + d->ts[a] + d->B - 1) / d->B;
+        d->Ns *= (int64_t)d->nt[a] * d->B;
+        ppc *= dx / d->h[a];
+    }
+    if (d->Ns >= (int64_t)1 << 31) return fail(TACCHI_E_ARG, "too many particle slots (limit 2^31 - 1)");
+    // bin capacity: 2.5x the rest particle count of a block (a block's
+    // particles would need to be compressed to J < 0.4 to overflow it)
+    const double c0 = 2.5 * ppc * d->B * d->B * d->B;
+    d->cap = (int)(std::ceil(std::max(64.0, c0) / 64.0) * 64.0);
     (void)nodes;
     return TACCHI_OK;
 }
@@ -252,6 +270,7 @@ struct tacchi_sim {
     double pose[7];
     double pending[7];
     int phase = 0;        // 0: ready for P2G, 1: P2G done, 2: grid updated
+    int parity = 0;       // which bin buffers hold the current substep's lists
     double dtA = 0.0;     // dt the stored affine matrices were formed with
     double dt_phase = 0.0;
     SimDev<float> sf;
@@ -269,7 +288,7 @@ struct tacchi_sim {
 
 namespace {
 
-enum { KC_SCAN = 0, KC_SCATTER = 1, KC_P2G = 2, KC_GRID = 3, KC_G2P = 4, KC_HEIGHT = 5, KC_RENDER = 6 };
+enum { KC_BIN = 0, KC_P2G = 1, KC_GRID = 2, KC_G2P = 3, KC_HEIGHT = 4, KC_RENDER = 5 };
 
 hipEvent_t pool_event(tacchi_sim *s)
 {
@@ -312,12 +331,18 @@ SimDev<T> make_simdev(tacchi_sim *s)
     const Layout &L = s->L;
     SimDev<T> S{};
     S.N = d.N;
+    S.Ns = d.Ns;
     S.n0 = d.n[0]; S.n1 = d.n[1]; S.n2 = d.n[2];
     S.g0 = d.g[0]; S.g1 = d.g[1]; S.g2 = d.g[2];
     S.nb0 = d.nb[0]; S.nb1 = d.nb[1]; S.nb2 = d.nb[2];
     S.nblk = d.nblk;
+    S.ts0 = d.ts[0]; S.ts1 = d.ts[1]; S.ts2 = d.ts[2];
+    S.nt0 = d.nt[0]; S.nt1 = d.nt[1]; S.nt2 = d.nt[2];
+    S.div_nt0 = make_fastdiv((uint32_t)d.nt[0]);
+    S.div_nt1 = make_fastdiv((uint32_t)d.nt[1]);
     S.div_n0 = make_fastdiv((uint32_t)d.n[0]);
     S.div_n1 = make_fastdiv((uint32_t)d.n[1]);
+    S.cap = d.cap;
     for (int a = 0; a < 3; ++a) {
         S.xr[a] = T(d.xr[a]);
         S.hr[a] = T(d.h[a] / d.dx);
@@ -334,17 +359,16 @@ SimDev<T> make_simdev(tacchi_sim *s)
     S.lambda = T(d.lambda);
     S.floor_node = d.floor_node;
     S.wall = 3;
-    S.fixed_count = (int64_t)s->cfg.n_fixed_layers * d.n[0] * d.n[1];
+    S.n_fixed = s->cfg.n_fixed_layers;
     char *w = s->ws;
     S.u = (T *)(w + L.u);
     S.v = (T *)(w + L.v);
     S.H = (T *)(w + L.H);
     S.A = (T *)(w + L.A);
-    S.key = (int *)(w + L.key);
-    S.perm = (int *)(w + L.perm);
-    S.cnt = (int *)(w + L.cnt);
-    S.off = (int *)(w + L.off);
-    S.cursor = (int *)(w + L.cursor);
+    S.cnt_cur = (int *)(w + L.cnt[s->parity]);
+    S.cnt_next = (int *)(w + L.cnt[s->parity ^ 1]);
+    S.perm_cur = (int *)(w + L.perm[s->parity]);
+    S.perm_next = (int *)(w + L.perm[s->parity ^ 1]);
     S.tiles = (T *)(w + L.tiles);
     S.V = (T *)(w + L.V);
     S.err = (int *)(w + L.err);
@@ -376,12 +400,13 @@ template <typename T>
 tacchi_status launch_bin(tacchi_sim *s)
 {
     SimDev<T> &S = sdev<T>(s);
-    tacchi_status st = zero_bytes<T>(s, S.cnt, (size_t)S.nblk * 4);
+    tacchi_status st = zero_bytes<T>(s, S.cnt_cur, (size_t)S.nblk * 4);
     if (st) return st;
+    KernelTimer t(s, KC_BIN);
     if (s->d.B == 4)
-        hipLaunchKernelGGL((k_bin<T, 4>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S);
+        hipLaunchKernelGGL((k_bin<T, 4>), dim3(grid1d(S.Ns)), dim3(kWG), 0, s->stream, S);
     else
-        hipLaunchKernelGGL((k_bin<T, 8>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S);
+        hipLaunchKernelGGL((k_bin<T, 8>), dim3(grid1d(S.Ns)), dim3(kWG), 0, s->stream, S);
     TC_LAUNCHED();
     return TACCHI_OK;
 }
@@ -425,18 +450,7 @@ void launch_p2g_b(tacchi_sim *s, bool fix_dt, T fix, const P2GScales &k)
 template <typename T>
 tacchi_status do_p2g(tacchi_sim *s, double dt)
 {
-    SimDev<T> &S = sdev<T>(s);
-    {
-        KernelTimer t(s, KC_SCAN);
-        hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s->stream, S.cnt, S.off, S.cursor, S.nblk, S.force);
-    }
-    TC_LAUNCHED();
-    {
-        KernelTimer t(s, KC_SCATTER);
-        hipLaunchKernelGGL(k_scatter, dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, (const int *)S.key, S.cursor,
-                           S.perm, S.N);
-    }
-    TC_LAUNCHED();
+    (void)sdev<T>(s);
     const bool fix_dt = dt != s->dtA;
     const T fix = T((dt - s->dtA) * s->d.V0 * 4.0 / (s->d.dx * s->d.dx));
     const P2GScales k = p2g_scales(s, dt);
@@ -511,6 +525,9 @@ tacchi_status read_error_word(tacchi_sim *s)
     TC_HIP(hipMemcpyAsync(&h_err, s->ws + s->L.err, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     TC_HIP(hipStreamSynchronize(s->stream));
     if (h_err & ERR_OUT_OF_GRID) return fail(TACCHI_E_OUT_OF_GRID, "a particle's stencil left the grid");
+    if (h_err & ERR_CAPACITY)
+        return fail(TACCHI_E_UNSTABLE, "a grid block collected more particles than its bin capacity "
+                                       "(local compression below J = 0.4)");
     if (h_err & ERR_INVERTED) return fail(TACCHI_E_UNSTABLE, "an element inverted (J <= 0) under neo-Hookean");
     if (h_err & ERR_NONFINITE) return fail(TACCHI_E_UNSTABLE, "non-finite particle state");
     return TACCHI_OK;
@@ -533,7 +550,7 @@ template <typename T>
 tacchi_status init_state(tacchi_sim *s)
 {
     SimDev<T> &S = sdev<T>(s);
-    hipLaunchKernelGGL(k_init_particles<T>, dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S);
+    hipLaunchKernelGGL(k_init_particles<T>, dim3(grid1d(S.Ns)), dim3(kWG), 0, s->stream, S);
     TC_LAUNCHED();
     tacchi_status st = zero_bytes<T>(s, S.V, (size_t)s->d.nodes * 4 * sizeof(T));
     if (st) return st;
@@ -568,12 +585,20 @@ tacchi_status read_particles_t(tacchi_sim *s, void *x, void *v, void *C, void *F
         if (dst[k]) tgt[k] = on_device ? (T *)dst[k] : (T *)((char *)stage + offs[k]);
     const T dtA_coef = T(s->dtA * s->d.V0 * 4.0 / (s->d.dx * s->d.dx));
     const double *o = s->cfg.grid.origin;
-    if (s->cfg.mat.model == TACCHI_NEOHOOKEAN)
-        hipLaunchKernelGGL((k_read_particles<T, 0>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]),
-                           T(o[1]), T(o[2]), T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
+    const bool neo = s->cfg.mat.model == TACCHI_NEOHOOKEAN;
+    const dim3 g(grid1d(S.N)), blk(kWG);
+    if (s->d.B == 4 && neo)
+        hipLaunchKernelGGL((k_read_particles<T, 4, 0>), g, blk, 0, s->stream, S, T(o[0]), T(o[1]), T(o[2]),
+                           T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
+    else if (s->d.B == 4)
+        hipLaunchKernelGGL((k_read_particles<T, 4, 1>), g, blk, 0, s->stream, S, T(o[0]), T(o[1]), T(o[2]),
+                           T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
+    else if (neo)
+        hipLaunchKernelGGL((k_read_particles<T, 8, 0>), g, blk, 0, s->stream, S, T(o[0]), T(o[1]), T(o[2]),
+                           T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
     else
-        hipLaunchKernelGGL((k_read_particles<T, 1>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]),
-                           T(o[1]), T(o[2]), T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
+        hipLaunchKernelGGL((k_read_particles<T, 8, 1>), g, blk, 0, s->stream, S, T(o[0]), T(o[1]), T(o[2]),
+                           T(s->d.dx), dtA_coef, tgt[0], tgt[1], tgt[2], tgt[3]);
     TC_LAUNCHED();
     TC_HIP(hipStreamSynchronize(s->stream));
     if (!on_device)
@@ -606,8 +631,12 @@ tacchi_status write_particles_t(tacchi_sim *s, const void *x, const void *v, con
         }
     }
     const double *o = s->cfg.grid.origin;
-    hipLaunchKernelGGL(k_write_particles<T>, dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]), T(o[1]),
-                       T(o[2]), T(1.0 / s->d.dx), in[0], in[1], in[2], in[3]);
+    if (s->d.B == 4)
+        hipLaunchKernelGGL((k_write_particles<T, 4>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]),
+                           T(o[1]), T(o[2]), T(1.0 / s->d.dx), in[0], in[1], in[2], in[3]);
+    else
+        hipLaunchKernelGGL((k_write_particles<T, 8>), dim3(grid1d(S.N)), dim3(kWG), 0, s->stream, S, T(o[0]),
+                           T(o[1]), T(o[2]), T(1.0 / s->d.dx), in[0], in[1], in[2], in[3]);
     TC_LAUNCHED();
     tacchi_status st = zero_bytes<T>(s, S.err, 64);
     if (st) return st;
@@ -631,7 +660,12 @@ tacchi_status heightmap_t(tacchi_sim *s, void *out, int on_device, bool relative
     if (relative) Sr.xr[2] = T(0), Sr.hr[2] = T(0);
     {
         KernelTimer t(s, KC_HEIGHT);
-        hipLaunchKernelGGL(k_heightmap<T>, dim3(grid1d(nxy)), dim3(kWG), 0, s->stream, Sr, zoff, T(s->d.dx), hm);
+        if (s->d.B == 4)
+            hipLaunchKernelGGL((k_heightmap<T, 4>), dim3(grid1d(nxy)), dim3(kWG), 0, s->stream, Sr, zoff,
+                               T(s->d.dx), hm);
+        else
+            hipLaunchKernelGGL((k_heightmap<T, 8>), dim3(grid1d(nxy)), dim3(kWG), 0, s->stream, Sr, zoff,
+                               T(s->d.dx), hm);
     }
     TC_LAUNCHED();
     if (out) {
@@ -811,6 +845,10 @@ tacchi_status tacchi_g2p(tacchi_sim *s, double dt)
     if (st) return st;
     st = s->cfg.precision == TACCHI_F64 ? do_g2p<double>(s, dt) : do_g2p<float>(s, dt);
     if (st) return st;
+    // the bin lists written by G2P become the current ones
+    s->parity ^= 1;
+    s->sf = make_simdev<float>(s);
+    s->sd = make_simdev<double>(s);
     std::memcpy(s->pose, s->pending, sizeof s->pose);
     s->dtA = dt;
     s->phase = 0;

@@ -26,8 +26,8 @@ EXPORTS = (
     "tacchi_num_particles", "tacchi_sync", "tacchi_destroy", "tacchi_last_error",
     "tacchi_timing_enable", "tacchi_timing_read",
 )
-NUM_KERNEL_CLASSES = 7
-KERNEL_CLASSES = ("scan", "scatter", "p2g", "grid", "g2p", "heightmap", "render")
+NUM_KERNEL_CLASSES = 6
+KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
 
 
 class TacchiError(RuntimeError):

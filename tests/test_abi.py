@@ -44,8 +44,10 @@ def test_workspace_sizes():
     assert b64 > b32 > 0
     g = W.gelsight_contact(0)
     b, _ = _bytes(g["cfg"], g["poses"][0], precision=N.F32)
-    # 1.6M particles x (24 scalars + key + perm) + 2 grids of 4.2M nodes x 4 scalars
-    assert 1.6e6 * 104 + 2 * 4.19e6 * 16 <= b < 4e8
+    # 1.6M particles in 208 x 208 x 48 tiled slots x 24 scalars, two bin lists of
+    # 8192 blocks x 1280 entries, 8192 P2G tiles of 10^3 nodes and the
+    # 4.2M-node velocity grid, 4 scalars per node
+    assert 208 * 208 * 48 * 96 + 2 * 8192 * 1280 * 4 + 8192 * 1000 * 16 + 256 * 256 * 64 * 16 <= b < 6e8
 
 
 @pytest.mark.parametrize("mutate,msg", [
