@@ -180,6 +180,14 @@ tacchi_status tacchi_indenter_force(tacchi_sim *sim, double f[3]);
 /* Current indenter pose (host copy, no sync). */
 tacchi_status tacchi_get_pose(const tacchi_sim *sim, tacchi_pose *pose);
 
+/* Fixed-corotated model in FP32: the polar factor of F is computed in FP32
+ * by a scaled Newton iteration and recomputed in FP64 where the Frobenius
+ * condition number |F| |adj F| / |det F| exceeds 1e6, det F <= 0 or the FP32
+ * iteration does not converge. *count receives the number of such FP64
+ * recomputations since creation (always 0 in FP64 mode, where every polar
+ * factor is computed in FP64). Synchronises. */
+tacchi_status tacchi_polar_fallbacks(tacchi_sim *sim, uint64_t *count);
+
 /* Number of particles N of the handle. */
 int64_t tacchi_num_particles(const tacchi_sim *sim);
 
@@ -202,6 +210,60 @@ tacchi_status tacchi_timing_read(tacchi_sim *sim, double *ms, int64_t *counts, i
 
 /* Release the handle (host memory only; the workspace stays the caller's). */
 void tacchi_destroy(tacchi_sim *sim);
+
+/* ---------------------------------------------------------------------------
+ * Batched contacts: many independent elastomer contacts (each its own block,
+ * grid, material, indenter and dt) advanced together, one kernel launch per
+ * phase of a substep for all of them, with runs of substeps captured once as
+ * a HIP graph and replayed. Contacts must be FP32 (precision TACCHI_F32).
+ * Indenter trajectories are given up front: traj[i][k] is contact i's pose
+ * after k substeps (k = 0..substeps); past the last entry the final pose is
+ * held. A per-particle-count tuner picks each contact's grid block edge B in
+ * {4, 8} and workgroup size in {128, 256} by timing a few substeps of one
+ * contact per log2(N) class; choices are cached in the JSON file
+ * `tune_cache` (read if present, extended when `tune` != 0; NULL disables the
+ * file). Without a cached or tuned choice a contact uses B = 8, 256 threads.
+ * The batch owns one single-contact handle per contact for read-out.
+ * ------------------------------------------------------------------------- */
+typedef struct tacchi_batch tacchi_batch;   /* opaque, host memory owned by the library */
+
+/* Device workspace bytes for a batch (0 on invalid input, reason in
+ * tacchi_last_error()). */
+size_t tacchi_batch_workspace_bytes(const tacchi_config *cfgs, int32_t n, int32_t substeps);
+
+/* Validate and initialise all contacts (as tacchi_create), tabulate their
+ * indenters ([n][substeps+1] poses, dt[n] per contact, each within its CFL
+ * limit), tune, and set up the launch groups. `hip_stream` must be a
+ * non-default stream for graph replay (with NULL every substep is launched
+ * directly). Synchronises. Errors: E_ARG, E_WORKSPACE, E_UNSTABLE (CFL),
+ * E_DEVICE. */
+tacchi_status tacchi_batch_create(const tacchi_config *cfgs, int32_t n, const tacchi_pose *traj,
+                                  const double *dt, int32_t substeps, const char *tune_cache,
+                                  int32_t tune, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                                  tacchi_batch **out);
+
+/* Advance every contact by `substeps` substeps (asynchronous). */
+tacchi_status tacchi_batch_run(tacchi_batch *batch, int32_t substeps);
+
+/* Handle of contact i for read-out calls (tacchi_heightmap, tacchi_render,
+ * tacchi_read_particles, tacchi_indenter_force, tacchi_sync). It belongs to
+ * the batch: do not step, write or destroy it. NULL if i is out of range. */
+tacchi_sim *tacchi_batch_contact(tacchi_batch *batch, int32_t i);
+
+/* Per-contact tuning choice: grid block edge, workgroup size and the measured
+ * microseconds per substep of the tuning run (0 if the choice was a default);
+ * any pointer may be NULL, arrays hold n entries. */
+tacchi_status tacchi_batch_tuning(const tacchi_batch *batch, int32_t *tile, int32_t *wg,
+                                  double *us_per_substep);
+
+/* Substeps advanced so far. */
+int64_t tacchi_batch_substeps_done(const tacchi_batch *batch);
+
+/* Drain the stream and report the first contact's device error, if any. */
+tacchi_status tacchi_batch_sync(tacchi_batch *batch);
+
+/* Release the batch and its contact handles (host memory only). */
+void tacchi_batch_destroy(tacchi_batch *batch);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *tacchi_last_error(void);

@@ -81,14 +81,14 @@ constexpr float kFixedLimit = 3.6028797e16f;     // 2^55: largest accepted scale
 // A when the substep's dt differs from the dt A was formed with:
 // A += (dt_A - dt) V0 (4/dx^2) tau. mscale/pscale scale mass and momentum
 // into accumulator units (1 in FP64); munit/punit scale back.
-template <typename T, int B, bool FIXDT, int MODEL>
-__global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, T pscale, T munit, T punit)
+template <typename T, int B, bool FIXDT, int MODEL, int WG>
+__device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix_coef, T mscale, T pscale, T munit,
+                                          T punit)
 {
     using Acc = TileAcc<T>;
     using Slot = typename Acc::Slot;
     constexpr int TB = B + 3, TN = TB * TB * TB;
     __shared__ Slot tile[4 * TN];
-    const int b = blockIdx.x;
     // the next substep's bin counts start from zero; the force of the coming
     // grid update too
     if (threadIdx.x == 0) S.cnt_next[b] = 0;
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, 
     const int count = min(S.cnt_cur[b], S.cap);
     if (count == 0) return;
     const int *plist = S.perm_cur + (int64_t)b * S.cap;
-    for (int i = threadIdx.x; i < 4 * TN; i += kWG) tile[i] = Slot(0);
+    for (int i = threadIdx.x; i < 4 * TN; i += WG) tile[i] = Slot(0);
     __syncthreads();
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, 
     const int lo0 = bx * B - 1, lo1 = by * B - 1, lo2 = bz * B - 1;
     const int64_t N = S.Ns;
     const T m = S.m * mscale;
-    for (int i = threadIdx.x; i < count; i += kWG) {
+    for (int i = threadIdx.x; i < count; i += WG) {
         const int p = plist[i];
         int li0, li1, li2;
         slot_lattice<T, B>(S, (uint32_t)p, li0, li1, li2);
@@ -182,13 +182,19 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, 
     }
     __syncthreads();
     T *dst = S.tiles + (int64_t)b * TN * 4;
-    for (int li = threadIdx.x; li < TN; li += kWG) {
+    for (int li = threadIdx.x; li < TN; li += WG) {
         T *d = dst + 4 * li;
         d[0] = Acc::value(tile[li]) * munit;
         d[1] = Acc::value(tile[TN + li]) * punit;
         d[2] = Acc::value(tile[2 * TN + li]) * punit;
         d[3] = Acc::value(tile[3 * TN + li]) * punit;
     }
+}
+
+template <typename T, int B, bool FIXDT, int MODEL>
+__global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, T pscale, T munit, T punit)
+{
+    p2g_block<T, B, FIXDT, MODEL, kWG>(S, blockIdx.x, fix_coef, mscale, pscale, munit, punit);
 }
 
 // Mass and momentum of grid node (block (bx,by,bz), local (lx,ly,lz)): the sum,
@@ -261,17 +267,16 @@ __device__ __forceinline__ T wave_sum(T x)
 // floor nodes are held; wall nodes drop their outward component. The inside test and the
 // rigid velocity are evaluated in FP64 in both precisions, so the discrete
 // contact decision does not depend on the simulation precision.
-template <typename T, int B>
-__global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
+template <typename T, int B, int WG>
+__device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, const IndenterDev<double> &I, T dt)
 {
     constexpr int B3 = B * B * B;
-    const int b = blockIdx.x;
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     const bool live = block_live(S, bx, by, bz);
     if (!live) return;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const T inv_dt = T(1) / dt;
-    for (int l = threadIdx.x; l < B3; l += kWG) {
+    for (int l = threadIdx.x; l < B3; l += WG) {
         const int lx = l % B, ly = (l / B) % B, lz = l / (B * B);
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
         const int64_t addr = (int64_t)b * B3 + l;
@@ -313,17 +318,23 @@ __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I
         vv[0] = V0; vv[1] = V1; vv[2] = V2; vv[3] = T(0);
     }
     if (I.shape >= 0) {
-        __shared__ double red[3][kWG / 64];
+        __shared__ double red[3][WG / 64];
         fx = wave_sum(fx); fy = wave_sum(fy); fz = wave_sum(fz);
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) { red[0][w] = fx; red[1][w] = fy; red[2][w] = fz; }
         __syncthreads();
         if (threadIdx.x < 3) {
             double s = 0.0;
-            for (int k = 0; k < kWG / 64; ++k) s += red[threadIdx.x][k];
+            for (int k = 0; k < WG / 64; ++k) s += red[threadIdx.x][k];
             if (s != 0.0) atomicAdd(&S.force[threadIdx.x], s);
         }
     }
+}
+
+template <typename T, int B>
+__global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
+{
+    grid_block<T, B, kWG>(S, blockIdx.x, I, dt);
 }
 
 // ---------------------------------------------------------------- G2P
@@ -334,12 +345,11 @@ __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I
 // A = m C - dt V0 (4/dx^2) tau for the next P2G, applies the bonded bottom
 // layers (Eq. 10), advects (Eq. 11) and appends itself to the bin list of
 // the block holding its new stencil base.
-template <typename T, int B, int MODEL>
-__global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
+template <typename T, int B, int MODEL, int WG>
+__device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt, T stress_coef)
 {
     constexpr int TB = B + 3, TN = TB * TB * TB;
     __shared__ T tile[3 * TN];
-    const int b = blockIdx.x;
     const int count = min(S.cnt_cur[b], S.cap);
     if (count == 0) return;
     const int *plist = S.perm_cur + (int64_t)b * S.cap;
@@ -347,7 +357,7 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
     // whose cell lies in the block, so their stencil base is lo-1 .. lo+B-1
     const int lo0 = bx * B - 1, lo1 = by * B - 1, lo2 = bz * B - 1;
-    for (int li = threadIdx.x; li < TN; li += kWG) {
+    for (int li = threadIdx.x; li < TN; li += WG) {
         const int x = li % TB, yz = li / TB, y = yz % TB, z = yz / TB;
         const int gx = lo0 + x, gy = lo1 + y, gz = lo2 + z;
         T a0 = T(0), a1 = T(0), a2 = T(0);
@@ -361,7 +371,7 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
     }
     __syncthreads();
     const int64_t N = S.Ns;
-    for (int i0 = 0; i0 < count; i0 += kWG) {
+    for (int i0 = 0; i0 < count; i0 += WG) {
         const int i = i0 + threadIdx.x;
         int newkey = -1;
         int p = 0;
@@ -464,6 +474,12 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
         }
         bin_append(S, S.cnt_next, S.perm_next, newkey, (uint32_t)p);
     }
+}
+
+template <typename T, int B, int MODEL>
+__global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
+{
+    g2p_block<T, B, MODEL, kWG>(S, blockIdx.x, dt, stress_coef);
 }
 
 // ---------------------------------------------------------------- outputs

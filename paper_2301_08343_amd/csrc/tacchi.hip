@@ -937,6 +937,18 @@ tacchi_status tacchi_indenter_force(tacchi_sim *s, double f[3])
     return read_error_word(s);
 }
 
+tacchi_status tacchi_polar_fallbacks(tacchi_sim *s, uint64_t *count)
+{
+    if (!s || !count) return fail(TACCHI_E_ARG, "NULL argument");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    unsigned int c = 0;
+    TC_HIP(hipMemcpyAsync(&c, s->ws + s->L.fallback, sizeof c, hipMemcpyDeviceToHost, s->stream));
+    TC_HIP(hipStreamSynchronize(s->stream));
+    *count = c;
+    return TACCHI_OK;
+}
+
 tacchi_status tacchi_get_pose(const tacchi_sim *s, tacchi_pose *pose)
 {
     if (!s || !pose) return fail(TACCHI_E_ARG, "NULL argument");
@@ -1002,3 +1014,5 @@ void tacchi_destroy(tacchi_sim *s)
 }
 
 }  // extern "C"
+
+#include "batch_host.hpp"

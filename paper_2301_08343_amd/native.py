@@ -24,7 +24,9 @@ EXPORTS = (
     "tacchi_grid_update", "tacchi_g2p", "tacchi_read_grid", "tacchi_heightmap", "tacchi_render",
     "tacchi_read_particles", "tacchi_write_particles", "tacchi_indenter_force", "tacchi_get_pose",
     "tacchi_num_particles", "tacchi_sync", "tacchi_destroy", "tacchi_last_error",
-    "tacchi_timing_enable", "tacchi_timing_read",
+    "tacchi_timing_enable", "tacchi_timing_read", "tacchi_polar_fallbacks",
+    "tacchi_batch_workspace_bytes", "tacchi_batch_create", "tacchi_batch_run", "tacchi_batch_contact",
+    "tacchi_batch_tuning", "tacchi_batch_substeps_done", "tacchi_batch_sync", "tacchi_batch_destroy",
 )
 NUM_KERNEL_CLASSES = 6
 KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
@@ -121,6 +123,27 @@ def lib():
         L.tacchi_timing_read.restype = ctypes.c_int32
         L.tacchi_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int32]
+        L.tacchi_polar_fallbacks.restype = ctypes.c_int32
+        L.tacchi_polar_fallbacks.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.tacchi_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.tacchi_batch_workspace_bytes.argtypes = [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int32]
+        L.tacchi_batch_create.restype = ctypes.c_int32
+        L.tacchi_batch_create.argtypes = [ctypes.POINTER(Config), ctypes.c_int32, ctypes.POINTER(Pose),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_char_p,
+                                          ctypes.c_int32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+        L.tacchi_batch_run.restype = ctypes.c_int32
+        L.tacchi_batch_run.argtypes = [_vp, ctypes.c_int32]
+        L.tacchi_batch_contact.restype = _vp
+        L.tacchi_batch_contact.argtypes = [_vp, ctypes.c_int32]
+        L.tacchi_batch_tuning.restype = ctypes.c_int32
+        L.tacchi_batch_tuning.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_double)]
+        L.tacchi_batch_substeps_done.restype = ctypes.c_int64
+        L.tacchi_batch_substeps_done.argtypes = [_vp]
+        L.tacchi_batch_sync.restype = ctypes.c_int32
+        L.tacchi_batch_sync.argtypes = [_vp]
+        L.tacchi_batch_destroy.restype = None
+        L.tacchi_batch_destroy.argtypes = [_vp]
         L.tacchi_last_error.restype = ctypes.c_char_p
         L.tacchi_last_error.argtypes = []
         _lib = L

@@ -37,9 +37,25 @@ class Sim:
         self.N = int(L.tacchi_num_particles(h))
         self.n = tuple(cfg["n"])
 
+    @classmethod
+    def borrowed(cls, handle, cfg: dict, precision: int, device, stream):
+        """View of a handle owned elsewhere (a batch contact): read-out only."""
+        self = cls.__new__(cls)
+        self.cfg = cfg
+        self.precision = precision
+        self.dtype = torch.float64 if precision == N.F64 else torch.float32
+        self.device = torch.device(device)
+        self.stream = stream
+        self._h = ctypes.c_void_p(handle)
+        self._owned = False
+        self.N = int(N.lib().tacchi_num_particles(self._h))
+        self.n = tuple(cfg["n"])
+        return self
+
     def close(self):
         if getattr(self, "_h", None):
-            N.lib().tacchi_destroy(self._h)
+            if getattr(self, "_owned", True):
+                N.lib().tacchi_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -120,6 +136,11 @@ class Sim:
         cnt = (ctypes.c_int64 * N.NUM_KERNEL_CLASSES)()
         N.check(N.lib().tacchi_timing_read(self._h, ms, cnt, 1 if reset else 0))
         return {name: (ms[k], cnt[k]) for k, name in enumerate(N.KERNEL_CLASSES)}
+
+    def polar_fallbacks(self) -> int:
+        c = ctypes.c_uint64()
+        N.check(N.lib().tacchi_polar_fallbacks(self._h, ctypes.byref(c)))
+        return int(c.value)
 
     def pose(self) -> np.ndarray:
         p = N.Pose()

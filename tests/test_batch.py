@@ -1,0 +1,125 @@
+"""Batched contacts: each contact of a batch advanced by the batched, graph-
+replayed kernels matches the same contact run alone, small contacts match the
+FP64 oracle, and the tuner's choices round-trip through its cache file."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2301_08343_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08343_amd.batch import Batch
+    from paper_2301_08343_amd.sim import Sim
+    return Batch, Sim
+
+
+def to_np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def tiny_contact(seed, steps, shape=W.SPHERE):
+    """A 16 x 16 x 6 corotated block at 0.25 mm pressed by a sphere."""
+    rng = W.SplitMix64(0x71 + seed)
+    h = 0.25e-3
+    n = (16, 16, 6)
+    pad = 5
+    cfg = W._contact(block_origin=(pad * h, pad * h, 3 * h), block_size=(n[0] * h, n[1] * h, n[2] * h), n=n,
+                     grid_origin=(0, 0, 0), dx=h, gn=(n[0] + 2 * pad, n[1] + 2 * pad, n[2] + 10),
+                     E=rng.uniform(0.1e6, 0.3e6), nu=rng.uniform(0.40, 0.48), rho=1000.0, model=W.COROTATED,
+                     shape=shape, sp=[1.5e-3], seed=seed)
+    cx, cy = W.block_center_xy(cfg)
+    depth = 0.4e-3
+    tilt = W.quat_axis_angle((1.0, 0.3, 0.0), math.radians(4.0))
+    poses = W.press_trajectory((cx + rng.uniform(-0.5e-3, 0.5e-3), cy, W.top_z(cfg)), tilt, depth, steps)
+    lam = cfg["E"] * cfg["nu"] / ((1 + cfg["nu"]) * (1 - 2 * cfg["nu"]))
+    mu = cfg["E"] / (2 * (1 + cfg["nu"]))
+    dt = 0.45 * h / math.sqrt((lam + 2 * mu) / cfg["rho"])
+    return dict(cfg=cfg, poses=poses, dt=dt)
+
+
+def test_batch_contacts_match_their_solo_runs(gpu):
+    Batch, Sim = gpu
+    S = 120
+    contacts = [W.batch_contact(seed, steps=S) for seed in range(4)]
+    batch = Batch(contacts, S)
+    batch.run(S)  # two graph replays of 50 substeps + 20 direct
+    assert batch.substeps_done() == S
+    batch.sync()
+    tuning = batch.tuning()
+    for i, c in enumerate(contacts):
+        solo = Sim(c["cfg"], c["poses"][0], precision="f32", tile=tuning[i][0])
+        solo.run(c["poses"][1:S + 1], c["dt"])
+        xs = to_np(solo.read_particles()[0])
+        xb = to_np(batch.contact(i).read_particles()[0])
+        hs = to_np(solo.heightmap())
+        hb = to_np(batch.contact(i).heightmap())
+        diff = np.abs(xs - xb).max()
+        print(f"contact {i}: N = {solo.N}, tile {tuning[i][0]}, wg {tuning[i][1]}, max |dx| = {diff:.3e} m")
+        assert diff <= 2e-9
+        assert np.abs(hs - hb).max() <= 2e-9
+        assert np.abs(hb - W.top_z(c["cfg"])).max() > 1e-6  # the indenter deformed the surface
+
+
+def test_batch_graph_and_direct_launches_agree(gpu):
+    Batch, _ = gpu
+    S = 104
+    contacts = [W.batch_contact(seed, steps=S) for seed in (5, 6)]
+    a = Batch(contacts, S, use_graph=True)
+    b = Batch(contacts, S, use_graph=False)
+    a.run(50)
+    a.run(54)
+    b.run(S)
+    a.sync()
+    b.sync()
+    for i in range(2):
+        xa = to_np(a.contact(i).read_particles()[0])
+        xb = to_np(b.contact(i).read_particles()[0])
+        assert np.array_equal(xa, xb)
+
+
+def test_small_batch_matches_oracle(oracle_lib, gpu):
+    Batch, _ = gpu
+    S = 150
+    contacts = [tiny_contact(s, S) for s in range(3)]
+    batch = Batch(contacts, S)
+    batch.run(S)
+    batch.sync()
+    for i, c in enumerate(contacts):
+        orc = oracle_lib.OracleSim(c["cfg"], c["poses"][0])
+        orc.run(c["poses"], c["dt"], 0, S)
+        xo = orc.particles()[0]
+        xb = to_np(batch.contact(i).read_particles()[0]).T
+        err = np.abs(xb - xo).max()
+        print(f"tiny contact {i}: max |dx| = {err:.3e} m")
+        assert err <= 1e-5 * c["cfg"]["block_size"][0]
+        assert np.abs(to_np(batch.contact(i).heightmap()) - orc.heightmap()).max() <= 0.1e-6
+
+
+def test_tuner_writes_and_reuses_its_cache(gpu, tmp_path):
+    Batch, _ = gpu
+    S = 30
+    contacts = [W.batch_contact(seed, steps=S) for seed in (7, 8, 9)]
+    path = str(tmp_path / "tune.json")
+    a = Batch(contacts, S, tune_cache=path, tune=True)
+    ta = a.tuning()
+    data = json.load(open(path))
+    classes = {int(math.floor(math.log2(W.lattice_count(c["cfg"])))) for c in contacts}
+    assert {e["log2n"] for e in data["entries"]} == classes
+    for e in data["entries"]:
+        assert e["tile"] in (4, 8) and e["wg"] in (128, 256) and e["us_per_substep"] > 0
+    b = Batch(contacts, S, tune_cache=path, tune=False)
+    assert [t[:2] for t in b.tuning()] == [t[:2] for t in ta]
+    a.run(S)
+    b.run(S)
+    for i in range(3):
+        assert np.array_equal(to_np(a.contact(i).read_particles()[0]), to_np(b.contact(i).read_particles()[0]))

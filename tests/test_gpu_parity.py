@@ -238,3 +238,72 @@ def test_gelsight_shape_downscaled_parity(oracle_lib, gpu, family):
           f"indent {W.top_z(cfg) - 0.05e-3 - orc.heightmap().min():.3e} m")
     assert err_x <= 1e-5 * width
     assert err_h <= 0.1e-6
+
+
+def _corotated_case(seed):
+    wl = W.small_sphere_contact(seed=seed)
+    cfg = dict(wl["cfg"], model=W.COROTATED)
+    x, v, C, F = W.random_particle_state(seed, cfg, vel_scale=0.05, c_scale=30.0, f_scale=0.05)
+    rng = W.SplitMix64(seed + 100)
+    n = len(x)
+    picks = [rng.randint(n) for _ in range(24)]
+    R0 = np.array([[0.36, 0.48, -0.8], [-0.8, 0.6, 0.0], [0.48, 0.64, 0.6]])  # a rotation
+    for q, p in enumerate(picks):
+        if q % 2 == 0:
+            F[p] = R0 @ np.diag([1.2, 0.9, -0.4])      # inverted, well-separated singular values
+        else:
+            F[p] = R0 @ np.diag([1.1, 0.95, 3e-7])     # condition number ~4e6
+    return wl, cfg, (x, v, C, F), picks
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_corotated_substep_matches_oracle(oracle_lib, gpu, precision):
+    """Fixed-corotated model with inverted and ill-conditioned elements: the
+    FP32 path recomputes those polar factors in FP64 (counted), and the whole
+    substep matches the oracle, whose polar factor comes from a Jacobi
+    eigen-decomposition of F^T F."""
+    Sim, aos_to_soa = gpu
+    wl, cfg, state, picks = _corotated_case(11)
+    pose = wl["poses"][0].copy()
+    pose[2] -= 0.6e-3
+    pose_end = pose.copy()
+    pose_end[2] -= 0.5e-6
+    orc = oracle_lib.OracleSim(cfg, pose)
+    orc.set_particles(*state)
+    sim = Sim(cfg, pose, precision=precision)
+    sim.write_particles(*aos_to_soa(*state))
+    dt = wl["dt"]
+    tol = TOL[precision]
+    assert orc.step(pose_end, dt) == 0
+    sim.step(pose_end, dt)
+    xo, vo, Co, Fo = orc.particles()
+    xg, vg, Cg, Fg = (to_np(t) for t in sim.read_particles())
+    n = len(xo)
+    np.testing.assert_allclose(xg.T, xo, rtol=0, atol=(1e-15 if precision == "f64" else 1e-8))
+    np.testing.assert_allclose(vg.T, vo, rtol=0, atol=tol * 50 * np.abs(vo).max())
+    np.testing.assert_allclose(Fg.T.reshape(n, 3, 3), Fo, rtol=0, atol=tol * 10)
+    np.testing.assert_allclose(Cg.T.reshape(n, 3, 3), Co, rtol=0, atol=tol * 100 * np.abs(Co).max())
+    fb = sim.polar_fallbacks()
+    if precision == "f32":
+        # every picked particle needs FP64 in P2G (rebuilding A) and in G2P
+        assert fb >= 2 * len(set(picks)), fb
+    else:
+        assert fb == 0
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_corotated_press_trajectory(oracle_lib, gpu, precision):
+    Sim, _ = gpu
+    wl = W.small_sphere_contact(seed=4)
+    cfg = dict(wl["cfg"], model=W.COROTATED)
+    steps = 400
+    orc = oracle_lib.OracleSim(cfg, wl["poses"][0])
+    orc.run(wl["poses"], wl["dt"], 0, steps)
+    sim = Sim(cfg, wl["poses"][0], precision=precision)
+    sim.run(wl["poses"][1:steps + 1], wl["dt"])
+    x, _, _, _ = sim.read_particles()
+    err_x = np.abs(to_np(x).T - orc.particles()[0]).max()
+    err_h = np.abs(to_np(sim.heightmap()) - orc.heightmap()).max()
+    print(f"corotated {precision}: max |dx| = {err_x:.3e} m, max |dH| = {err_h:.3e} m")
+    assert err_x <= 1e-5 * 24e-3
+    assert err_h <= 0.1e-6
