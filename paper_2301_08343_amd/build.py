@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libtacchi.so")
-SOURCES = [os.path.join(CSRC, "tacchi.hip")]
+SOURCES = [os.path.join(CSRC, "tacchi.hip"), os.path.join(CSRC, "surrogate.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -1,0 +1,793 @@
+// Training and inference kernels of the tactile surrogate (gfx950).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (BF16 inputs,
+// FP32 accumulation). The forward kernel puts the weights in the MFMA's A
+// operand (rows = output channels) and the im2col patches in B (columns =
+// pixels), so each lane ends with 4 consecutive channels of one pixel and
+// stores them as one 8-byte write. Every operand fragment is a 16-byte load of
+// 8 consecutive K values: 8 input channels of one tap of NHWC activations, or
+// 8 entries of a packed weight row. The input gradient is the same kernel with
+// the spatially flipped, transposed weights. The weight gradient reduces over
+// pixels: pixel chunks are transposed through LDS, partial sums of pixel
+// ranges go to scratch and are reduced in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/tsg.h"
+
+namespace tsg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+thread_local std::string g_err;
+
+tsg_status fail(tsg_status st, const std::string &m)
+{
+    g_err = m;
+    return st;
+}
+
+#define TSG_LAUNCHED()                                                                                  \
+    do {                                                                                                \
+        hipError_t e_ = hipGetLastError();                                                              \
+        if (e_ != hipSuccess) return fail(-3, std::string("launch failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+// float -> bfloat16 with round-to-nearest-even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float dgelu(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p)
+{
+    return __builtin_bit_cast(bf16x8, *(const uint4 *)p);
+}
+
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u}); }
+
+// ------------------------------------------------------------------ weight packs
+
+__global__ void k_pack(const float *w, int cout, int cin, int cin_p, int cout_p, int taps, int kf, int kt,
+                       uint16_t *wf, uint16_t *wt)
+{
+    // one thread per (row, k) of the larger of the two packs
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (wf && idx < (int64_t)cout * kf) {
+        const int co = (int)(idx / kf), k = (int)(idx % kf);
+        const int tap = k / cin_p, ci = k % cin_p;
+        float v = 0.0f;
+        if (tap < taps && ci < cin) v = w[((int64_t)co * taps + tap) * cin + ci];
+        wf[idx] = f2bf(v);
+    }
+    if (wt && idx < (int64_t)cin_p * kt) {
+        const int ci = (int)(idx / kt), k = (int)(idx % kt);
+        const int tap = k / cout_p, co = k % cout_p;
+        float v = 0.0f;
+        if (tap < taps && co < cout && ci < cin) v = w[((int64_t)co * taps + (taps - 1 - tap)) * cin + ci];
+        wt[idx] = f2bf(v);
+    }
+}
+
+// ------------------------------------------------------------------ convolution
+
+struct ConvArgs {
+    const uint16_t *in;
+    int n, h, w, in_ld, in_off, cin_p;
+    const uint16_t *wp;
+    int kp;
+    const float *bias;
+    int cout;
+    uint16_t *out;
+    int out_ld, out_off;
+    uint16_t *z;
+    int z_ld, z_off;
+    float *out32;
+};
+
+// One wave computes (WCO*16) output channels x (WPX*16) pixels; 4 waves per
+// workgroup along the pixels.
+template <int WCO, int WPX, int TAPS, int EPI>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int hw = a.h * a.w, npix = a.n * hw;
+    const int co0 = blockIdx.y * (WCO * 16);
+    const int pix0 = (blockIdx.x * 4 + wave) * (WPX * 16);
+    if (pix0 >= npix) return;
+    const int r16 = lane & 15, kg = (lane >> 4) * 8;
+    int pn[WPX], ph[WPX], pw[WPX];
+    bool pv[WPX];
+#pragma unroll
+    for (int j = 0; j < WPX; ++j) {
+        const int p = pix0 + j * 16 + r16;
+        pv[j] = p < npix;
+        const int q = pv[j] ? p : 0;
+        pn[j] = q / hw;
+        const int rem = q - pn[j] * hw;
+        ph[j] = rem / a.w;
+        pw[j] = rem - ph[j] * a.w;
+    }
+    f32x4 acc[WCO][WPX];
+#pragma unroll
+    for (int i = 0; i < WCO; ++i)
+#pragma unroll
+        for (int j = 0; j < WPX; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < a.kp; k0 += 32) {
+        const int k = k0 + kg;
+        const int tap = k / a.cin_p;
+        const int ci = k - tap * a.cin_p;
+        const int dh = TAPS == 9 ? tap / 3 - 1 : 0, dw = TAPS == 9 ? tap % 3 - 1 : 0;
+        const bool tap_ok = tap < TAPS;
+        bf16x8 av[WCO], bv[WPX];
+#pragma unroll
+        for (int i = 0; i < WCO; ++i) {
+            const int co = co0 + i * 16 + r16;
+            av[i] = co < a.cout ? load8(a.wp + (int64_t)co * a.kp + k) : zero8();
+        }
+#pragma unroll
+        for (int j = 0; j < WPX; ++j) {
+            const int hh = ph[j] + dh, ww = pw[j] + dw;
+            const bool ok = tap_ok && pv[j] && (unsigned)hh < (unsigned)a.h && (unsigned)ww < (unsigned)a.w;
+            bv[j] = ok ? load8(a.in + ((int64_t)(pn[j] * a.h + hh) * a.w + ww) * a.in_ld + a.in_off + ci) : zero8();
+        }
+#pragma unroll
+        for (int i = 0; i < WCO; ++i)
+#pragma unroll
+            for (int j = 0; j < WPX; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    // lane holds acc[i][j][v] = out[pixel pix0 + 16 j + r16][channel co0 + 16 i + 4 (lane/16) + v]
+#pragma unroll
+    for (int j = 0; j < WPX; ++j) {
+        if (!pv[j]) continue;
+        const int64_t p = pix0 + j * 16 + r16;
+#pragma unroll
+        for (int i = 0; i < WCO; ++i) {
+            const int cb = co0 + i * 16 + (lane >> 4) * 4;
+            if (EPI == TSG_EPI_F32) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (cb + v < a.cout) a.out32[p * a.cout + cb + v] = acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f);
+                continue;
+            }
+            if (cb >= a.cout) continue;
+            uint16_t o[4];
+            if (EPI == TSG_EPI_BIAS_GELU) {
+                uint16_t zz[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float s = acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f);
+                    zz[v] = f2bf(s);
+                    o[v] = f2bf(gelu(s));
+                }
+                *(uint2 *)(a.z + p * a.z_ld + a.z_off + cb) =
+                    uint2{(uint32_t)zz[0] | ((uint32_t)zz[1] << 16), (uint32_t)zz[2] | ((uint32_t)zz[3] << 16)};
+            } else if (EPI == TSG_EPI_DGELU) {
+                const uint2 zr = *(const uint2 *)(a.z + p * a.z_ld + a.z_off + cb);
+                const uint16_t zz[4] = {(uint16_t)(zr.x & 0xffffu), (uint16_t)(zr.x >> 16), (uint16_t)(zr.y & 0xffffu),
+                                        (uint16_t)(zr.y >> 16)};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = f2bf(acc[i][j][v] * dgelu(bf2f(zz[v])));
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = f2bf(acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f));
+            }
+            *(uint2 *)(a.out + p * a.out_ld + a.out_off + cb) =
+                uint2{(uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16)};
+        }
+    }
+}
+
+template <int WCO, int TAPS>
+tsg_status launch_conv_epi(const ConvArgs &a, int epi, hipStream_t st)
+{
+    constexpr int WPX = 4;
+    const int npix = a.n * a.h * a.w;
+    const dim3 grid((npix + 4 * WPX * 16 - 1) / (4 * WPX * 16), (a.cout + WCO * 16 - 1) / (WCO * 16));
+    switch (epi) {
+    case TSG_EPI_BIAS: hipLaunchKernelGGL((k_conv<WCO, WPX, TAPS, TSG_EPI_BIAS>), grid, dim3(256), 0, st, a); break;
+    case TSG_EPI_BIAS_GELU:
+        hipLaunchKernelGGL((k_conv<WCO, WPX, TAPS, TSG_EPI_BIAS_GELU>), grid, dim3(256), 0, st, a);
+        break;
+    case TSG_EPI_DGELU: hipLaunchKernelGGL((k_conv<WCO, WPX, TAPS, TSG_EPI_DGELU>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_conv<WCO, WPX, TAPS, TSG_EPI_F32>), grid, dim3(256), 0, st, a); break;
+    }
+    TSG_LAUNCHED();
+    return 0;
+}
+
+// ------------------------------------------------------------------ weight gradient
+
+// Partial dw over one pixel range for a tile of 32 output channels x 32
+// input channels of one tap. The pixel chunk (32 pixels) of dout and of the
+// tap-shifted input are transposed into LDS (channel-major) so that each
+// lane's MFMA fragment is 8 consecutive pixels of one channel; 4 waves each
+// own one 16x16 quarter of the tile.
+__global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h, int w, int in_ld, int in_off,
+                                               int cin_p, const uint16_t *dout, int d_ld, int d_off, int cout,
+                                               int taps, int pix_per_split, float *part)
+{
+    __shared__ __align__(16) uint16_t sA[32][40];  // [co][pixel], padded rows
+    __shared__ __align__(16) uint16_t sB[32][40];  // [ci][pixel]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int hw = h * w, npix = n * hw;
+    const int co0 = blockIdx.x * 32;
+    const int tap = blockIdx.y / ((cin_p + 31) / 32);
+    const int ci0 = (blockIdx.y % ((cin_p + 31) / 32)) * 32;
+    const int split = blockIdx.z;
+    const int dh = taps == 9 ? tap / 3 - 1 : 0, dw = taps == 9 ? tap % 3 - 1 : 0;
+    const int pbeg = split * pix_per_split, pend = min(npix, pbeg + pix_per_split);
+    const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;  // this wave's quarter
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // loader mapping: 256 threads = 32 pixels x 8 groups of 4 channels
+    const int lp = tid >> 3, lc = (tid & 7) * 4;
+    for (int p0 = pbeg; p0 < pend; p0 += 32) {
+        const int p = p0 + lp;
+        uint2 va = uint2{0u, 0u}, vb = uint2{0u, 0u};
+        if (p < pend) {
+            if (co0 + lc < cout) va = *(const uint2 *)(dout + (int64_t)p * d_ld + d_off + co0 + lc);
+            const int nn = p / hw, rem = p - nn * hw, hh = rem / w + dh, ww = rem % w + dw;
+            if (ci0 + lc < cin_p && (unsigned)hh < (unsigned)h && (unsigned)ww < (unsigned)w)
+                vb = *(const uint2 *)(in + ((int64_t)(nn * h + hh) * w + ww) * in_ld + in_off + ci0 + lc);
+        }
+        __syncthreads();
+        sA[lc + 0][lp] = (uint16_t)(va.x & 0xffffu);
+        sA[lc + 1][lp] = (uint16_t)(va.x >> 16);
+        sA[lc + 2][lp] = (uint16_t)(va.y & 0xffffu);
+        sA[lc + 3][lp] = (uint16_t)(va.y >> 16);
+        sB[lc + 0][lp] = (uint16_t)(vb.x & 0xffffu);
+        sB[lc + 1][lp] = (uint16_t)(vb.x >> 16);
+        sB[lc + 2][lp] = (uint16_t)(vb.y & 0xffffu);
+        sB[lc + 3][lp] = (uint16_t)(vb.y >> 16);
+        __syncthreads();
+        const int r16 = lane & 15, kg = (lane >> 4) * 8;
+        const bf16x8 a8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[wm + r16][kg]);
+        const bf16x8 b8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sB[wn + r16][kg]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc, 0, 0, 0);
+    }
+    // acc[v] = partial dw[co0 + wm + 4 (lane/16) + v][tap][ci0 + wn + lane%16]
+    const int ci = ci0 + wn + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int co = co0 + wm + (lane >> 4) * 4 + v;
+        if (co < cout && ci < cin_p)
+            part[(((int64_t)split * cout + co) * taps + tap) * cin_p + ci] = acc[v];
+    }
+}
+
+// dw[co][tap][ci] = sum over splits (fixed order) of the partials, ci < cin.
+__global__ void k_wgrad_reduce(const float *part, int splits, int cout, int taps, int cin, int cin_p, float *dw)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)cout * taps * cin;
+    if (idx >= total) return;
+    const int ci = (int)(idx % cin);
+    const int64_t ct = idx / cin;  // co * taps + tap
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += part[((int64_t)k * cout * taps + ct) * cin_p + ci];
+    dw[idx] = s;
+}
+
+// Column sums of a [npix][c] view: one partial per (split, channel), then a
+// fixed-order reduction. Used for the bias gradients.
+__global__ void k_colsum_bf16(const uint16_t *d, int npix, int c, int ld, int off, int rows_per_split, float *part)
+{
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    const int split = blockIdx.y;
+    if (ch >= c) return;
+    const int r0 = split * rows_per_split, r1 = min(npix, r0 + rows_per_split);
+    float s = 0.0f;
+    for (int r = r0; r < r1; ++r) s += bf2f(d[(int64_t)r * ld + off + ch]);
+    part[(int64_t)split * c + ch] = s;
+}
+
+__global__ void k_colsum_reduce(const float *part, int splits, int c, float *out)
+{
+    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= c) return;
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * c + ch];
+    out[ch] = s;
+}
+
+// 1x1 head, FP32 output gradient: partial sums of dout^T in (cout x cin) and
+// of dout (bias) per pixel range.
+__global__ void k_head_wgrad(const uint16_t *in, int npix, int in_ld, int in_off, int cin, const float *dout,
+                             int cout, int rows_per_split, float *part)
+{
+    const int split = blockIdx.x;
+    const int t = threadIdx.x;  // one thread per (co, ci) pair or bias entry
+    const int nval = cout * (cin + 1);
+    if (t >= nval) return;
+    const int co = t / (cin + 1), ci = t % (cin + 1);
+    const int r0 = split * rows_per_split, r1 = min(npix, r0 + rows_per_split);
+    float s = 0.0f;
+    for (int r = r0; r < r1; ++r) {
+        const float g = dout[(int64_t)r * cout + co];
+        s += ci < cin ? g * bf2f(in[(int64_t)r * in_ld + in_off + ci]) : g;
+    }
+    part[(int64_t)split * nval + t] = s;
+}
+
+constexpr int kHeadSplits = 256;
+
+// Fixed-order sum of the head partials into dw [cout][cin] and db [cout].
+__global__ void k_head_reduce(const float *part, int splits, int cout, int cin, float *dw, float *db)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nval = cout * (cin + 1);
+    if (t >= nval) return;
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * nval + t];
+    const int co = t / (cin + 1), ci = t % (cin + 1);
+    if (ci < cin)
+        dw[co * cin + ci] = s;
+    else
+        db[co] = s;
+}
+
+__global__ void k_head_dgrad(const float *dout, int npix, int cout, const float *w, int cin, uint16_t *din, int ld,
+                             int off, const uint16_t *z, int z_ld, int z_off)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)npix * cin) return;
+    const int64_t p = idx / cin;
+    const int ci = (int)(idx % cin);
+    float s = 0.0f;
+    for (int co = 0; co < cout; ++co) s += dout[p * cout + co] * w[(int64_t)co * cin + ci];
+    if (z) s *= dgelu(bf2f(z[p * z_ld + z_off + ci]));
+    din[p * ld + off + ci] = f2bf(s);
+}
+
+// ------------------------------------------------------------------ pooling, upsampling, elementwise
+
+__global__ void k_avgpool2(const uint16_t *in, int n, int h, int w, int c, int ld, int off, uint16_t *out, int old,
+                           int ooff)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ho = h / 2, wo = w / 2;
+    if (idx >= (int64_t)n * ho * wo * c) return;
+    const int ch = (int)(idx % c);
+    const int64_t q = idx / c;
+    const int x = (int)(q % wo), y = (int)((q / wo) % ho), nn = (int)(q / ((int64_t)wo * ho));
+    float s = 0.0f;
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+            s += bf2f(in[((int64_t)(nn * h + 2 * y + dy) * w + 2 * x + dx) * ld + off + ch]);
+    out[q * old + ooff + ch] = f2bf(0.25f * s);
+}
+
+__global__ void k_avgpool2_bwd(const uint16_t *dout, int n, int h, int w, int c, int dld, int doff, uint16_t *din,
+                               int ild, int ioff, int accumulate)
+{
+    // h, w: input (fine) size; one thread per fine element
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * h * w * c) return;
+    const int ch = (int)(idx % c);
+    const int64_t q = idx / c;
+    const int x = (int)(q % w), y = (int)((q / w) % h), nn = (int)(q / ((int64_t)w * h));
+    const int ho = h / 2, wo = w / 2;
+    float g = 0.25f * bf2f(dout[((int64_t)(nn * ho + y / 2) * wo + x / 2) * dld + doff + ch]);
+    uint16_t *dst = din + q * ild + ioff + ch;
+    if (accumulate) g += bf2f(*dst);
+    *dst = f2bf(g);
+}
+
+__global__ void k_upsample2(const uint16_t *in, int n, int h, int w, int c, int ld, int off, uint16_t *out, int old,
+                            int ooff)
+{
+    // h, w: input (coarse) size; one thread per fine element
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int H2 = 2 * h, W2 = 2 * w;
+    if (idx >= (int64_t)n * H2 * W2 * c) return;
+    const int ch = (int)(idx % c);
+    const int64_t q = idx / c;
+    const int x = (int)(q % W2), y = (int)((q / W2) % H2), nn = (int)(q / ((int64_t)W2 * H2));
+    out[q * old + ooff + ch] = in[((int64_t)(nn * h + y / 2) * w + x / 2) * ld + off + ch];
+}
+
+__global__ void k_upsample2_bwd(const uint16_t *dout, int n, int h, int w, int c, int dld, int doff, uint16_t *din,
+                                int ild, int ioff)
+{
+    // h, w: coarse size; one thread per coarse element
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * h * w * c) return;
+    const int ch = (int)(idx % c);
+    const int64_t q = idx / c;
+    const int x = (int)(q % w), y = (int)((q / w) % h), nn = (int)(q / ((int64_t)w * h));
+    const int W2 = 2 * w;
+    float s = 0.0f;
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+            s += bf2f(dout[((int64_t)(nn * 2 * h + 2 * y + dy) * W2 + 2 * x + dx) * dld + doff + ch]);
+    din[q * ild + ioff + ch] = f2bf(s);
+}
+
+__global__ void k_add_inplace(uint16_t *a, int ald, int aoff, const uint16_t *b, int bld, int boff, int npix, int c)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)npix * c) return;
+    const int64_t p = idx / c;
+    const int ch = (int)(idx % c);
+    uint16_t *pa = a + p * ald + aoff + ch;
+    *pa = f2bf(bf2f(*pa) + bf2f(b[p * bld + boff + ch]));
+}
+
+__global__ void k_dgelu(uint16_t *d, int dld, int doff, const uint16_t *z, int zld, int zoff, int npix, int c)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)npix * c) return;
+    const int64_t p = idx / c;
+    const int ch = (int)(idx % c);
+    uint16_t *pd = d + p * dld + doff + ch;
+    *pd = f2bf(bf2f(*pd) * dgelu(bf2f(z[p * zld + zoff + ch])));
+}
+
+__global__ void k_to_bf16(const float *src, int npix, int c, uint16_t *dst, int cp)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)npix * cp) return;
+    const int64_t p = idx / cp;
+    const int ch = (int)(idx % cp);
+    dst[idx] = ch < c ? f2bf(src[p * c + ch]) : (uint16_t)0;
+}
+
+// MSE: per-block partial sums of squared errors (fixed order), then one block
+// adds the partials in order.
+__global__ void __launch_bounds__(256) k_mse_partial(const float *pred, const float *target, int64_t count,
+                                                     float *dpred, float scale, float *part)
+{
+    __shared__ float red[256];
+    const int64_t per = (count + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = blockIdx.x * per, b1 = min(count, b0 + per);
+    float s = 0.0f;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+        const float e = pred[i] - target[i];
+        s += e * e;
+        if (dpred) dpred[i] = 2.0f * e * scale;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_mse_final(const float *part, int nparts, float scale, float *loss)
+{
+    if (threadIdx.x != 0) return;
+    float s = 0.0f;
+    for (int k = 0; k < nparts; ++k) s += part[k];
+    *loss = s * scale;
+}
+
+__global__ void k_adamw(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                        float eps, float wd, float bc1, float bc2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1, vh = vi / bc2;
+    p[i] -= lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+}
+
+// Nearest neighbour: one workgroup per query; the reference set is streamed.
+__global__ void __launch_bounds__(256) k_nn(const float *q, int nq, const float *t, int nt, int d, float *dist2,
+                                            int *index)
+{
+    __shared__ float best[256];
+    __shared__ int bidx[256];
+    const int i = blockIdx.x;
+    if (i >= nq) return;
+    float bd = INFINITY;
+    int bi = 0x7fffffff;
+    for (int j = threadIdx.x; j < nt; j += 256) {
+        float s = 0.0f;
+        for (int k = 0; k < d; ++k) {
+            const float e = q[(int64_t)i * d + k] - t[(int64_t)j * d + k];
+            s += e * e;
+        }
+        if (s < bd || (s == bd && j < bi)) {
+            bd = s;
+            bi = j;
+        }
+    }
+    best[threadIdx.x] = bd;
+    bidx[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const float od = best[threadIdx.x + o];
+            const int oi = bidx[threadIdx.x + o];
+            if (od < best[threadIdx.x] || (od == best[threadIdx.x] && oi < bidx[threadIdx.x])) {
+                best[threadIdx.x] = od;
+                bidx[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        dist2[i] = best[0];
+        index[i] = bidx[0];
+    }
+}
+
+unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace tsg
+
+using namespace tsg;
+
+extern "C" {
+
+const char *tsg_last_error(void) { return g_err.c_str(); }
+
+int32_t tsg_pack_k(int32_t taps, int32_t cin_p) { return ((taps * cin_p + 31) / 32) * 32; }
+
+tsg_status tsg_pack_weights(const float *w, int32_t cout, int32_t cin, int32_t cin_p, int32_t cout_p, int32_t taps,
+                            uint16_t *wf, uint16_t *wt, void *stream)
+{
+    if (!w || cout < 1 || cin < 1 || cin_p < cin || cout_p < cout || (taps != 1 && taps != 9) || cin_p % 8 ||
+        cout_p % 8)
+        return fail(-1, "tsg_pack_weights: bad arguments");
+    const int kf = tsg_pack_k(taps, cin_p), kt = tsg_pack_k(taps, cout_p);
+    const int64_t n = std::max<int64_t>(wf ? (int64_t)cout * kf : 0, wt ? (int64_t)cin_p * kt : 0);
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, w, cout, cin, cin_p, cout_p,
+                       taps, kf, kt, wf, wt);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_conv(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t in_ld, int32_t in_off, int32_t cin_p,
+                    const uint16_t *wpack, const float *bias, int32_t cout, int32_t taps, int32_t epi, uint16_t *out,
+                    int32_t out_ld, int32_t out_off, uint16_t *zbuf, int32_t z_ld, int32_t z_off, float *out32,
+                    void *stream)
+{
+    if (!in || !wpack || n < 1 || h < 1 || w < 1 || cin_p < 8 || cin_p % 8 || in_ld % 8 || in_off % 8 ||
+        in_off + cin_p > in_ld || cout < 1 || (taps != 1 && taps != 9) || epi < 0 || epi > 3 ||
+        !aligned16(in) || !aligned16(wpack))
+        return fail(-1, "tsg_conv: bad input view or weights");
+    if (epi == TSG_EPI_F32) {
+        if (!out32) return fail(-1, "tsg_conv: F32 epilogue needs out32");
+    } else {
+        if (!out || cout % 4 || out_ld % 4 || out_off % 4 || out_off + cout > out_ld || ((uintptr_t)out & 7))
+            return fail(-1, "tsg_conv: bad output view");
+        if ((epi == TSG_EPI_BIAS_GELU || epi == TSG_EPI_DGELU) &&
+            (!zbuf || z_ld % 4 || z_off % 4 || z_off + cout > z_ld || ((uintptr_t)zbuf & 7)))
+            return fail(-1, "tsg_conv: GELU epilogues need a pre-activation view");
+    }
+    ConvArgs a{in, n, h, w, in_ld, in_off, cin_p, wpack, tsg_pack_k(taps, cin_p), bias, cout, out, out_ld, out_off,
+               zbuf, z_ld, z_off, out32};
+    hipStream_t st = (hipStream_t)stream;
+    const int wco = cout >= 64 ? 4 : (cout >= 32 ? 2 : 1);
+    if (taps == 9) {
+        if (wco == 4) return launch_conv_epi<4, 9>(a, epi, st);
+        if (wco == 2) return launch_conv_epi<2, 9>(a, epi, st);
+        return launch_conv_epi<1, 9>(a, epi, st);
+    }
+    if (wco == 4) return launch_conv_epi<4, 1>(a, epi, st);
+    if (wco == 2) return launch_conv_epi<2, 1>(a, epi, st);
+    return launch_conv_epi<1, 1>(a, epi, st);
+}
+
+static int wgrad_splits(int64_t npix, int cout, int cin_p, int taps)
+{
+    const int64_t tiles = (int64_t)((cout + 31) / 32) * taps * ((cin_p + 31) / 32);
+    int64_t s = std::max<int64_t>(1, 2048 / tiles);
+    s = std::min<int64_t>(s, std::max<int64_t>(1, npix / 256));
+    return (int)s;
+}
+
+size_t tsg_wgrad_scratch_bytes(int32_t n, int32_t h, int32_t w, int32_t cin_p, int32_t cout, int32_t taps)
+{
+    const int64_t npix = (int64_t)n * h * w;
+    const int s = wgrad_splits(npix, cout, cin_p, taps);
+    const size_t part = (size_t)s * cout * taps * cin_p * sizeof(float);
+    const size_t bias = (size_t)64 * cout * sizeof(float);
+    return part + bias;
+}
+
+tsg_status tsg_conv_wgrad(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t in_ld, int32_t in_off,
+                          int32_t cin, int32_t cin_p, const uint16_t *dout, int32_t d_ld, int32_t d_off, int32_t cout,
+                          int32_t taps, float *dw, float *db, float *scratch, size_t scratch_bytes, void *stream)
+{
+    if (!in || !dout || !dw || !scratch || cin < 1 || cin_p < cin || cin_p % 4 || cout % 4 || in_ld % 4 ||
+        in_off % 4 || d_ld % 4 || d_off % 4 || (taps != 1 && taps != 9))
+        return fail(-1, "tsg_conv_wgrad: bad arguments");
+    if (scratch_bytes < tsg_wgrad_scratch_bytes(n, h, w, cin_p, cout, taps))
+        return fail(-1, "tsg_conv_wgrad: scratch too small");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t npix = (int64_t)n * h * w;
+    const int splits = wgrad_splits(npix, cout, cin_p, taps);
+    int pps = (int)((npix + splits - 1) / splits);
+    pps = ((pps + 31) / 32) * 32;
+    const dim3 grid((cout + 31) / 32, taps * ((cin_p + 31) / 32), splits);
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld, d_off, cout,
+                       taps, pps, scratch);
+    TSG_LAUNCHED();
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout * taps * cin)), dim3(256), 0, st, scratch, splits,
+                       cout, taps, cin, cin_p, dw);
+    TSG_LAUNCHED();
+    if (db) {
+        float *bpart = scratch + (size_t)splits * cout * taps * cin_p;
+        const int bs = 64;
+        const int rps = (int)((npix + bs - 1) / bs);
+        hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks_for(cout, 64), bs), dim3(64), 0, st, dout, (int)npix, cout, d_ld,
+                           d_off, rps, bpart);
+        TSG_LAUNCHED();
+        hipLaunchKernelGGL(k_colsum_reduce, dim3(blocks_for(cout, 64)), dim3(64), 0, st, bpart, bs, cout, db);
+        TSG_LAUNCHED();
+    }
+    return 0;
+}
+
+size_t tsg_head_scratch_bytes(int32_t cout, int32_t cin)
+{
+    return (size_t)kHeadSplits * cout * (cin + 1) * sizeof(float);
+}
+
+tsg_status tsg_conv_wgrad_f32(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t in_ld, int32_t in_off,
+                              int32_t cin, int32_t cin_p, const float *dout, int32_t cout, float *dw, float *db,
+                              float *scratch, size_t scratch_bytes, void *stream)
+{
+    const int64_t npix = (int64_t)n * h * w;
+    if (!in || !dout || !dw || !db || !scratch || cout < 1 || cin < 1 || cout * (cin + 1) > 1024 || cin_p < cin ||
+        in_off + cin > in_ld || npix < 1)
+        return fail(-1, "tsg_conv_wgrad_f32: bad arguments");
+    if (scratch_bytes < tsg_head_scratch_bytes(cout, cin)) return fail(-1, "tsg_conv_wgrad_f32: scratch too small");
+    hipStream_t st = (hipStream_t)stream;
+    const int nval = cout * (cin + 1);
+    const int rps = (int)((npix + kHeadSplits - 1) / kHeadSplits);
+    hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadSplits), dim3(((nval + 63) / 64) * 64), 0, st, in, (int)npix, in_ld,
+                       in_off, cin, dout, cout, rps, scratch);
+    TSG_LAUNCHED();
+    hipLaunchKernelGGL(k_head_reduce, dim3(blocks_for(nval, 64)), dim3(64), 0, st, scratch, kHeadSplits, cout, cin, dw,
+                       db);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_head_dgrad(const float *dout, int32_t npix, int32_t cout, const float *w, int32_t cin, uint16_t *din,
+                          int32_t din_ld, int32_t din_off, const uint16_t *zbuf, int32_t z_ld, int32_t z_off,
+                          void *stream)
+{
+    if (!dout || !w || !din) return fail(-1, "tsg_head_dgrad: bad arguments");
+    hipLaunchKernelGGL(k_head_dgrad, dim3(blocks_for((int64_t)npix * cin)), dim3(256), 0, (hipStream_t)stream, dout,
+                       npix, cout, w, cin, din, din_ld, din_off, zbuf, z_ld, z_off);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_avgpool2(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t c, int32_t in_ld, int32_t in_off,
+                        uint16_t *out, int32_t out_ld, int32_t out_off, void *stream)
+{
+    if (!in || !out || h % 2 || w % 2) return fail(-1, "tsg_avgpool2: bad arguments");
+    hipLaunchKernelGGL(k_avgpool2, dim3(blocks_for((int64_t)n * (h / 2) * (w / 2) * c)), dim3(256), 0,
+                       (hipStream_t)stream, in, n, h, w, c, in_ld, in_off, out, out_ld, out_off);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_avgpool2_bwd(const uint16_t *dout, int32_t n, int32_t h, int32_t w, int32_t c, int32_t d_ld,
+                            int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, int32_t accumulate,
+                            void *stream)
+{
+    if (!dout || !din || h % 2 || w % 2) return fail(-1, "tsg_avgpool2_bwd: bad arguments");
+    hipLaunchKernelGGL(k_avgpool2_bwd, dim3(blocks_for((int64_t)n * h * w * c)), dim3(256), 0, (hipStream_t)stream,
+                       dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, accumulate);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_upsample2(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t c, int32_t in_ld,
+                         int32_t in_off, uint16_t *out, int32_t out_ld, int32_t out_off, void *stream)
+{
+    if (!in || !out) return fail(-1, "tsg_upsample2: bad arguments");
+    hipLaunchKernelGGL(k_upsample2, dim3(blocks_for((int64_t)n * 4 * h * w * c)), dim3(256), 0, (hipStream_t)stream,
+                       in, n, h, w, c, in_ld, in_off, out, out_ld, out_off);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_upsample2_bwd(const uint16_t *dout, int32_t n, int32_t h, int32_t w, int32_t c, int32_t d_ld,
+                             int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, void *stream)
+{
+    if (!dout || !din) return fail(-1, "tsg_upsample2_bwd: bad arguments");
+    hipLaunchKernelGGL(k_upsample2_bwd, dim3(blocks_for((int64_t)n * h * w * c)), dim3(256), 0, (hipStream_t)stream,
+                       dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_add_inplace(uint16_t *a, int32_t a_ld, int32_t a_off, const uint16_t *b, int32_t b_ld, int32_t b_off,
+                           int32_t npix, int32_t c, void *stream)
+{
+    if (!a || !b) return fail(-1, "tsg_add_inplace: bad arguments");
+    hipLaunchKernelGGL(k_add_inplace, dim3(blocks_for((int64_t)npix * c)), dim3(256), 0, (hipStream_t)stream, a, a_ld,
+                       a_off, b, b_ld, b_off, npix, c);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_dgelu(uint16_t *d, int32_t d_ld, int32_t d_off, const uint16_t *z, int32_t z_ld, int32_t z_off,
+                     int32_t npix, int32_t c, void *stream)
+{
+    if (!d || !z) return fail(-1, "tsg_dgelu: bad arguments");
+    hipLaunchKernelGGL(k_dgelu, dim3(blocks_for((int64_t)npix * c)), dim3(256), 0, (hipStream_t)stream, d, d_ld, d_off,
+                       z, z_ld, z_off, npix, c);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_mse(const float *pred, const float *target, int64_t count, float *loss, float *dpred, float *scratch,
+                   void *stream)
+{
+    if (!pred || !target || !loss || !scratch || count < 1) return fail(-1, "tsg_mse: bad arguments");
+    const int parts = 1024;
+    hipLaunchKernelGGL(k_mse_partial, dim3(parts), dim3(256), 0, (hipStream_t)stream, pred, target, count, dpred,
+                       1.0f / (float)count, scratch);
+    TSG_LAUNCHED();
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, (hipStream_t)stream, scratch, parts, 1.0f / (float)count,
+                       loss);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_adamw(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                     float wd, int32_t step, void *stream)
+{
+    if (!p || !g || !m || !v || n < 1 || step < 1) return fail(-1, "tsg_adamw: bad arguments");
+    const float bc1 = 1.0f - (float)std::pow((double)b1, (double)step);
+    const float bc2 = 1.0f - (float)std::pow((double)b2, (double)step);
+    hipLaunchKernelGGL(k_adamw, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr, b1, b2, eps,
+                       wd, bc1, bc2);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_to_bf16(const float *src, int32_t npix, int32_t c, uint16_t *dst, int32_t cp, void *stream)
+{
+    if (!src || !dst || cp < c) return fail(-1, "tsg_to_bf16: bad arguments");
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for((int64_t)npix * cp)), dim3(256), 0, (hipStream_t)stream, src, npix, c,
+                       dst, cp);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_nn_dist(const float *q, int32_t nq, const float *t, int32_t nt, int32_t d, float *dist2, int32_t *index,
+                       void *stream)
+{
+    if (!q || !t || !dist2 || !index || nq < 1 || nt < 1 || d < 1) return fail(-1, "tsg_nn_dist: bad arguments");
+    hipLaunchKernelGGL(k_nn, dim3(nq), dim3(256), 0, (hipStream_t)stream, q, nq, t, nt, d, dist2, index);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+}  // extern "C"

@@ -150,6 +150,59 @@ def lib():
     return _lib
 
 
+# every entry point declared in include/tsg.h, with its argument types
+_i32, _i64, _sz, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float
+_TSG_SIGS = {
+    "tsg_pack_k": (_i32, [_i32, _i32]),
+    "tsg_pack_weights": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "tsg_conv": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _i32, _i32,
+                        _vp, _i32, _i32, _vp, _vp]),
+    "tsg_wgrad_scratch_bytes": (_sz, [_i32, _i32, _i32, _i32, _i32, _i32]),
+    "tsg_conv_wgrad": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _vp,
+                              _vp, _vp, _sz, _vp]),
+    "tsg_head_scratch_bytes": (_sz, [_i32, _i32]),
+    "tsg_conv_wgrad_f32": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _sz,
+                                  _vp]),
+    "tsg_head_dgrad": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _i32, _i32, _vp]),
+    "tsg_avgpool2": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp]),
+    "tsg_avgpool2_bwd": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _vp]),
+    "tsg_upsample2": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp]),
+    "tsg_upsample2_bwd": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp]),
+    "tsg_add_inplace": (_i32, [_vp, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _vp]),
+    "tsg_dgelu": (_i32, [_vp, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _vp]),
+    "tsg_mse": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "tsg_adamw": (_i32, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _f32, _i32, _vp]),
+    "tsg_to_bf16": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp]),
+    "tsg_nn_dist": (_i32, [_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp]),
+    "tsg_last_error": (ctypes.c_char_p, []),
+}
+TSG_EXPORTS = tuple(_TSG_SIGS)
+_tsg = None
+
+
+class TsgError(RuntimeError):
+    pass
+
+
+def tsg():
+    """The library with the surrogate kernels' argument types set."""
+    global _tsg
+    if _tsg is None:
+        L = lib()
+        for name, (res, args) in _TSG_SIGS.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _tsg = L
+    return _tsg
+
+
+def tsg_call(name: str, *args):
+    """Call a tsg_* entry point and raise on a non-zero status."""
+    st = getattr(tsg(), name)(*args)
+    if st != 0:
+        raise TsgError(f"{name}: {tsg().tsg_last_error().decode()} (status {st})")
+
+
 def check(status: int):
     if status != OK:
         raise TacchiError(status, lib().tacchi_last_error().decode())
