@@ -164,6 +164,29 @@ tacchi_status tacchi_heightmap(tacchi_sim *sim, void *out, int32_t out_on_device
 tacchi_status tacchi_render(tacchi_sim *sim, const tacchi_render_params *rp, float *rgb,
                             int32_t h, int32_t w, int32_t out_on_device);
 
+/* Displacement field of the contact surface (the depth map of Sec. III-B
+ * extended to all three components): out[r][c][a] (metres, float32,
+ * res x res x 3) is the displacement x - X of the top face at the centre of
+ * cell (c, r) of a res x res partition of the block's top face, bilinear in
+ * the top-layer particles' displacements (particle i at (i + 1/2) h; clamped
+ * at the border). 1 <= res <= 4096. With out_on_device != 0 the call is
+ * asynchronous on the simulation's stream; otherwise it synchronises and
+ * reports the device error word. */
+tacchi_status tacchi_surface_displacement(tacchi_sim *sim, int32_t res, float *out, int32_t out_on_device);
+
+/* Gap field of an indenter over the undeformed top face, the geometric input
+ * of the learned surrogate: for n configurations and poses (indenter frame ->
+ * world, as in tacchi_step), out[k][r][c] (metres, float32, device memory)
+ * = z_ind - z_top at the centre of cell (c, r) of a res x res partition of
+ * block k's top face, where z_top = block.origin[2] + block.size[2] and z_ind
+ * is the lowest point of the indenter's solid (the inside test of Eq. 10's
+ * rigid body) on the vertical through that point; values are clipped to
+ * [-clip, clip] (no indenter within clip above: +clip). Found by sampling the
+ * inside test at 512 heights from z_top - clip and bisecting the first
+ * crossing 40 times. Synchronises. Errors: E_ARG, E_DEVICE. */
+tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n,
+                                  int32_t res, double clip, float *out, void *hip_stream);
+
 /* Particle state in SoA layout (see the conventions); any pointer may be
  * NULL to skip that array. Synchronises. */
 tacchi_status tacchi_read_particles(tacchi_sim *sim, void *x, void *v, void *C, void *F,
@@ -261,6 +284,11 @@ int64_t tacchi_batch_substeps_done(const tacchi_batch *batch);
 
 /* Drain the stream and report the first contact's device error, if any. */
 tacchi_status tacchi_batch_sync(tacchi_batch *batch);
+
+/* tacchi_surface_displacement of every contact: out is [n][res][res][3].
+ * Synchronises and reports device errors. */
+tacchi_status tacchi_batch_surface_displacement(tacchi_batch *batch, int32_t res, float *out,
+                                                int32_t out_on_device);
 
 /* Release the batch and its contact handles (host memory only). */
 void tacchi_batch_destroy(tacchi_batch *batch);

@@ -134,6 +134,17 @@ tsg_status tsg_to_bf16(const float *src, int32_t npix, int32_t c, uint16_t *dst,
 tsg_status tsg_nn_dist(const float *q, int32_t nq, const float *t, int32_t nt, int32_t d, float *dist2,
                        int32_t *index, void *stream);
 
+/* Router features of n gap fields [n][h][w] (fp32): out[k] (row length
+ * (h/f)(w/f) + 1) holds the f x f box means of field k in row-major order
+ * followed by depth[k] * depth_scale. h and w must be multiples of f. */
+tsg_status tsg_features(const float *gap, int32_t n, int32_t h, int32_t w, int32_t f, const float *depth,
+                        float depth_scale, float *out, void *stream);
+
+/* Per-sample mean squared difference of channel ch of two [n][npix][c] fp32
+ * arrays: out[k] = mean_p (a[k][p][ch] - b[k][p][ch])^2 (fixed-order sum). */
+tsg_status tsg_channel_mse(const float *a, const float *b, int32_t n, int32_t npix, int32_t c, int32_t ch,
+                           float *out, void *stream);
+
 const char *tsg_last_error(void);
 
 #ifdef __cplusplus

@@ -89,6 +89,9 @@ def lib():
         L.orc_phi.restype = ctypes.c_double
         L.orc_phi.argtypes = [ctypes.c_int, _dp, ctypes.c_uint64, _dp]
         L.orc_indenter_velocity.argtypes = [_dp, _dp, ctypes.c_double, _dp, _dp]
+        L.orc_lowest_point.restype = ctypes.c_double
+        L.orc_lowest_point.argtypes = [ctypes.c_int, _dp, ctypes.c_uint64, _dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.orc_noise2.restype = ctypes.c_double
         L.orc_noise2.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_double]
         _lib = L
@@ -262,3 +265,53 @@ def indenter_velocity(pose0, pose1, dt, X):
 
 def noise2(seed: int, x: float, y: float) -> float:
     return lib().orc_noise2(seed, x, y)
+
+
+def lowest_point(shape: int, sp, seed: int, pose, x, y, zlo, zhi, nscan=20000):
+    spc = np.ascontiguousarray(list(sp) + [0.0] * (8 - len(sp)), dtype=np.float64)
+    pc = np.ascontiguousarray(pose, dtype=np.float64)
+    return lib().orc_lowest_point(shape, _ptr(spc), seed, _ptr(pc), x, y, zlo, zhi, nscan)
+
+
+def indenter_gap(cfg: dict, pose, res: int, clip: float, nscan: int = 20000):
+    """[res][res] gap z_ind - z_top over the centres of a res x res partition
+    of the block's top face (z_top = top face of the undeformed block), where
+    z_ind is the indenter's lowest point on each vertical; clipped to +-clip."""
+    ox, oy, oz = cfg["block_origin"]
+    wx, wy, wz = cfg["block_size"]
+    ztop = oz + wz
+    out = np.zeros((res, res))
+    for r in range(res):
+        for c in range(res):
+            x = ox + (c + 0.5) * wx / res
+            y = oy + (r + 0.5) * wy / res
+            z = lowest_point(cfg["shape"], cfg["sp"], cfg["seed"], pose, x, y, ztop - clip, ztop + clip, nscan)
+            out[r, c] = min(max(z - ztop, -clip), clip)
+    return out
+
+
+def surface_displacement(cfg: dict, x, res: int):
+    """[res][res][3] displacement of the top surface sampled at the centres of
+    a res x res partition of the top face: bilinear interpolation of the
+    top-layer particles' displacements x - X (x: [N][3] in lattice order
+    i + n0 (j + n1 k), X the cell-centred rest lattice), with the sample
+    clamped to the outermost particles."""
+    n0, n1, n2 = cfg["n"]
+    h = [cfg["block_size"][a] / cfg["n"][a] for a in range(3)]
+    o = cfg["block_origin"]
+    top = np.asarray(x, dtype=np.float64).reshape(n2, n1, n0, 3)[n2 - 1]
+    ii, jj = np.meshgrid(np.arange(n0), np.arange(n1), indexing="xy")
+    rest = np.stack([o[0] + (ii + 0.5) * h[0], o[1] + (jj + 0.5) * h[1],
+                     np.full(ii.shape, o[2] + (n2 - 0.5) * h[2])], axis=-1)
+    u = top - rest  # [n1][n0][3]
+    out = np.zeros((res, res, 3))
+    for r in range(res):
+        for c in range(res):
+            si = min(max((c + 0.5) * n0 / res - 0.5, 0.0), n0 - 1.0)
+            sj = min(max((r + 0.5) * n1 / res - 0.5, 0.0), n1 - 1.0)
+            i0 = min(int(np.floor(si)), n0 - 2)
+            j0 = min(int(np.floor(sj)), n1 - 2)
+            tx, ty = si - i0, sj - j0
+            out[r, c] = ((1 - tx) * (1 - ty) * u[j0, i0] + tx * (1 - ty) * u[j0, i0 + 1]
+                         + (1 - tx) * ty * u[j0 + 1, i0] + tx * ty * u[j0 + 1, i0 + 1])
+    return out

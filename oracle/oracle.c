@@ -316,6 +316,47 @@ static double phi_world(const orc_sim *s, const double pose[7], const double X[3
     return orc_phi(s->cfg.shape, s->cfg.sp, s->cfg.seed, pl);
 }
 
+/* Lowest point of the posed indenter on the vertical line through (x, y):
+ * the line is scanned upward from zlo in nscan equal steps up to zhi and the
+ * first step that lands inside is bisected until the bracket stops shrinking.
+ * Returns zlo when zlo is already inside and zhi + (zhi - zlo) when the line
+ * stays outside up to zhi. */
+double orc_lowest_point(int shape, const double sp[8], uint64_t seed, const double pose[7], double x, double y,
+                        double zlo, double zhi, int nscan)
+{
+    double R[9];
+    quat_to_matrix(pose + 3, R);
+    double r[3], pl[3];
+    r[0] = x - pose[0];
+    r[1] = y - pose[1];
+#define ORC_INSIDE(zz, res)                                                                            \
+    do {                                                                                               \
+        r[2] = (zz) - pose[2];                                                                         \
+        for (int i_ = 0; i_ < 3; ++i_) pl[i_] = R[0 * 3 + i_] * r[0] + R[1 * 3 + i_] * r[1] + R[2 * 3 + i_] * r[2]; \
+        (res) = orc_phi(shape, sp, seed, pl) <= 0.0;                                                   \
+    } while (0)
+    int in;
+    ORC_INSIDE(zlo, in);
+    if (in) return zlo;
+    double a = zlo;
+    for (int k = 1; k <= nscan; ++k) {
+        double b = zlo + (zhi - zlo) * (double)k / (double)nscan;
+        ORC_INSIDE(b, in);
+        if (in) {
+            for (;;) {
+                double m = 0.5 * (a + b);
+                if (m <= a || m >= b) break;
+                ORC_INSIDE(m, in);
+                if (in) b = m; else a = m;
+            }
+            return b;
+        }
+        a = b;
+    }
+#undef ORC_INSIDE
+    return zhi + (zhi - zlo);
+}
+
 /* ---------------------------------------------------------------- lifecycle */
 
 /* Initialization (Eq. 1 and the prose around it): particles on the

@@ -84,6 +84,8 @@ void orc_lame(double E, double nu, double *mu, double *lambda);
 int orc_stress(int model, double mu, double lambda, const double F[9], double tau[9]);
 int orc_polar(const double F[9], double R[9], double S[9]);
 double orc_phi(int shape, const double sp[8], uint64_t seed, const double p_local[3]);
+double orc_lowest_point(int shape, const double sp[8], uint64_t seed, const double pose[7], double x, double y,
+                        double zlo, double zhi, int nscan);
 void orc_indenter_velocity(const double pose0[7], const double pose1[7], double dt,
                            const double X[3], double v[3]);
 double orc_noise2(uint64_t seed, double x, double y);

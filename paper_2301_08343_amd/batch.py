@@ -69,6 +69,13 @@ class Batch:
     def sync(self):
         N.check(N.lib().tacchi_batch_sync(self._h))
 
+    def surface_displacement(self, res: int) -> torch.Tensor:
+        """[n][res][res][3] top-surface displacements (m, float32); synchronises."""
+        out = torch.empty(self.n, res, res, 3, dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        N.check(N.lib().tacchi_batch_surface_displacement(self._h, res, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             for v in self._views:

@@ -537,6 +537,48 @@ __global__ void __launch_bounds__(256) k_nn(const float *q, int nq, const float 
     }
 }
 
+// Router features: the f x f box means of a gap field followed by the
+// scaled depth; one thread per output value.
+__global__ void k_features(const float *gap, int n, int h, int w, int f, const float *depth, float depth_scale,
+                           float *out)
+{
+    const int ho = h / f, wo = w / f, row = ho * wo + 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * row) return;
+    const int k = (int)(idx / row), t = (int)(idx - (int64_t)k * row);
+    if (t == row - 1) {
+        out[idx] = depth[k] * depth_scale;
+        return;
+    }
+    const int y = t / wo, x = t - y * wo;
+    float s = 0.0f;
+    for (int dy = 0; dy < f; ++dy)
+        for (int dx = 0; dx < f; ++dx) s += gap[((int64_t)k * h + y * f + dy) * w + x * f + dx];
+    out[idx] = s / (float)(f * f);
+}
+
+// Per-sample mean squared difference of one channel: one workgroup per
+// sample, fixed-order reduction.
+__global__ void __launch_bounds__(256) k_channel_mse(const float *a, const float *b, int npix, int c, int ch,
+                                                     float *out)
+{
+    __shared__ float red[256];
+    const int k = blockIdx.x;
+    const float *pa = a + (int64_t)k * npix * c + ch, *pb = b + (int64_t)k * npix * c + ch;
+    float s = 0.0f;
+    for (int p = threadIdx.x; p < npix; p += 256) {
+        const float e = pa[(int64_t)p * c] - pb[(int64_t)p * c];
+        s += e * e;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0] / (float)npix;
+}
+
 unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -786,6 +828,27 @@ tsg_status tsg_nn_dist(const float *q, int32_t nq, const float *t, int32_t nt, i
 {
     if (!q || !t || !dist2 || !index || nq < 1 || nt < 1 || d < 1) return fail(-1, "tsg_nn_dist: bad arguments");
     hipLaunchKernelGGL(k_nn, dim3(nq), dim3(256), 0, (hipStream_t)stream, q, nq, t, nt, d, dist2, index);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_features(const float *gap, int32_t n, int32_t h, int32_t w, int32_t f, const float *depth,
+                        float depth_scale, float *out, void *stream)
+{
+    if (!gap || !depth || !out || n < 1 || f < 1 || h % f || w % f) return fail(-1, "tsg_features: bad arguments");
+    const int64_t total = (int64_t)n * ((h / f) * (w / f) + 1);
+    hipLaunchKernelGGL(k_features, dim3(blocks_for(total)), dim3(256), 0, (hipStream_t)stream, gap, n, h, w, f, depth,
+                       depth_scale, out);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_channel_mse(const float *a, const float *b, int32_t n, int32_t npix, int32_t c, int32_t ch, float *out,
+                           void *stream)
+{
+    if (!a || !b || !out || n < 1 || npix < 1 || c < 1 || ch < 0 || ch >= c)
+        return fail(-1, "tsg_channel_mse: bad arguments");
+    hipLaunchKernelGGL(k_channel_mse, dim3(n), dim3(256), 0, (hipStream_t)stream, a, b, npix, c, ch, out);
     TSG_LAUNCHED();
     return 0;
 }

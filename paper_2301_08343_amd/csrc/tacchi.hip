@@ -676,6 +676,76 @@ tacchi_status heightmap_t(tacchi_sim *s, void *out, int on_device, bool relative
 }
 
 template <typename T>
+tacchi_status surface_disp_t(tacchi_sim *s, int res, float *out)
+{
+    SimDev<T> &S = sdev<T>(s);
+    if (s->d.B == 4)
+        hipLaunchKernelGGL((k_surface_disp<T, 4>), dim3(grid1d((int64_t)res * res)), dim3(kWG), 0, s->stream, S,
+                           T(s->d.dx), res, out);
+    else
+        hipLaunchKernelGGL((k_surface_disp<T, 8>), dim3(grid1d((int64_t)res * res)), dim3(kWG), 0, s->stream, S,
+                           T(s->d.dx), res, out);
+    TC_LAUNCHED();
+    return TACCHI_OK;
+}
+
+// One vertical gap query: the indenter at a pose above a block's top face.
+struct GapDev {
+    IndenterDev<double> I;  // shape, parameters and orientation (indenter frame -> world)
+    double pos[3];          // indenter origin, world metres
+    double x0, y0, wx, wy;  // top face origin and extent
+    double ztop;            // undeformed top face height
+};
+
+// out[k][r][c] = (lowest z of indenter k on the vertical through the sample
+// point) - ztop, clipped to [-clip, clip]. The indenter's signed distance is
+// sampled upward from ztop - clip in 512 steps; the first sample inside is
+// refined by 40 bisections.
+__global__ void __launch_bounds__(kWG) k_indenter_gap(const GapDev *q, int n, int res, double clip, float *out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (idx >= (int64_t)n * res * res) return;
+    const int k = (int)(idx / ((int64_t)res * res));
+    const int rem = (int)(idx - (int64_t)k * res * res);
+    const int r = rem / res, c = rem - r * res;
+    const GapDev &g = q[k];
+    const double x = g.x0 + (c + 0.5) * g.wx / res, y = g.y0 + (r + 0.5) * g.wy / res;
+    const double r0 = x - g.pos[0], r1 = y - g.pos[1];
+    auto inside = [&](double z) {
+        const double r2 = z - g.pos[2];
+        const double px = g.I.R[0] * r0 + g.I.R[3] * r1 + g.I.R[6] * r2;
+        const double py = g.I.R[1] * r0 + g.I.R[4] * r1 + g.I.R[7] * r2;
+        const double pz = g.I.R[2] * r0 + g.I.R[5] * r1 + g.I.R[8] * r2;
+        return indenter_phi<double>(g.I, px, py, pz) <= 0.0;
+    };
+    constexpr int kSamples = 512;
+    const double zlo = g.ztop - clip, step = 2.0 * clip / kSamples;
+    double gap = clip;
+    if (inside(zlo)) {
+        gap = -clip;
+    } else {
+        double a = zlo;
+        for (int s = 1; s <= kSamples; ++s) {
+            const double b = zlo + s * step;
+            if (inside(b)) {
+                double lo = a, hi = b;
+                for (int it = 0; it < 40; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (inside(mid))
+                        hi = mid;
+                    else
+                        lo = mid;
+                }
+                gap = hi - g.ztop;
+                break;
+            }
+            a = b;
+        }
+    }
+    out[idx] = (float)gap;
+}
+
+template <typename T>
 tacchi_status render_t(tacchi_sim *s, const tacchi_render_params *rp, float *rgb, int h, int w, int on_device)
 {
     tacchi_status st = heightmap_t<T>(s, nullptr, 1, true);
@@ -895,6 +965,69 @@ tacchi_status tacchi_heightmap(tacchi_sim *s, void *out, int32_t on_device)
                                         : heightmap_t<float>(s, out, on_device, false);
     if (st) return st;
     return read_error_word(s);
+}
+
+tacchi_status tacchi_surface_displacement(tacchi_sim *s, int32_t res, float *out, int32_t on_device)
+{
+    if (!s || !out) return fail(TACCHI_E_ARG, "NULL argument");
+    if (res < 1 || res > 4096) return fail(TACCHI_E_ARG, "res must be in [1, 4096]");
+    if (s->d.n[0] < 2 || s->d.n[1] < 2) return fail(TACCHI_E_ARG, "the top layer needs at least 2 x 2 particles");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    if (on_device)
+        return s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, out)
+                                              : surface_disp_t<float>(s, res, out);
+    const size_t bytes = (size_t)res * res * 3 * sizeof(float);
+    float *dst = nullptr;
+    TC_HIP(hipMallocAsync((void **)&dst, bytes, s->stream));
+    st = s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, dst) : surface_disp_t<float>(s, res, dst);
+    hipError_t e = st ? hipSuccess : hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, s->stream);
+    const hipError_t ef = hipFreeAsync(dst, s->stream);
+    const hipError_t es = hipStreamSynchronize(s->stream);
+    if (st) return st;
+    if (e != hipSuccess || ef != hipSuccess || es != hipSuccess)
+        return fail(TACCHI_E_DEVICE, "tacchi_surface_displacement: copy failed");
+    return read_error_word(s);
+}
+
+tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res,
+                                  double clip, float *out, void *hip_stream)
+{
+    if (!cfgs || !poses || !out || n < 1 || res < 1 || res > 4096 || !(clip > 0.0) || !std::isfinite(clip))
+        return fail(TACCHI_E_ARG, "tacchi_indenter_gap: bad arguments");
+    std::vector<GapDev> q((size_t)n);
+    for (int k = 0; k < n; ++k) {
+        const tacchi_config &c = cfgs[k];
+        if (c.ind.shape < TACCHI_SPHERE || c.ind.shape > TACCHI_TEXTURED_PLATE)
+            return fail(TACCHI_E_ARG, "unknown indenter shape");
+        double pose[7];
+        for (int a = 0; a < 3; ++a) pose[a] = poses[k].pos[a];
+        for (int a = 0; a < 4; ++a) pose[3 + a] = poses[k].quat[a];
+        const double qn = std::sqrt(pose[3] * pose[3] + pose[4] * pose[4] + pose[5] * pose[5] + pose[6] * pose[6]);
+        if (!(qn > 0.5) || !(qn < 2.0)) return fail(TACCHI_E_ARG, "pose quaternion is not unit");
+        q[k].I = make_indenter<double>(c, pose, pose, 1.0);
+        for (int a = 0; a < 3; ++a) q[k].pos[a] = pose[a];
+        q[k].x0 = c.block.origin[0];
+        q[k].y0 = c.block.origin[1];
+        q[k].wx = c.block.size[0];
+        q[k].wy = c.block.size[1];
+        q[k].ztop = c.block.origin[2] + c.block.size[2];
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    GapDev *dq = nullptr;
+    TC_HIP(hipMallocAsync((void **)&dq, q.size() * sizeof(GapDev), st));
+    hipError_t e = hipMemcpyAsync(dq, q.data(), q.size() * sizeof(GapDev), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_indenter_gap, dim3(grid1d((int64_t)n * res * res)), dim3(kWG), 0, st, dq, n, res, clip,
+                           out);
+        e = hipGetLastError();
+    }
+    const hipError_t ef = hipFreeAsync(dq, st);
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e != hipSuccess || ef != hipSuccess || es != hipSuccess)
+        return fail(TACCHI_E_DEVICE, std::string("tacchi_indenter_gap: ") +
+                                         hipGetErrorString(e != hipSuccess ? e : (ef != hipSuccess ? ef : es)));
+    return TACCHI_OK;
 }
 
 tacchi_status tacchi_render(tacchi_sim *s, const tacchi_render_params *rp, float *rgb, int32_t h, int32_t w,

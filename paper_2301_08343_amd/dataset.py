@@ -1,0 +1,74 @@
+"""Training data of the tactile surrogate, produced by the batched MPM.
+
+A sample is one GelSight-sized contact (indenter family, shape parameters,
+position and depth drawn from its seed) solved at lattice spacing h:
+  input  x[res][res][2]: the gap between the indenter at its final pose and
+         the undeformed top face (clipped to +-GAP_CLIP), and the press
+         depth broadcast, both in mm;
+  target y[res][res][3]: the top surface's displacement (ux, uy, uz) after
+         the press, in units of Y_UNIT.
+All of it is computed by the library (gap field kernel, batched substeps,
+displacement resampling kernel); this module only batches the calls.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import workloads as W
+from .batch import Batch
+from .sim import indenter_gap
+
+GAP_CLIP = 2e-3   # m
+X_UNIT = 1e-3     # inputs in mm
+Y_UNIT = 1e-4     # targets in 0.1 mm
+RES = 64
+H_DATA = 0.2e-3   # lattice spacing of the training solves
+
+
+def contacts_for(seeds, h=H_DATA):
+    return [W.gelsight_contact_at(int(s), h) for s in seeds]
+
+
+def inputs(contacts, res=RES, device="cuda") -> torch.Tensor:
+    """[n][res][res][2] float32 surrogate inputs (gap, depth) in mm."""
+    gap = indenter_gap([c["cfg"] for c in contacts], [c["poses"][-1] for c in contacts], res, GAP_CLIP, device)
+    x = torch.empty(len(contacts), res, res, 2, dtype=torch.float32, device=device)
+    x[..., 0] = gap / X_UNIT
+    x[..., 1] = torch.tensor([c["depth"] / X_UNIT for c in contacts], dtype=torch.float32,
+                             device=device).view(-1, 1, 1)
+    return x
+
+
+def solve(contacts, res=RES, tune_cache=None, device="cuda") -> torch.Tensor:
+    """Run every contact's full press with the batched MPM and return the
+    [n][res][res][3] top-surface displacement in Y_UNIT (float32)."""
+    steps = contacts[0]["steps"]
+    if any(c["steps"] != steps for c in contacts):
+        raise ValueError("contacts of one batch must share their substep count")
+    b = Batch(contacts, steps, tune_cache=tune_cache, device=device)
+    try:
+        b.run(steps)
+        u = b.surface_displacement(res)
+    finally:
+        b.close()
+    return u / Y_UNIT
+
+
+def generate(seeds, res=RES, h=H_DATA, batch=128, device="cuda", log=print):
+    """(x, y) device tensors for the given seeds, solved `batch` at a time."""
+    seeds = list(seeds)
+    xs, ys = [], []
+    t0 = time.perf_counter()
+    for k in range(0, len(seeds), batch):
+        cs = contacts_for(seeds[k:k + batch], h)
+        xs.append(inputs(cs, res, device))
+        ys.append(solve(cs, res, device=device))
+        if log:
+            done = k + len(cs)
+            el = time.perf_counter() - t0
+            ps = sum(c["particles"] * c["steps"] for c in cs)
+            log(f"data: {done}/{len(seeds)} samples, {el:.1f} s, last batch {ps:.3e} particle-substeps")
+    return torch.cat(xs), torch.cat(ys)
+

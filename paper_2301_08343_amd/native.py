@@ -27,6 +27,7 @@ EXPORTS = (
     "tacchi_timing_enable", "tacchi_timing_read", "tacchi_polar_fallbacks",
     "tacchi_batch_workspace_bytes", "tacchi_batch_create", "tacchi_batch_run", "tacchi_batch_contact",
     "tacchi_batch_tuning", "tacchi_batch_substeps_done", "tacchi_batch_sync", "tacchi_batch_destroy",
+    "tacchi_surface_displacement", "tacchi_indenter_gap", "tacchi_batch_surface_displacement",
 )
 NUM_KERNEL_CLASSES = 6
 KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
@@ -144,6 +145,13 @@ def lib():
         L.tacchi_batch_sync.argtypes = [_vp]
         L.tacchi_batch_destroy.restype = None
         L.tacchi_batch_destroy.argtypes = [_vp]
+        L.tacchi_surface_displacement.restype = ctypes.c_int32
+        L.tacchi_surface_displacement.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32]
+        L.tacchi_indenter_gap.restype = ctypes.c_int32
+        L.tacchi_indenter_gap.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(Pose), ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_double, _vp, _vp]
+        L.tacchi_batch_surface_displacement.restype = ctypes.c_int32
+        L.tacchi_batch_surface_displacement.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32]
         L.tacchi_last_error.restype = ctypes.c_char_p
         L.tacchi_last_error.argtypes = []
         _lib = L
@@ -174,6 +182,8 @@ _TSG_SIGS = {
     "tsg_adamw": (_i32, [_vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _f32, _i32, _vp]),
     "tsg_to_bf16": (_i32, [_vp, _i32, _i32, _vp, _i32, _vp]),
     "tsg_nn_dist": (_i32, [_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp]),
+    "tsg_features": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _f32, _vp, _vp]),
+    "tsg_channel_mse": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp]),
     "tsg_last_error": (ctypes.c_char_p, []),
 }
 TSG_EXPORTS = tuple(_TSG_SIGS)

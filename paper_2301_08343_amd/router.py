@@ -1,0 +1,161 @@
+"""Query router: the surrogate answers, the batched MPM checks and falls back.
+
+Each query is a contact (indenter, pose, depth). Per batch of queries:
+  1. the gap field kernel builds the surrogate inputs and the surrogate
+     predicts the surface displacement;
+  2. the out-of-distribution score is the distance from the query's feature
+     vector (4 x 4 box means of the gap field in mm, i.e. 16 x 16 values,
+     and the depth in mm) to its nearest training sample; queries above the
+     threshold (the 99.5th percentile of the held-out samples' scores) go to
+     the MPM;
+  3. a seeded 2% audit sends further queries to the MPM, where the surrogate's
+     height error is measured against the MPM's answer;
+  4. a circuit breaker routes every later query to the MPM once the RMSE of
+     the most recent audits exceeds the limit (5 um by default);
+  5. the MPM answers every query sent to it; the rest keep the surrogate's.
+Latency of a query = its batch's start -> its answer ready (all queries are
+queued at time zero and batches run back to back).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import dataset as D
+from . import native
+from .surrogate import Net
+from .training import per_sample_rmse
+from .workloads import SplitMix64
+
+FEAT_POOL = 4
+
+
+def features(x, depth_scale=1.0) -> torch.Tensor:
+    """[n][(res/4)^2 + 1] router features of surrogate inputs x [n][res][res][2]."""
+    n, res = x.shape[0], x.shape[1]
+    gap = x[..., 0].contiguous()
+    depth = x[:, 0, 0, 1].contiguous()
+    out = torch.empty(n, (res // FEAT_POOL) ** 2 + 1, dtype=torch.float32, device=x.device)
+    native.tsg_call("tsg_features", gap.data_ptr(), n, res, res, FEAT_POOL, depth.data_ptr(), depth_scale,
+                    out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return out
+
+
+def nn_distance(q, ref):
+    d2 = torch.empty(q.shape[0], dtype=torch.float32, device=q.device)
+    idx = torch.empty(q.shape[0], dtype=torch.int32, device=q.device)
+    native.tsg_call("tsg_nn_dist", q.data_ptr(), q.shape[0], ref.data_ptr(), ref.shape[0], q.shape[1],
+                    d2.data_ptr(), idx.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return d2.sqrt(), idx
+
+
+def audit_draws(n, rate, seed):
+    """Query k is audited when the k-th SplitMix64 output of `seed` is below rate * 2^64."""
+    rng = SplitMix64(seed)
+    lim = int(rate * 2.0 ** 64)
+    return np.array([rng.next_u64() < lim for _ in range(n)], dtype=bool)
+
+
+class Router:
+    def __init__(self, net: Net, train_features, threshold, audit_rate=0.02, audit_seed=7, rmse_limit_um=5.0,
+                 window=20):
+        self.net = net
+        self.train_features = train_features.contiguous()
+        self.threshold = float(threshold)
+        self.audit_rate = audit_rate
+        self.audit_seed = audit_seed
+        self.rmse_limit_um = rmse_limit_um
+        self.window = window
+
+    @staticmethod
+    def calibrate(train_features, heldout_features, q=0.995):
+        d, _ = nn_distance(heldout_features.contiguous(), train_features.contiguous())
+        return float(torch.quantile(d.cpu(), q))
+
+    def serve(self, contacts, batch=512, log=None):
+        """Answer every contact; returns (answers [n][res][res][3] in Y_UNIT, report dict)."""
+        n = len(contacts)
+        audit = audit_draws(n, self.audit_rate, self.audit_seed)
+        answers = torch.empty(n, D.RES, D.RES, 3, dtype=torch.float32, device="cuda")
+        lat = np.zeros(n)
+        route = np.zeros(n, dtype=np.int8)  # 0 surrogate, 1 ood, 2 audit, 3 breaker
+        audits_sq = []
+        tripped = False
+        n_mpm = 0
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for k0 in range(0, n, batch):
+            cs = contacts[k0:k0 + batch]
+            m = len(cs)
+            t0 = time.perf_counter()
+            x = D.inputs(cs)
+            pred = self.net.forward(x).clone() if not tripped else None
+            if tripped:
+                send = np.ones(m, dtype=bool)
+                route[k0:k0 + m] = 3
+            else:
+                d, _ = nn_distance(features(x), self.train_features)
+                ood = (d > self.threshold).cpu().numpy()
+                aud = audit[k0:k0 + m]
+                send = ood | aud
+                route[k0:k0 + m][ood] = 1
+                route[k0:k0 + m][aud & ~ood] = 2
+                answers[k0:k0 + m] = pred
+            torch.cuda.synchronize()
+            t_sur = time.perf_counter()
+            lat[k0:k0 + m] = t_sur - t0
+            idx = np.nonzero(send)[0]
+            if len(idx):
+                ym = D.solve([cs[i] for i in idx])
+                n_mpm += len(idx)
+                it = torch.tensor(idx, device="cuda")
+                if not tripped:
+                    aud_idx = [j for j, i in enumerate(idx) if route[k0 + i] == 2]
+                    if aud_idx:
+                        ai = torch.tensor(aud_idx, device="cuda")
+                        e = per_sample_rmse(pred.index_select(0, it.index_select(0, ai)), ym.index_select(0, ai), 2)
+                        audits_sq += [float(v) ** 2 for v in (e * D.Y_UNIT * 1e6).cpu()]
+                answers.index_copy_(0, it + k0, ym)
+                torch.cuda.synchronize()
+                lat[k0 + idx] = time.perf_counter() - t0
+            recent = audits_sq[-self.window:]
+            if not tripped and recent and math.sqrt(sum(recent) / len(recent)) > self.rmse_limit_um:
+                tripped = True
+            if log:
+                log(f"router: {k0 + m}/{n} answered, {n_mpm} by MPM, tripped={tripped}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_all
+        audited = math.sqrt(sum(audits_sq) / len(audits_sq)) if audits_sq else float("nan")
+        rep = {
+            "queries": n, "wall_s": wall, "frames_per_s": n / wall,
+            "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mpm_fallbacks": int(n_mpm), "ood": int((route == 1).sum()), "audited": int((route == 2).sum()),
+            "breaker_routed": int((route == 3).sum()), "breaker_tripped": tripped,
+            "audited_height_rmse_um": audited,
+        }
+        return answers, rep
+
+
+def plain_mpm(contacts, batch=512, log=None):
+    """Answer every contact with the batched MPM alone; (answers, report)."""
+    n = len(contacts)
+    lat = np.zeros(n)
+    outs = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for k0 in range(0, n, batch):
+        cs = contacts[k0:k0 + batch]
+        t0 = time.perf_counter()
+        outs.append(D.solve(cs))
+        torch.cuda.synchronize()
+        lat[k0:k0 + len(cs)] = time.perf_counter() - t0
+        if log:
+            log(f"plain MPM: {k0 + len(cs)}/{n} answered")
+    wall = time.perf_counter() - t_all
+    return torch.cat(outs), {"queries": n, "wall_s": wall, "frames_per_s": n / wall,
+                             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+                             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3)}

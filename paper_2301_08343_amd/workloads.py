@@ -103,11 +103,11 @@ def press_trajectory(start_pos, quat, depth, steps):
     (tip touching the top face) to `depth` below it; returns [steps+1][7] poses
     (x, y, z, qw, qx, qy, qz)."""
     poses = np.zeros((steps + 1, 7))
-    for k in range(steps + 1):
-        poses[k, 0] = start_pos[0]
-        poses[k, 1] = start_pos[1]
-        poses[k, 2] = start_pos[2] - depth * k / steps
-        poses[k, 3:] = quat
+    k = np.arange(steps + 1, dtype=np.float64)
+    poses[:, 0] = start_pos[0]
+    poses[:, 1] = start_pos[1]
+    poses[:, 2] = start_pos[2] - depth * k / steps
+    poses[:, 3:] = quat
     return poses
 
 
@@ -194,6 +194,37 @@ def gelsight_contact(seed: int = 0, steps: int = 2000, scale: int = 1):
     return dict(name=f"gelsight_{SHAPE_NAMES[family]}", cfg=cfg, dt=dt, steps=steps,
                 poses=poses, depth=depth,
                 render=default_render(nxy * dx / w, h, w))
+
+
+def gelsight_contact_at(seed: int, h: float = 0.2e-3):
+    """The GelSight-sized contact of `seed` (the same indenter, position and
+    depth draws as gelsight_contact) on a lattice of spacing h with grid
+    spacing h: the 20 x 20 x 4 mm block in a 25.6 x 25.6 x 6.4 mm grid (at
+    least 9 nodes taller than the block), bottom face 3 nodes above the grid
+    floor, 2000 (0.1 mm / h) substeps of
+    dt = 4 ms / substeps, so the press lasts 4 ms as at 0.1 mm."""
+    rng = SplitMix64(0x6E15 + seed)
+    family = seed % 5
+    sp = draw_indenter(rng, family)
+    nxy = int(round(20e-3 / h))
+    nz = int(round(4e-3 / h))
+    gxy = int(round(25.6e-3 / h))
+    gz = max(int(round(6.4e-3 / h)), nz + 9)
+    origin_xy = round((0.5 * (gxy - 1) * h - 0.5 * nxy * h) / h) * h
+    cfg = _contact(block_origin=(origin_xy, origin_xy, 3 * h),
+                   block_size=(nxy * h, nxy * h, nz * h), n=(nxy, nxy, nz),
+                   grid_origin=(0.0, 0.0, 0.0), dx=h, gn=(gxy, gxy, gz),
+                   E=0.15e6, nu=0.45, rho=1000.0, model=NEOHOOKEAN,
+                   shape=family, sp=sp, seed=seed)
+    cx, cy = block_center_xy(cfg)
+    cx += rng.uniform(-3e-3, 3e-3)
+    cy += rng.uniform(-3e-3, 3e-3)
+    depth = rng.uniform(0.2e-3, 1.5e-3)
+    steps = int(round(2000 * 0.1e-3 / h))
+    dt = 4e-3 / steps
+    poses = press_trajectory((cx, cy, top_z(cfg)), IDENTITY_QUAT, depth, steps)
+    return dict(name=f"gelsight_{SHAPE_NAMES[family]}_h{h * 1e3:.2f}mm", cfg=cfg, dt=dt, steps=steps,
+                poses=poses, depth=depth, particles=nxy * nxy * nz)
 
 
 def batch_contact(seed: int, steps: int = 2000):

@@ -564,3 +564,86 @@ def test_render_plane_and_paraboloid_normals(oracle_lib):
             N = np.array([2 * A * (xs[u] - cx), 2 * B * (ys[v] - cy), -1.0])
             N /= np.linalg.norm(N)
             np.testing.assert_allclose(img[v, u], _phong(N, rp), atol=1e-9)
+
+
+# ---------------------------------------------------------------- surrogate inputs and targets
+
+def _flat_cfg(shape, sp, n=(12, 10, 4), h=0.5e-3):
+    return W._contact(block_origin=(2e-3, 3e-3, 1e-3), block_size=(n[0] * h, n[1] * h, n[2] * h), n=n,
+                      grid_origin=(0, 0, 0), dx=h, gn=(n[0] + 12, n[1] + 14, n[2] + 10), E=1e5, nu=0.4,
+                      rho=1000.0, model=W.NEOHOOKEAN, shape=shape, sp=sp, seed=3)
+
+
+def test_gap_of_an_upright_sphere_is_its_lower_cap(oracle_lib):
+    R = 2e-3
+    cfg = _flat_cfg(W.SPHERE, [R])
+    ztop = cfg["block_origin"][2] + cfg["block_size"][2]
+    pose = (4.6e-3, 5.4e-3, ztop - 0.7e-3, 1.0, 0.0, 0.0, 0.0)
+    res, clip = 9, 1.5e-3
+    g = oracle_lib.indenter_gap(cfg, pose, res, clip)
+    for r in range(res):
+        for c in range(res):
+            x = cfg["block_origin"][0] + (c + 0.5) * cfg["block_size"][0] / res
+            y = cfg["block_origin"][1] + (r + 0.5) * cfg["block_size"][1] / res
+            rho2 = (x - pose[0]) ** 2 + (y - pose[1]) ** 2
+            exact = clip if rho2 >= R * R else pose[2] + R - math.sqrt(R * R - rho2) - ztop
+            assert abs(g[r, c] - min(max(exact, -clip), clip)) <= 1e-12
+
+
+def test_gap_of_a_tilted_punch_is_its_bottom_plane(oracle_lib):
+    R = 1.8e-3
+    cfg = _flat_cfg(W.CYLINDER, [R])
+    ztop = cfg["block_origin"][2] + cfg["block_size"][2]
+    q = W.quat_axis_angle((0.6, 0.8, 0.0), math.radians(4.0))
+    pose = (5.2e-3, 5.6e-3, ztop - 0.3e-3) + tuple(q)
+    # bottom face normal = third column of the rotation (indenter z axis in world)
+    w, x_, y_, z_ = q
+    nz = (2 * (x_ * z_ + w * y_), 2 * (y_ * z_ - w * x_), 1 - 2 * (x_ * x_ + y_ * y_))
+    res, clip = 10, 1.5e-3
+    g = oracle_lib.indenter_gap(cfg, pose, res, clip)
+    checked = 0
+    for r in range(res):
+        for c in range(res):
+            x = cfg["block_origin"][0] + (c + 0.5) * cfg["block_size"][0] / res
+            y = cfg["block_origin"][1] + (r + 0.5) * cfg["block_size"][1] / res
+            z = pose[2] - (nz[0] * (x - pose[0]) + nz[1] * (y - pose[1])) / nz[2]
+            d = np.array([x - pose[0], y - pose[1], z - pose[2]])
+            radial = np.linalg.norm(d - np.dot(d, nz) * np.array(nz))
+            if radial < 0.95 * R:
+                assert abs(g[r, c] - (z - ztop)) <= 1e-12
+                checked += 1
+            elif radial > 1.05 * R and abs(d[2]) < 1e-3:
+                assert g[r, c] > z - ztop + 1e-6  # outside the punch the line meets its side wall higher up
+    assert checked >= 6
+
+
+def test_surface_displacement_reproduces_affine_fields(oracle_lib):
+    cfg = _flat_cfg(W.SPHERE, [1e-3], n=(9, 7, 3))
+    n0, n1, n2 = cfg["n"]
+    h = [cfg["block_size"][a] / cfg["n"][a] for a in range(3)]
+    o = cfg["block_origin"]
+    kk, jj, ii = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
+    X = np.stack([o[0] + (ii + 0.5) * h[0], o[1] + (jj + 0.5) * h[1], o[2] + (kk + 0.5) * h[2]], -1).reshape(-1, 3)
+    A = np.array([[1e-3, -2e-3, 0.5e-3], [3e-3, 1e-3, -1e-3], [-2e-3, 4e-3, 2e-3]])
+    b = np.array([1e-5, -3e-5, -2e-4])
+    x = X + X @ A.T + b
+    res = 5
+    u = oracle_lib.surface_displacement(cfg, x, res)
+    ztop = o[2] + (n2 - 0.5) * h[2]
+    for r in range(res):
+        for c in range(res):
+            P = np.array([o[0] + (c + 0.5) * cfg["block_size"][0] / res,
+                          o[1] + (r + 0.5) * cfg["block_size"][1] / res, ztop])
+            # every sample of a 5 x 5 partition of 9 x 7 particles lies inside the lattice hull
+            assert np.abs(u[r, c] - (A @ P + b)).max() <= 1e-15
+    # on a square lattice at res = n0 the samples are the top particles themselves (row r = j, column c = i)
+    cfg8 = _flat_cfg(W.SPHERE, [1e-3], n=(8, 8, 3))
+    rng = np.random.default_rng(5)
+    o8 = cfg8["block_origin"]
+    h8 = cfg8["block_size"][0] / 8
+    kk, jj, ii = np.meshgrid(np.arange(3), np.arange(8), np.arange(8), indexing="ij")
+    X8 = np.stack([o8[0] + (ii + 0.5) * h8, o8[1] + (jj + 0.5) * h8, o8[2] + (kk + 0.5) * h8], -1).reshape(-1, 3)
+    d8 = rng.standard_normal(X8.shape) * 1e-5
+    u8 = oracle_lib.surface_displacement(cfg8, X8 + d8, 8)
+    top = d8.reshape(3, 8, 8, 3)[2]
+    assert np.abs(u8 - top).max() <= 1e-18

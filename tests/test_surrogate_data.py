@@ -1,0 +1,72 @@
+"""The surrogate's inputs and targets on the GPU against the oracle: the
+indenter gap field over the top face and the resampled top-surface
+displacement of a simulated contact."""
+import numpy as np
+import pytest
+
+from paper_2301_08343_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_08343_amd import sim
+    return sim
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_gap_field_matches_oracle(oracle_lib, gpu, seed):
+    """All five indenter families, upright (GelSight draws) and tilted (batch draws)."""
+    c = W.gelsight_contact(seed, steps=20) if seed < 5 else W.batch_contact(seed, steps=20)
+    cfg, pose = c["cfg"], c["poses"][-1]
+    res, clip = 16, 2e-3
+    got = gpu.indenter_gap([cfg], [pose], res, clip)[0].cpu().double().numpy()
+    ref = oracle_lib.indenter_gap(cfg, pose, res, clip)
+    # the kernel brackets the crossing to 2 clip / 512 / 2^40 and rounds to FP32
+    err = np.abs(got - ref)
+    print(f"seed {seed} shape {cfg['shape']}: max |d gap| = {err.max():.3e} m, min gap {ref.min():.3e}")
+    assert np.all(err <= 1e-9 + 2.0 ** -24 * np.abs(ref))
+    assert ref.min() < clip  # the indenter is seen over the face
+
+
+def test_gap_field_batches_many_contacts(oracle_lib, gpu):
+    cs = [W.gelsight_contact(s, steps=10) for s in range(20, 26)]
+    got = gpu.indenter_gap([c["cfg"] for c in cs], [c["poses"][-1] for c in cs], 8, 1.5e-3).cpu().double().numpy()
+    for k, c in enumerate(cs):
+        ref = oracle_lib.indenter_gap(c["cfg"], c["poses"][-1], 8, 1.5e-3)
+        assert np.all(np.abs(got[k] - ref) <= 1e-9 + 2.0 ** -24 * np.abs(ref))
+
+
+def test_surface_displacement_matches_oracle(oracle_lib, gpu):
+    c = W.small_sphere_contact(1, steps=150)
+    S = 150
+    sim = gpu.Sim(c["cfg"], c["poses"][0], precision="f64")
+    sim.run(c["poses"][1:S + 1], c["dt"])
+    orc = oracle_lib.OracleSim(c["cfg"], c["poses"][0])
+    orc.run(c["poses"], c["dt"], 0, S)
+    for res in (7, 48, 64):
+        got = sim.surface_displacement(res).cpu().double().numpy()
+        ref = oracle_lib.surface_displacement(c["cfg"], orc.particles()[0], res)
+        err = np.abs(got - ref).max()
+        print(f"res {res}: max |du| = {err:.3e} m, max |u| = {np.abs(ref).max():.3e} m")
+        # FP64 trajectories agree to ~1e-16 m; the output is FP32
+        assert np.all(np.abs(got - ref) <= 1e-12 + 2.0 ** -24 * np.abs(ref))
+    assert np.abs(ref[..., 2]).max() > 1e-5
+
+
+def test_batch_surface_displacement_equals_per_contact(gpu):
+    from paper_2301_08343_amd.batch import Batch
+    S = 60
+    contacts = [W.batch_contact(seed, steps=S) for seed in (3, 4, 5)]
+    b = Batch(contacts, S)
+    b.run(S)
+    b.sync()
+    all_u = b.surface_displacement(32)
+    for i in range(3):
+        one = b.contact(i).surface_displacement(32)
+        torch.cuda.synchronize()
+        assert torch.equal(all_u[i], one)
