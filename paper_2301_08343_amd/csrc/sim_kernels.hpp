@@ -88,7 +88,10 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     using Acc = TileAcc<T>;
     using Slot = typename Acc::Slot;
     constexpr int TB = B + 3, TN = TB * TB * TB;
-    __shared__ Slot tile[4 * TN];
+    // LDS rows padded to 12 nodes for B = 8: the 8 x 8 particle patch of a
+    // wave then hits every bank the same number of times in each atomic
+    constexpr int PX = B == 8 ? 12 : TB, TL = TB * TB * PX;
+    __shared__ Slot tile[4 * TL];
     // the next substep's bin counts start from zero; the force of the coming
     // grid update too
     if (threadIdx.x == 0) S.cnt_next[b] = 0;
@@ -97,7 +100,7 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     const int count = min(S.cnt_cur[b], S.cap);
     if (count == 0) return;
     const int *plist = S.perm_cur + (int64_t)b * S.cap;
-    for (int i = threadIdx.x; i < 4 * TN; i += WG) tile[i] = Slot(0);
+    for (int i = threadIdx.x; i < 4 * TL; i += WG) tile[i] = Slot(0);
     __syncthreads();
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
@@ -172,11 +175,11 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const T wt = wab * wz[c];
-                    const int li = ((l2 + c) * TB + (l1 + bb)) * TB + (l0 + a);
+                    const int li = ((l2 + c) * TB + (l1 + bb)) * PX + (l0 + a);
                     Acc::add(&tile[li], wt * m);
-                    Acc::add(&tile[TN + li], wt * (qa[0] + Am[2] * T(c)));
-                    Acc::add(&tile[2 * TN + li], wt * (qa[1] + Am[5] * T(c)));
-                    Acc::add(&tile[3 * TN + li], wt * (qa[2] + Am[8] * T(c)));
+                    Acc::add(&tile[TL + li], wt * (qa[0] + Am[2] * T(c)));
+                    Acc::add(&tile[2 * TL + li], wt * (qa[1] + Am[5] * T(c)));
+                    Acc::add(&tile[3 * TL + li], wt * (qa[2] + Am[8] * T(c)));
                 }
             }
     }
@@ -184,10 +187,11 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     T *dst = S.tiles + (int64_t)b * TN * 4;
     for (int li = threadIdx.x; li < TN; li += WG) {
         T *d = dst + 4 * li;
-        d[0] = Acc::value(tile[li]) * munit;
-        d[1] = Acc::value(tile[TN + li]) * punit;
-        d[2] = Acc::value(tile[2 * TN + li]) * punit;
-        d[3] = Acc::value(tile[3 * TN + li]) * punit;
+        const int row = li / TB, ls = row * PX + (li - row * TB);
+        d[0] = Acc::value(tile[ls]) * munit;
+        d[1] = Acc::value(tile[TL + ls]) * punit;
+        d[2] = Acc::value(tile[2 * TL + ls]) * punit;
+        d[3] = Acc::value(tile[3 * TL + ls]) * punit;
     }
 }
 
