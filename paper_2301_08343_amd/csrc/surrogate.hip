@@ -597,7 +597,7 @@ tsg_status tsg_pack_weights(const float *w, int32_t cout, int32_t cin, int32_t c
                             uint16_t *wf, uint16_t *wt, void *stream)
 {
     if (!w || cout < 1 || cin < 1 || cin_p < cin || cout_p < cout || (taps != 1 && taps != 9) || cin_p % 8 ||
-        cout_p % 8)
+        (wt && cout_p % 8))
         return fail(-1, "tsg_pack_weights: bad arguments");
     const int kf = tsg_pack_k(taps, cin_p), kt = tsg_pack_k(taps, cout_p);
     const int64_t n = std::max<int64_t>(wf ? (int64_t)cout * kf : 0, wt ? (int64_t)cin_p * kt : 0);

@@ -27,13 +27,19 @@ RES = 64
 H_DATA = 0.2e-3   # lattice spacing of the training solves
 
 
-def contacts_for(seeds, h=H_DATA):
-    return [W.gelsight_contact_at(int(s), h) for s in seeds]
+def contacts_for(seeds, h=H_DATA, full=True):
+    """Contacts of the given seeds; full=False leaves out the trajectories
+    (enough for the surrogate inputs; solve() rebuilds them)."""
+    return [W.gelsight_contact_at(int(s), h, full) for s in seeds]
+
+
+def _full(c):
+    return c if c["poses"] is not None else W.gelsight_contact_at(c["seed"], c["h"], True)
 
 
 def inputs(contacts, res=RES, device="cuda") -> torch.Tensor:
     """[n][res][res][2] float32 surrogate inputs (gap, depth) in mm."""
-    gap = indenter_gap([c["cfg"] for c in contacts], [c["poses"][-1] for c in contacts], res, GAP_CLIP, device)
+    gap = indenter_gap([c["cfg"] for c in contacts], [c["end_pose"] for c in contacts], res, GAP_CLIP, device)
     x = torch.empty(len(contacts), res, res, 2, dtype=torch.float32, device=device)
     x[..., 0] = gap / X_UNIT
     x[..., 1] = torch.tensor([c["depth"] / X_UNIT for c in contacts], dtype=torch.float32,
@@ -44,6 +50,7 @@ def inputs(contacts, res=RES, device="cuda") -> torch.Tensor:
 def solve(contacts, res=RES, tune_cache=None, device="cuda") -> torch.Tensor:
     """Run every contact's full press with the batched MPM and return the
     [n][res][res][3] top-surface displacement in Y_UNIT (float32)."""
+    contacts = [_full(c) for c in contacts]
     steps = contacts[0]["steps"]
     if any(c["steps"] != steps for c in contacts):
         raise ValueError("contacts of one batch must share their substep count")

@@ -38,6 +38,37 @@ def save(path, net: Net, train_feats, threshold, meta):
               metadata={k: json.dumps(v) for k, v in dict(meta, threshold=threshold).items()})
 
 
+def save_compact(path, net: Net, threshold, meta):
+    """Weights as bfloat16 (exactly what the kernels use) and biases as FP32:
+    a model loaded from it predicts bit for bit as the one saved."""
+    from safetensors.torch import save_file
+    ws, bs = [], []
+    for name, ci, co, t in net.specs:
+        w, b = net.param(name)
+        ws.append(w.detach().reshape(-1))
+        bs.append(b.detach())
+    save_file({"weights_bf16": torch.cat(ws).to(torch.bfloat16).cpu(), "biases": torch.cat(bs).cpu()}, path,
+              metadata={k: json.dumps(v) for k, v in dict(meta, threshold=threshold).items()})
+
+
+def load_compact(path, batch=512):
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        meta = {k: json.loads(v) for k, v in f.metadata().items()}
+        wb = f.get_tensor("weights_bf16").float()
+        bb = f.get_tensor("biases")
+    net = Net(batch=batch, res=meta["res"], enc=tuple(meta["enc"]), mid=meta["mid"])
+    ow = ob = 0
+    for name, ci, co, t in net.specs:
+        w, b = net.param(name)
+        w.copy_(wb[ow:ow + w.numel()].view_as(w))
+        b.copy_(bb[ob:ob + co])
+        ow += w.numel()
+        ob += co
+    net.repack()
+    return net, meta
+
+
 def load(path, batch=512):
     from safetensors import safe_open
     with safe_open(path, framework="pt") as f:
@@ -48,6 +79,34 @@ def load(path, batch=512):
     net.flat.copy_(flat)
     net.repack()
     return net, feats.cuda(), meta
+
+
+def train_features(n, h, chunk=2048):
+    """Router features of training seeds 0 .. n-1 (gap fields only, no solve)."""
+    out = []
+    for k in range(0, n, chunk):
+        out.append(RT.features(D.inputs(D.contacts_for(range(k, min(n, k + chunk)), h, full=False))))
+    return torch.cat(out)
+
+
+def serve_benchmark(net, ftr, thr, h, queries, plain_sample, log=log):
+    """The query stream through the router, and plain batched MPM on its first
+    `plain_sample` queries (whose answers also measure the served error)."""
+    rep = {}
+    qs = D.contacts_for(range(QUERY_SEED0, QUERY_SEED0 + queries), h, full=False)
+    r = RT.Router(net, ftr, thr)
+    ans, rrep = r.serve(qs, log=log)
+    rep["router"] = rrep
+    log(f"router: {json.dumps(rrep)}")
+    k = min(plain_sample, queries)
+    ymp, prep = RT.plain_mpm(qs[:k], log=log)
+    rep["plain_mpm"] = dict(prep, note=f"first {k} queries; frames/s extrapolates to the stream")
+    served = TR.per_sample_rmse(ans[:k], ymp, 2) * D.Y_UNIT * 1e6
+    rep["served_vs_mpm_height_rmse_um"] = float((served ** 2).mean().sqrt())
+    rep["speedup_frames_per_s"] = rrep["frames_per_s"] / prep["frames_per_s"]
+    log(f"plain MPM: {json.dumps(prep)}; served answers vs MPM: "
+        f"{rep['served_vs_mpm_height_rmse_um']:.2f} um; speedup {rep['speedup_frames_per_s']:.1f}x")
+    return rep
 
 
 def main(argv=None):
@@ -95,27 +154,17 @@ def main(argv=None):
     meta = {"res": net.res, "enc": list(net.enc), "mid": net.mid, "h_m": a.h, "train_samples": a.train,
             "y_unit_m": D.Y_UNIT, "x_unit_m": D.X_UNIT, "gap_clip_m": D.GAP_CLIP}
     save(os.path.join(a.out, "surrogate.safetensors"), net, ftr, thr, meta)
+    save_compact(os.path.join(a.out, "surrogate_compact.safetensors"), net, thr,
+                 dict(meta, heldout=rep["heldout"]))
     rep["router_threshold"] = thr
 
     if a.queries > 0:
         del xtr, ytr
         torch.cuda.empty_cache()
-        qs = D.contacts_for(range(QUERY_SEED0, QUERY_SEED0 + a.queries), a.h)
         serve_net = Net(batch=512, seed=0)
         serve_net.flat.copy_(net.flat)
         serve_net.repack()
-        r = RT.Router(serve_net, ftr, thr)
-        ans, rrep = r.serve(qs, log=log)
-        rep["router"] = rrep
-        log(f"router: {json.dumps(rrep)}")
-        k = min(a.plain_sample, a.queries)
-        ymp, prep = RT.plain_mpm(qs[:k], log=log)
-        rep["plain_mpm"] = dict(prep, note=f"first {k} queries; frames/s extrapolates to the stream")
-        served = TR.per_sample_rmse(ans[:k], ymp, 2) * D.Y_UNIT * 1e6
-        rep["served_vs_mpm_height_rmse_um"] = float((served ** 2).mean().sqrt())
-        rep["speedup_frames_per_s"] = rrep["frames_per_s"] / prep["frames_per_s"]
-        log(f"plain MPM: {json.dumps(prep)}; served answers vs MPM: "
-            f"{rep['served_vs_mpm_height_rmse_um']:.2f} um; speedup {rep['speedup_frames_per_s']:.1f}x")
+        rep.update(serve_benchmark(serve_net, ftr, thr, a.h, a.queries, a.plain_sample))
 
     with open(os.path.join(a.out, "report.json"), "w") as f:
         json.dump(rep, f, indent=1)

@@ -196,13 +196,15 @@ def gelsight_contact(seed: int = 0, steps: int = 2000, scale: int = 1):
                 render=default_render(nxy * dx / w, h, w))
 
 
-def gelsight_contact_at(seed: int, h: float = 0.2e-3):
+def gelsight_contact_at(seed: int, h: float = 0.2e-3, full: bool = True):
     """The GelSight-sized contact of `seed` (the same indenter, position and
     depth draws as gelsight_contact) on a lattice of spacing h with grid
     spacing h: the 20 x 20 x 4 mm block in a 25.6 x 25.6 x 6.4 mm grid (at
     least 9 nodes taller than the block), bottom face 3 nodes above the grid
     floor, 2000 (0.1 mm / h) substeps of
-    dt = 4 ms / substeps, so the press lasts 4 ms as at 0.1 mm."""
+    dt = 4 ms / substeps, so the press lasts 4 ms as at 0.1 mm. With
+    full=False the trajectory is left out (poses = None); `end_pose` is the
+    final pose either way."""
     rng = SplitMix64(0x6E15 + seed)
     family = seed % 5
     sp = draw_indenter(rng, family)
@@ -222,9 +224,11 @@ def gelsight_contact_at(seed: int, h: float = 0.2e-3):
     depth = rng.uniform(0.2e-3, 1.5e-3)
     steps = int(round(2000 * 0.1e-3 / h))
     dt = 4e-3 / steps
-    poses = press_trajectory((cx, cy, top_z(cfg)), IDENTITY_QUAT, depth, steps)
+    start = (cx, cy, top_z(cfg))
+    poses = press_trajectory(start, IDENTITY_QUAT, depth, steps) if full else None
+    end = np.array([cx, cy, start[2] - depth * float(steps) / steps, *IDENTITY_QUAT])
     return dict(name=f"gelsight_{SHAPE_NAMES[family]}_h{h * 1e3:.2f}mm", cfg=cfg, dt=dt, steps=steps,
-                poses=poses, depth=depth, particles=nxy * nxy * nz)
+                poses=poses, end_pose=end, depth=depth, particles=nxy * nxy * nz, seed=seed, h=h)
 
 
 def batch_contact(seed: int, steps: int = 2000):

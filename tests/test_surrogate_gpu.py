@@ -293,7 +293,9 @@ def test_adamw(T):
         gd = f32_dev(g)
         T.tsg_call("tsg_adamw", pd.data_ptr(), gd.data_ptr(), md.data_ptr(), vd.data_ptr(), n, 2e-3, 0.9, 0.999,
                    1e-8, 1e-2, step, stream())
-        p, m, v = R.adamw(p0, g, m0, v0, step, lr=2e-3)
+        # the hyperparameters are FP32 arguments: the reference takes their FP32 values
+        f = lambda a: float(np.float32(a))  # noqa: E731
+        p, m, v = R.adamw(p0, g, m0, v0, step, lr=f(2e-3), b1=f(0.9), b2=f(0.999), eps=f(1e-8), wd=f(1e-2))
         # a step moves p by about lr; FP32 arithmetic is off by a few ulps of p and of the step
         assert np.all(np.abs(host(pd) - p) <= 8 * 2.0 ** -23 * (np.abs(p) + 2e-3)), step
         assert np.all(np.abs(host(md) - m) <= 4 * 2.0 ** -23 * np.abs(m) + 1e-30)
@@ -404,3 +406,25 @@ def test_training_reduces_the_loss(T):
     last = float(last.item())
     print(f"loss {first:.4e} -> {last:.4e}")
     assert last < 0.1 * first
+
+
+def test_router_features_and_per_sample_mse(T):
+    rng = np.random.default_rng(121)
+    n, h, w, f = 3, 16, 12, 4
+    gap = rng.standard_normal((n, h, w)).astype(np.float32).astype(np.float64)
+    depth = rng.uniform(0.2, 1.5, n).astype(np.float32).astype(np.float64)
+    out = torch.zeros(n, (h // f) * (w // f) + 1, dtype=torch.float32, device="cuda")
+    T.tsg_call("tsg_features", f32_dev(gap).data_ptr(), n, h, w, f, f32_dev(depth).data_ptr(), 2.0, out.data_ptr(),
+               stream())
+    box = gap.reshape(n, h // f, f, w // f, f).mean(axis=(2, 4)).reshape(n, -1)
+    got = host(out)
+    assert np.all(np.abs(got[:, :-1] - box) <= 16 * U_32 * np.abs(gap).max())
+    assert np.array_equal(got[:, -1], (2.0 * depth).astype(np.float32).astype(np.float64))
+    a = rng.standard_normal((n, 50, 3)).astype(np.float32).astype(np.float64)
+    b = rng.standard_normal((n, 50, 3)).astype(np.float32).astype(np.float64)
+    mse = torch.zeros(n, dtype=torch.float32, device="cuda")
+    for ch in range(3):
+        T.tsg_call("tsg_channel_mse", f32_dev(a).data_ptr(), f32_dev(b).data_ptr(), n, 50, 3, ch, mse.data_ptr(),
+                   stream())
+        ref = ((a[..., ch] - b[..., ch]) ** 2).mean(axis=1)
+        assert np.all(np.abs(host(mse) - ref) <= 60 * U_32 * ref)
