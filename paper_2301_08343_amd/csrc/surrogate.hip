@@ -806,8 +806,9 @@ tsg_status tsg_adamw(float *p, const float *g, float *m, float *v, int64_t n, fl
                      float wd, int32_t step, void *stream)
 {
     if (!p || !g || !m || !v || n < 1 || step < 1) return fail(-1, "tsg_adamw: bad arguments");
-    const float bc1 = 1.0f - (float)std::pow((double)b1, (double)step);
-    const float bc2 = 1.0f - (float)std::pow((double)b2, (double)step);
+    // 1 - b^t in FP64 before rounding: b2^t is close to 1 for small t
+    const float bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
+    const float bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
     hipLaunchKernelGGL(k_adamw, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n, lr, b1, b2, eps,
                        wd, bc1, bc2);
     TSG_LAUNCHED();

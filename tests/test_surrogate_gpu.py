@@ -414,8 +414,8 @@ def test_router_features_and_per_sample_mse(T):
     gap = rng.standard_normal((n, h, w)).astype(np.float32).astype(np.float64)
     depth = rng.uniform(0.2, 1.5, n).astype(np.float32).astype(np.float64)
     out = torch.zeros(n, (h // f) * (w // f) + 1, dtype=torch.float32, device="cuda")
-    T.tsg_call("tsg_features", f32_dev(gap).data_ptr(), n, h, w, f, f32_dev(depth).data_ptr(), 2.0, out.data_ptr(),
-               stream())
+    gd, dd = f32_dev(gap), f32_dev(depth)  # held: a temporary's memory could be reused before the kernel runs
+    T.tsg_call("tsg_features", gd.data_ptr(), n, h, w, f, dd.data_ptr(), 2.0, out.data_ptr(), stream())
     box = gap.reshape(n, h // f, f, w // f, f).mean(axis=(2, 4)).reshape(n, -1)
     got = host(out)
     assert np.all(np.abs(got[:, :-1] - box) <= 16 * U_32 * np.abs(gap).max())
@@ -423,8 +423,8 @@ def test_router_features_and_per_sample_mse(T):
     a = rng.standard_normal((n, 50, 3)).astype(np.float32).astype(np.float64)
     b = rng.standard_normal((n, 50, 3)).astype(np.float32).astype(np.float64)
     mse = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ad, bd = f32_dev(a), f32_dev(b)
     for ch in range(3):
-        T.tsg_call("tsg_channel_mse", f32_dev(a).data_ptr(), f32_dev(b).data_ptr(), n, 50, 3, ch, mse.data_ptr(),
-                   stream())
+        T.tsg_call("tsg_channel_mse", ad.data_ptr(), bd.data_ptr(), n, 50, 3, ch, mse.data_ptr(), stream())
         ref = ((a[..., ch] - b[..., ch]) ** 2).mean(axis=1)
         assert np.all(np.abs(host(mse) - ref) <= 60 * U_32 * ref)
