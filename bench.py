@@ -46,7 +46,52 @@ def parse():
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--surrogate", default=os.path.join(ROOT, "paper_2301_08343_amd", "weights",
+                                                        "surrogate_h0.2mm.safetensors"),
+                    help="trained surrogate; its query-stream leg runs when the file exists")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--queries", type=int, default=10000)
+    ap.add_argument("--plain-sample", type=int, default=512)
     return ap.parse_args()
+
+
+def surrogate_leg(args):
+    """Contact-query stream through the trained surrogate and its router vs
+    plain batched MPM (run after the timed MPM frames)."""
+    import torch
+    from paper_2301_08343_amd import surrogate_pipeline as SP
+    from paper_2301_08343_amd.surrogate import forward_flops
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    net, meta = SP.load_compact(args.surrogate, batch=512)
+    x = torch.zeros(512, meta["res"], meta["res"], 2, dtype=torch.float32, device="cuda")
+    net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    inf_s = (time.perf_counter() - t0) / reps
+    ftr = SP.train_features(meta["train_samples"], meta["h_m"])
+    rep = SP.serve_benchmark(net, ftr, meta["threshold"], meta["h_m"], args.queries, args.plain_sample, log=log)
+    r, p = rep["router"], rep["plain_mpm"]
+    return {"metric": "tactile frames/s, surrogate + MPM fallback vs plain batched MPM",
+            "frames_per_s": r["frames_per_s"], "plain_mpm_frames_per_s": p["frames_per_s"],
+            "speedup": rep["speedup_frames_per_s"],
+            "latency_p50_ms": r["latency_p50_ms"], "latency_p99_ms": r["latency_p99_ms"],
+            "plain_mpm_latency_p50_ms": p["latency_p50_ms"], "plain_mpm_latency_p99_ms": p["latency_p99_ms"],
+            "audited_height_rmse_um": r["audited_height_rmse_um"],
+            "served_vs_mpm_height_rmse_um": rep["served_vs_mpm_height_rmse_um"],
+            "heldout_height_rmse_um": meta.get("heldout", {}).get("height_rmse_um"),
+            "queries": r["queries"], "mpm_fallbacks": r["mpm_fallbacks"], "ood": r["ood"],
+            "audited": r["audited"], "breaker_tripped": r["breaker_tripped"],
+            "inference_frames_per_s": 512 / inf_s,
+            "inference_tflops": 512 * forward_flops(meta["res"]) / inf_s / 1e12,
+            "plain_mpm_sample": p["queries"], "data_h_m": meta["h_m"], "train_samples": meta["train_samples"],
+            "dtype": "bf16 storage, fp32 accumulation"}
 
 
 def cpu_baseline(wl, budget_s):
@@ -163,6 +208,10 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl_cpu, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_surrogate and os.path.exists(args.surrogate):
+        out["surrogate"] = surrogate_leg(args)
     print(json.dumps(out), flush=True)
 
 

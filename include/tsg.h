@@ -145,6 +145,16 @@ tsg_status tsg_features(const float *gap, int32_t n, int32_t h, int32_t w, int32
 tsg_status tsg_channel_mse(const float *a, const float *b, int32_t n, int32_t npix, int32_t c, int32_t ch,
                            float *out, void *stream);
 
+/* Symmetry copies of n samples (x [n][res][res][2], y [n][res][res][3], fp32,
+ * row = y index, column = x index): sample k is transformed by ops[k] (device
+ * int32): bit 2 transposes x <-> y, bit 0 mirrors x, bit 1 mirrors y, applied
+ * in that order; the target's (ux, uy) components are turned with the field
+ * (swapped by the transpose, negated by the mirror of their axis). Outputs
+ * must not alias the inputs. The elastomer block, its lattice and grid are
+ * symmetric under these eight maps, so each copy is again a valid sample. */
+tsg_status tsg_augment(const float *x, const float *y, int32_t n, int32_t res, const int32_t *ops, float *x_out,
+                       float *y_out, void *stream);
+
 const char *tsg_last_error(void);
 
 #ifdef __cplusplus

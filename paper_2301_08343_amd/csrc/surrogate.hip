@@ -579,6 +579,41 @@ __global__ void __launch_bounds__(256) k_channel_mse(const float *a, const float
     if (threadIdx.x == 0) out[k] = red[0] / (float)npix;
 }
 
+// Symmetry copies of surrogate samples: op bit 2 transposes (x <-> y), bit 0
+// mirrors x, bit 1 mirrors y, applied to the field in that order; vector
+// channels (ux, uy) of the target turn with it. One thread per output pixel.
+__global__ void k_augment(const float *x, const float *y, int n, int res, const int *ops, float *xo, float *yo)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * res * res) return;
+    const int k = (int)(idx / ((int64_t)res * res));
+    const int rem = (int)(idx - (int64_t)k * res * res);
+    const int r = rem / res, c = rem - r * res;  // output row (y) and column (x)
+    const int op = ops[k];
+    int sx = c, sy = r;
+    if (op & 2) sy = res - 1 - sy;
+    if (op & 1) sx = res - 1 - sx;
+    if (op & 4) {
+        const int t = sx;
+        sx = sy;
+        sy = t;
+    }
+    const int64_t src = ((int64_t)k * res + sy) * res + sx;
+    xo[idx * 2 + 0] = x[src * 2 + 0];
+    xo[idx * 2 + 1] = x[src * 2 + 1];
+    float ux = y[src * 3 + 0], uy = y[src * 3 + 1];
+    if (op & 4) {
+        const float t = ux;
+        ux = uy;
+        uy = t;
+    }
+    if (op & 1) ux = -ux;
+    if (op & 2) uy = -uy;
+    yo[idx * 3 + 0] = ux;
+    yo[idx * 3 + 1] = uy;
+    yo[idx * 3 + 2] = y[src * 3 + 2];
+}
+
 unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -850,6 +885,17 @@ tsg_status tsg_channel_mse(const float *a, const float *b, int32_t n, int32_t np
     if (!a || !b || !out || n < 1 || npix < 1 || c < 1 || ch < 0 || ch >= c)
         return fail(-1, "tsg_channel_mse: bad arguments");
     hipLaunchKernelGGL(k_channel_mse, dim3(n), dim3(256), 0, (hipStream_t)stream, a, b, npix, c, ch, out);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_augment(const float *x, const float *y, int32_t n, int32_t res, const int32_t *ops, float *x_out,
+                       float *y_out, void *stream)
+{
+    if (!x || !y || !ops || !x_out || !y_out || n < 1 || res < 1 || x == x_out || y == y_out)
+        return fail(-1, "tsg_augment: bad arguments");
+    hipLaunchKernelGGL(k_augment, dim3(blocks_for((int64_t)n * res * res)), dim3(256), 0, (hipStream_t)stream, x, y, n,
+                       res, ops, x_out, y_out);
     TSG_LAUNCHED();
     return 0;
 }

@@ -120,6 +120,7 @@ def main(argv=None):
     ap.add_argument("--plain-sample", type=int, default=512)
     ap.add_argument("--h", type=float, default=D.H_DATA)
     ap.add_argument("--gen-batch", type=int, default=256)
+    ap.add_argument("--no-symmetry", action="store_true", help="train without the mirror/transpose copies")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
@@ -138,7 +139,7 @@ def main(argv=None):
     log(f"data: {json.dumps(rep['data'])}")
 
     net = Net(batch=a.batch, seed=0)
-    hist = TR.train(net, xtr, ytr, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
+    hist = TR.train(net, xtr, ytr, epochs=a.epochs, batch=a.batch, lr=a.lr, symmetry=not a.no_symmetry, log=log)
     tsec = sum(h[2] for h in hist)
     steps = a.epochs * (a.train // a.batch)
     flops = 3 * forward_flops() * steps * a.batch

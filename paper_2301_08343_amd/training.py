@@ -24,8 +24,17 @@ def lr_at(step, total, warmup, peak):
     return 0.5 * peak * (1.0 + math.cos(math.pi * t))
 
 
-def train(net: Net, x, y, epochs=20, batch=256, lr=2e-3, wd=1e-2, seed=0, log=print):
-    """Train in place; returns [(epoch, mean loss, seconds, samples/s)]."""
+def augment(x, y, ops, xo, yo):
+    """Symmetry copies (tsg_augment) of x, y by the int32 device tensor ops."""
+    native.tsg_call("tsg_augment", x.data_ptr(), y.data_ptr(), x.shape[0], x.shape[1], ops.data_ptr(),
+                    xo.data_ptr(), yo.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return xo, yo
+
+
+def train(net: Net, x, y, epochs=20, batch=256, lr=2e-3, wd=1e-2, seed=0, symmetry=True, log=print):
+    """Train in place; returns [(epoch, mean loss, seconds, samples/s)].
+    With `symmetry` every mini-batch sample is replaced by one of its eight
+    mirror/transpose copies, drawn per sample and step."""
     n = x.shape[0]
     steps_per_epoch = n // batch
     if steps_per_epoch < 1:
@@ -34,8 +43,11 @@ def train(net: Net, x, y, epochs=20, batch=256, lr=2e-3, wd=1e-2, seed=0, log=pr
     g = torch.Generator().manual_seed(seed)
     hist = []
     step = 0
+    xa = torch.empty((batch,) + tuple(x.shape[1:]), dtype=torch.float32, device=x.device)
+    ya = torch.empty((batch,) + tuple(y.shape[1:]), dtype=torch.float32, device=y.device)
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).to(x.device)
+        ops_all = torch.randint(0, 8, (steps_per_epoch, batch), generator=g, dtype=torch.int32).to(x.device)
         acc = torch.zeros(1, dtype=torch.float32, device=x.device)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -43,6 +55,8 @@ def train(net: Net, x, y, epochs=20, batch=256, lr=2e-3, wd=1e-2, seed=0, log=pr
             idx = perm[k * batch:(k + 1) * batch]
             xb = x.index_select(0, idx)
             yb = y.index_select(0, idx)
+            if symmetry:
+                xb, yb = augment(xb, yb, ops_all[k], xa, ya)
             loss = net.train_step(xb, yb, lr_at(step, total, steps_per_epoch, lr), wd=wd)
             acc += loss
             step += 1
