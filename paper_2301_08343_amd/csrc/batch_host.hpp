@@ -392,7 +392,7 @@ tacchi_status tacchi_batch_create(const tacchi_config *cfgs, int32_t n, const ta
             const double *q0 = &bt->traj[((size_t)i * (substeps + 1) + k) * 7];
             itab[(size_t)i * substeps + k] = make_indenter<double>(cfgs[i], q0, q0 + 7, dt[i]);
         }
-        const double one = 1099511627776.0;  // 2^40, see P2GScales
+        const double one = kFixedUnits;  // see P2GScales
         cc[i] = {(float)dt[i], (float)(dt[i] * d.V0 * 4.0 / (d.dx * d.dx)), (float)(one / d.m),
                  (float)(one * dt[i] / d.m), (float)(d.m / one), (float)(d.m / (one * dt[i]))};
     }

@@ -47,11 +47,13 @@ __global__ void __launch_bounds__(kWG) k_bin(SimDev<T> S)
 
 // LDS accumulation slot of one tile channel. FP64 adds natively
 // (ds_add_f64). FP32 accumulates 64-bit fixed point with ds_add_u64: the
-// contributions are pre-scaled so that one particle mass is 2^40 units and one
-// momentum unit m/dt (a particle crossing a cell per substep) is 2^40 units,
+// contributions are pre-scaled so that one particle mass is 2^28 units and one
+// momentum unit m/dt (a particle crossing a cell per substep) is 2^28 units,
 // converted to integers and summed exactly, so the sum does not depend on the
 // order of the atomics; gfx950 also executes ds_add_u64 about 25x faster than
-// ds_add_f32.
+// ds_add_f32. Each contribution is below 2^31 units (checked per particle:
+// 8 cells per substep, far beyond the CFL limit), so it converts with one
+// FP32 -> int32 instruction and is sign-extended into the 64-bit sum.
 template <typename T>
 struct TileAcc;
 
@@ -67,12 +69,12 @@ template <>
 struct TileAcc<float> {
     using Slot = unsigned long long;
     static constexpr bool kFixed = true;
-    __device__ static void add(Slot *s, float v) { atomicAdd(s, (unsigned long long)(long long)v); }
+    __device__ static void add(Slot *s, float v) { atomicAdd(s, (unsigned long long)(long long)(int)v); }
     __device__ static float value(Slot s) { return (float)(double)(long long)s; }
 };
 
-constexpr float kFixedOne = 1099511627776.0f;    // 2^40
-constexpr float kFixedLimit = 3.6028797e16f;     // 2^55: largest accepted scaled contribution
+constexpr double kFixedUnits = 268435456.0;     // 2^28 units per particle mass and per m/dt
+constexpr float kFixedLimit = 2147483520.0f;     // largest float below 2^31: bound of a scaled contribution
 
 // One workgroup per grid block: particles binned to the block scatter mass
 // and momentum (Eqs. 2-5) into a (B+3)^3 LDS tile; the whole tile is then
@@ -206,9 +208,11 @@ __global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, 
 // Block c's tile spans nodes lo_c - 1 .. lo_c + B + 1, so along each axis the
 // node is covered by its own block, by the lower neighbour when l <= 1 and by
 // the upper neighbour when l = B-1. Blocks without particles wrote no tile.
+// nc27, when given, holds the particle counts of the 27 blocks around (bx,
+// by, bz) at index (oz+1)*9 + (oy+1)*3 + (ox+1) (0 outside the grid).
 template <typename T, int B>
 __device__ __forceinline__ void gather_node(const SimDev<T> &S, int bx, int by, int bz, int lx, int ly, int lz,
-                                            T out[4])
+                                            T out[4], const int *nc27 = nullptr)
 {
     constexpr int TB = B + 3, TN = TB * TB * TB;
     out[0] = out[1] = out[2] = out[3] = T(0);
@@ -223,9 +227,13 @@ __device__ __forceinline__ void gather_node(const SimDev<T> &S, int bx, int by, 
         for (int oy = lo[1]; oy <= hi[1]; ++oy)
             for (int ox = lo[0]; ox <= hi[0]; ++ox) {
                 const int cx = bx + ox, cy = by + oy, cz = bz + oz;
-                if (cx < 0 || cy < 0 || cz < 0 || cx >= S.nb0 || cy >= S.nb1 || cz >= S.nb2) continue;
+                if (nc27) {
+                    if (nc27[(oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)] == 0) continue;
+                } else {
+                    if (cx < 0 || cy < 0 || cz < 0 || cx >= S.nb0 || cy >= S.nb1 || cz >= S.nb2) continue;
+                    if (S.cnt_cur[(cz * S.nb1 + cy) * S.nb0 + cx] == 0) continue;
+                }
                 const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
-                if (S.cnt_cur[c] == 0) continue;
                 // tile index of the node in block c's tile (origin lo_c - 1)
                 const int ti = ((lz - oz * B + 1) * TB + (ly - oy * B + 1)) * TB + (lx - ox * B + 1);
                 const T *src = S.tiles + ((int64_t)c * TN + ti) * 4;
@@ -263,9 +271,9 @@ __device__ __forceinline__ T wave_sum(T x)
 
 // One workgroup per grid block that a G2P tile may read (the block or one of
 // its 26 neighbours has particles). Per node with mass above S.m_floor
-// (0 in FP64; in FP32 2^-30 of a particle's mass, below which P/M is
+// (0 in FP64; in FP32 2^-22 of a particle's mass, below which P/M is
 // dominated by fixed-point quantisation and the node's weight in any particle
-// is under FP32 resolution): V = P/M + dt g (Eq. 6);
+// is negligible): V = P/M + dt g (Eq. 6);
 // inside the indenter V takes the rigid indenter velocity (sticky contact;
 // the reaction M (V_before - V_indenter)/dt is summed into the force);
 // floor nodes are held; wall nodes drop their outward component. The inside test and the
@@ -276,7 +284,18 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
 {
     constexpr int B3 = B * B * B;
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
-    const bool live = block_live(S, bx, by, bz);
+    // particle counts of the 27 surrounding blocks, loaded once per workgroup
+    __shared__ int nc27[27];
+    if (threadIdx.x < 27) {
+        const int t = threadIdx.x;
+        const int cx = bx + t % 3 - 1, cy = by + (t / 3) % 3 - 1, cz = bz + t / 9 - 1;
+        const bool in = cx >= 0 && cy >= 0 && cz >= 0 && cx < S.nb0 && cy < S.nb1 && cz < S.nb2;
+        nc27[t] = in ? S.cnt_cur[(cz * S.nb1 + cy) * S.nb0 + cx] : 0;
+    }
+    __syncthreads();
+    bool live = false;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) live = live || nc27[t] > 0;
     if (!live) return;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const T inv_dt = T(1) / dt;
@@ -285,7 +304,7 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
         const int64_t addr = (int64_t)b * B3 + l;
         T mp[4];
-        gather_node<T, B>(S, bx, by, bz, lx, ly, lz, mp);
+        gather_node<T, B>(S, bx, by, bz, lx, ly, lz, mp, nc27);
         const T m = mp[0];
         T V0 = T(0), V1 = T(0), V2 = T(0);
         if (m > S.m_floor && gx < S.g0 && gy < S.g1 && gz < S.g2) {
@@ -407,33 +426,39 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
                 // sums well conditioned in FP32
                 const int lc = ((l2 + 1) * TB + (l1 + 1)) * TB + (l0 + 1);
                 const T vr[3] = {tile[lc], tile[TN + lc], tile[2 * TN + lc]};
-                T s0[3] = {T(0), T(0), T(0)};       // sum w V
-                T sx[3] = {T(0), T(0), T(0)};       // sum w (V - vr) a
-                T sy[3] = {T(0), T(0), T(0)};
-                T sz[3] = {T(0), T(0), T(0)};
-                T sr[3] = {T(0), T(0), T(0)};       // sum w (V - vr)
+                // The weights are a tensor product, so the sums over the 27
+                // nodes of w D, w D a, w D b, w D c (D = V - vr, offsets a, b,
+                // c along x, y, z) are taken one axis at a time: over c, then
+                // b, then a.
+                T sx[3], sy[3], sz[3], sr[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+                for (int r = 0; r < 3; ++r) {
+                    T u[3], uy[3], uz[3];
 #pragma unroll
-                    for (int bb = 0; bb < 3; ++bb) {
-                        const T wbc = wy[bb] * wz[c];
-                        const int lrow = ((l2 + c) * TB + (l1 + bb)) * TB + l0;
+                    for (int a = 0; a < 3; ++a) {
+                        T t[3], tz[3];
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const T wt = wx[a] * wbc;
-                            const int li = lrow + a;
-#pragma unroll
-                            for (int r = 0; r < 3; ++r) {
-                                const T Vn = tile[r * TN + li];
-                                const T wd = wt * (Vn - vr[r]);
-                                s0[r] += wt * Vn;
-                                sr[r] += wd;
-                                sx[r] += wd * T(a);
-                                sy[r] += wd * T(bb);
-                                sz[r] += wd * T(c);
-                            }
+                        for (int bb = 0; bb < 3; ++bb) {
+                            const int li = ((l2 * TB + (l1 + bb)) * TB + l0 + a) + r * TN;
+                            const T d0 = tile[li] - vr[r];
+                            const T d1 = tile[li + TB * TB] - vr[r];
+                            const T d2 = tile[li + 2 * TB * TB] - vr[r];
+                            t[bb] = wz[0] * d0 + wz[1] * d1 + wz[2] * d2;
+                            tz[bb] = wz[1] * d1 + T(2) * wz[2] * d2;
                         }
+                        u[a] = wy[0] * t[0] + wy[1] * t[1] + wy[2] * t[2];
+                        uy[a] = wy[1] * t[1] + T(2) * wy[2] * t[2];
+                        uz[a] = wy[0] * tz[0] + wy[1] * tz[1] + wy[2] * tz[2];
                     }
+                    sr[r] = wx[0] * u[0] + wx[1] * u[1] + wx[2] * u[2];
+                    sx[r] = wx[1] * u[1] + T(2) * wx[2] * u[2];
+                    sy[r] = wx[0] * uy[0] + wx[1] * uy[1] + wx[2] * uy[2];
+                    sz[r] = wx[0] * uz[0] + wx[1] * uz[1] + wx[2] * uz[2];
+                }
+                // sum w V = sum w D + vr sum w, with sum w the product of the
+                // per-axis weight sums
+                const T wsum = (wx[0] + wx[1] + wx[2]) * (wy[0] + wy[1] + wy[2]) * (wz[0] + wz[1] + wz[2]);
+                const T s0[3] = {sr[0] + vr[0] * wsum, sr[1] + vr[1] * wsum, sr[2] + vr[2] * wsum};
                 // C = (4/dx^2) sum w V (X_i - x_p)^T, in 1/s with grid-unit offsets
                 T Cm[9];
 #pragma unroll

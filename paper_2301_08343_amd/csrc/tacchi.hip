@@ -349,11 +349,12 @@ SimDev<T> make_simdev(tacchi_sim *s)
         S.grav[a] = T(s->cfg.gravity[a] / d.dx);
     }
     S.m = T(d.m);
-    // FP32 grid nodes lighter than 2^-30 particle masses (1024 units of the
-    // fixed-point P2G accumulator) are treated as empty: their P/M is dominated
-    // by quantisation, and the weight they carry into any particle is below
-    // 27 * 2^-30, about FP32 resolution.
-    S.m_floor = sizeof(T) == 4 ? T(d.m * 9.313225746154785e-10) : T(0);
+    // FP32 grid nodes lighter than 2^-22 particle masses (64 units of the
+    // fixed-point P2G accumulator) are treated as empty: their P/M carries
+    // quantisation error of up to 1/64 cell per substep, and the weight they
+    // carry into any particle is below 27 * 2^-22, so the velocity error they
+    // would pass on stays under 2^-21 cells per substep.
+    S.m_floor = sizeof(T) == 4 ? T(d.m * 2.384185791015625e-07) : T(0);
     S.vcoef = T(d.V0 * 4.0 / (d.dx * d.dx));
     S.mu = T(d.mu);
     S.lambda = T(d.lambda);
@@ -421,7 +422,7 @@ struct P2GScales {
 P2GScales p2g_scales(const tacchi_sim *s, double dt)
 {
     if (s->cfg.precision == TACCHI_F64) return {1.0, 1.0, 1.0, 1.0};
-    const double one = 1099511627776.0;  // 2^40
+    const double one = kFixedUnits;
     const double m = s->d.m;
     return {one / m, one * dt / m, m / one, m / (one * dt)};
 }
