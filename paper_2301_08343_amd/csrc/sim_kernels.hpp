@@ -73,6 +73,49 @@ struct TileAcc<float> {
     __device__ static float value(Slot s) { return (float)(double)(long long)s; }
 };
 
+// Storage order of a block's (B+3)^3 P2G tile in global memory. Along each
+// axis the tile coordinate t splits into three regions by the block whose
+// node it is: t = 0 (the lower neighbour's last layer, 1 node), t = 1..B (the
+// block's own nodes), t = B+1, B+2 (the upper neighbour's first two layers).
+// The tile is stored region by region (z region, then y, then x), each region
+// x-fastest, so the grid update of a neighbour reads one contiguous run per
+// region instead of 1- or 2-node pieces of every row.
+template <int B>
+struct TileRegions {
+    static constexpr int TB = B + 3;
+    __device__ static int size(int r) { return r == 0 ? 1 : (r == 1 ? B : 2); }
+    __device__ static int start(int r) { return r == 0 ? 0 : (r == 1 ? 1 : B + 1); }
+    __device__ static int region(int t) { return t == 0 ? 0 : (t <= B ? 1 : 2); }
+    __device__ static int slot(int rx, int ux, int ry, int uy, int rz, int uz)
+    {
+        const int sx = size(rx), sy = size(ry), sz = size(rz);
+        return start(rz) * TB * TB + sz * start(ry) * TB + sz * sy * start(rx) + (uz * sy + uy) * sx + ux;
+    }
+    // slot of tile coordinates (x, y, z)
+    __device__ static int slot_of(int x, int y, int z)
+    {
+        const int rx = region(x), ry = region(y), rz = region(z);
+        return slot(rx, x - start(rx), ry, y - start(ry), rz, z - start(rz));
+    }
+    // tile coordinates of slot s (inverse of slot_of)
+    __device__ static void coords(int s, int &x, int &y, int &z)
+    {
+        const int rz = s < TB * TB ? 0 : (s < (B + 1) * TB * TB ? 1 : 2);
+        s -= start(rz) * TB * TB;
+        const int sz = size(rz);
+        const int ry = s < sz * TB ? 0 : (s < sz * (B + 1) * TB ? 1 : 2);
+        s -= sz * start(ry) * TB;
+        const int sy = size(ry);
+        const int rx = s < sz * sy ? 0 : (s < sz * sy * (B + 1) ? 1 : 2);
+        s -= sz * sy * start(rx);
+        const int sx = size(rx);
+        const int ux = s % sx, q = s / sx;
+        x = start(rx) + ux;
+        y = start(ry) + q % sy;
+        z = start(rz) + q / sy;
+    }
+};
+
 constexpr double kFixedUnits = 268435456.0;     // 2^28 units per particle mass and per m/dt
 constexpr float kFixedLimit = 2147483520.0f;     // largest float below 2^31: bound of a scaled contribution
 
@@ -187,9 +230,13 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     }
     __syncthreads();
     T *dst = S.tiles + (int64_t)b * TN * 4;
-    for (int li = threadIdx.x; li < TN; li += WG) {
-        T *d = dst + 4 * li;
-        const int row = li / TB, ls = row * PX + (li - row * TB);
+    // stored in region order (TileRegions): consecutive threads write
+    // consecutive slots
+    for (int si = threadIdx.x; si < TN; si += WG) {
+        T *d = dst + 4 * si;
+        int x, y, z;
+        TileRegions<B>::coords(si, x, y, z);
+        const int ls = (z * TB + y) * PX + x;
         d[0] = Acc::value(tile[ls]) * munit;
         d[1] = Acc::value(tile[TL + ls]) * punit;
         d[2] = Acc::value(tile[2 * TL + ls]) * punit;
@@ -234,8 +281,9 @@ __device__ __forceinline__ void gather_node(const SimDev<T> &S, int bx, int by, 
                     if (S.cnt_cur[(cz * S.nb1 + cy) * S.nb0 + cx] == 0) continue;
                 }
                 const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
-                // tile index of the node in block c's tile (origin lo_c - 1)
-                const int ti = ((lz - oz * B + 1) * TB + (ly - oy * B + 1)) * TB + (lx - ox * B + 1);
+                // slot of the node in block c's tile (tile origin lo_c - 1; the
+                // offset -1/0/+1 selects region 2/1/0 along each axis)
+                const int ti = TileRegions<B>::slot_of(lx - ox * B + 1, ly - oy * B + 1, lz - oz * B + 1);
                 const T *src = S.tiles + ((int64_t)c * TN + ti) * 4;
                 out[0] += src[0];
                 out[1] += src[1];
