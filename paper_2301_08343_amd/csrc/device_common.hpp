@@ -189,6 +189,24 @@ __device__ __forceinline__ void stencil_base(const T xr[3], const T uu[3], int b
     }
 }
 
+// Position of node (lx, ly, lz) inside its block's B^3 run of the velocity
+// grid. The G2P tile of a block reads the last layer of its lower neighbour
+// and the first two layers of its upper neighbour along each axis, so each
+// axis splits into the segments {0, 1}, {2 .. B-2}, {B-1}; the block's nodes
+// are stored segment region by segment region (z, then y, then x), each
+// region x-fastest, and a neighbour's share is a few contiguous runs.
+template <int B>
+__device__ __forceinline__ int node_local(int lx, int ly, int lz)
+{
+    auto seg = [](int l) { return l <= 1 ? 0 : (l <= B - 2 ? 1 : 2); };
+    auto start = [](int r) { return r == 0 ? 0 : (r == 1 ? 2 : B - 1); };
+    auto size = [](int r) { return r == 0 ? 2 : (r == 1 ? B - 3 : 1); };
+    const int rx = seg(lx), ry = seg(ly), rz = seg(lz);
+    const int sx = size(rx), sy = size(ry), sz = size(rz);
+    return start(rz) * B * B + sz * start(ry) * B + sz * sy * start(rx) +
+           ((lz - start(rz)) * sy + (ly - start(ry))) * sx + (lx - start(rx));
+}
+
 template <int B>
 __device__ __forceinline__ int64_t node_addr(int nb0, int nb1, int x, int y, int z)
 {
@@ -196,7 +214,7 @@ __device__ __forceinline__ int64_t node_addr(int nb0, int nb1, int x, int y, int
     int bx = x >> LB, by = y >> LB, bz = z >> LB;
     int lx = x & (B - 1), ly = y & (B - 1), lz = z & (B - 1);
     int64_t blk = ((int64_t)bz * nb1 + by) * nb0 + bx;
-    return blk * (B * B * B) + ((lz * B + ly) * B + lx);
+    return blk * (B * B * B) + node_local<B>(lx, ly, lz);
 }
 
 // Block key of a particle: the grid block holding the grid cell the particle

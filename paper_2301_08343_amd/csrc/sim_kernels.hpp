@@ -350,7 +350,7 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
     for (int l = threadIdx.x; l < B3; l += WG) {
         const int lx = l % B, ly = (l / B) % B, lz = l / (B * B);
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
-        const int64_t addr = (int64_t)b * B3 + l;
+        const int64_t addr = (int64_t)b * B3 + node_local<B>(lx, ly, lz);
         T mp[4];
         gather_node<T, B>(S, bx, by, bz, lx, ly, lz, mp, nc27);
         const T m = mp[0];
