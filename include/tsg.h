@@ -155,6 +155,14 @@ tsg_status tsg_channel_mse(const float *a, const float *b, int32_t n, int32_t np
 tsg_status tsg_augment(const float *x, const float *y, int32_t n, int32_t res, const int32_t *ops, float *x_out,
                        float *y_out, void *stream);
 
+/* Contact term of the surrogate's output, added in FP32 after the head:
+ * out[p][2] += scale * min(x[p][0], 0) for p < npix, with out the head's
+ * [npix][3] output and x the FP32 input [npix][2] (channel 0 the gap field).
+ * Where the indenter is below the undeformed face, the sticking surface
+ * follows it, so this term carries the large part of u_z exactly and the
+ * network (BF16 storage) only learns the smooth remainder. */
+tsg_status tsg_contact_residual(float *out, const float *x, int64_t npix, float scale, void *stream);
+
 const char *tsg_last_error(void);
 
 #ifdef __cplusplus

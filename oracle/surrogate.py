@@ -178,8 +178,11 @@ def _levels(P):
     return sum(1 for k in P if k.startswith("enc") and k.endswith("a"))
 
 
-def forward(P, x, storage=_ident):
-    """Network output [n,H,W,Cout] and the cache the backward pass needs."""
+def forward(P, x, storage=_ident, contact_residual=0.0):
+    """Network output [n,H,W,Cout] and the cache the backward pass needs.
+
+    contact_residual c adds c * min(x[..., 0], 0) to output channel 2 (the
+    unrounded input, no parameters, so the backward pass is unchanged)."""
     levels = _levels(P)
     S = storage
     cache = {"x": S(x)}
@@ -204,6 +207,8 @@ def forward(P, x, storage=_ident):
         cat = np.concatenate([up, skips[l]], axis=-1)
         h = cg(f"dec{l}b", cg(f"dec{l}a", cat))
     out = conv(h, *W["head"])
+    if contact_residual:
+        out[..., 2] += contact_residual * np.minimum(x[..., 0], 0.0)
     cache["head"] = (h, None)
     cache["W"] = W
     return out, cache
@@ -242,7 +247,7 @@ def backward(cache, gout, storage=_ident):
     return G
 
 
-def loss_and_grads(P, x, y, storage=_ident):
-    out, cache = forward(P, x, storage)
+def loss_and_grads(P, x, y, storage=_ident, contact_residual=0.0):
+    out, cache = forward(P, x, storage, contact_residual)
     loss, gout = mse(out, y)
     return loss, out, backward(cache, gout, storage)

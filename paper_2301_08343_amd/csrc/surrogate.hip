@@ -614,6 +614,15 @@ __global__ void k_augment(const float *x, const float *y, int n, int res, const 
     yo[idx * 3 + 2] = y[src * 3 + 2];
 }
 
+// out[p][2] += scale * min(x[p][0], 0): the contact term of the output,
+// added in FP32 after the head.
+__global__ void k_contact_residual(float *out, const float *x, int64_t npix, float scale)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    out[p * 3 + 2] += scale * fminf(x[p * 2], 0.0f);
+}
+
 unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -896,6 +905,15 @@ tsg_status tsg_augment(const float *x, const float *y, int32_t n, int32_t res, c
         return fail(-1, "tsg_augment: bad arguments");
     hipLaunchKernelGGL(k_augment, dim3(blocks_for((int64_t)n * res * res)), dim3(256), 0, (hipStream_t)stream, x, y, n,
                        res, ops, x_out, y_out);
+    TSG_LAUNCHED();
+    return 0;
+}
+
+tsg_status tsg_contact_residual(float *out, const float *x, int64_t npix, float scale, void *stream)
+{
+    if (!out || !x || npix < 1) return fail(-1, "tsg_contact_residual: bad arguments");
+    hipLaunchKernelGGL(k_contact_residual, dim3(blocks_for(npix)), dim3(256), 0, (hipStream_t)stream, out, x, npix,
+                       scale);
     TSG_LAUNCHED();
     return 0;
 }

@@ -185,6 +185,7 @@ _TSG_SIGS = {
     "tsg_features": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _f32, _vp, _vp]),
     "tsg_channel_mse": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp]),
     "tsg_augment": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "tsg_contact_residual": (_i32, [_vp, _vp, _i64, _f32, _vp]),
     "tsg_last_error": (ctypes.c_char_p, []),
 }
 TSG_EXPORTS = tuple(_TSG_SIGS)

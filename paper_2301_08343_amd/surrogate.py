@@ -71,12 +71,15 @@ def _ptr(t):
 class Net:
     """The surrogate with buffers for batches of up to `batch` samples."""
 
-    def __init__(self, batch: int, res: int = 64, enc=ENC, mid=MID, seed: int = 0, device: str = "cuda"):
+    def __init__(self, batch: int, res: int = 64, enc=ENC, mid=MID, seed: int = 0, device: str = "cuda",
+                 contact_residual: float = 0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("the surrogate kernels need a GPU")
         if res % (1 << len(enc)) or res < (1 << len(enc)):
             raise ValueError("res must be divisible by 2**levels")
         self.batch, self.res, self.enc, self.mid = batch, res, tuple(enc), mid
+        # output channel 2 += contact_residual * min(input channel 0, 0), in FP32
+        self.contact_residual = float(contact_residual)
         self.L = len(enc)
         self.dev = torch.device(device)
         self.specs = layer_specs(self.enc, mid)
@@ -122,7 +125,8 @@ class Net:
 
     def state_dict(self):
         return {"flat": self.flat.detach().cpu(), "m": self.m.detach().cpu(), "v": self.v.detach().cpu(),
-                "step": self.step_count, "res": self.res, "enc": list(self.enc), "mid": self.mid}
+                "step": self.step_count, "res": self.res, "enc": list(self.enc), "mid": self.mid,
+                "contact_residual": self.contact_residual}
 
     def load_state_dict(self, sd):
         if list(sd["enc"]) != list(self.enc) or sd["mid"] != self.mid or sd["res"] != self.res:
@@ -131,6 +135,7 @@ class Net:
         self.m.copy_(sd["m"])
         self.v.copy_(sd["v"])
         self.step_count = int(sd["step"])
+        self.contact_residual = float(sd.get("contact_residual", self.contact_residual))
         self.repack()
 
     def repack(self):
@@ -223,6 +228,7 @@ class Net:
         if n > self.batch or tuple(x32.shape[1:]) != (self.res, self.res, CIN):
             raise ValueError("input must be [n <= batch, res, res, 2]")
         x32 = x32.contiguous()
+        self._x32 = x32
         native.tsg_call("tsg_to_bf16", _ptr(x32), n * self.res * self.res, CIN, _ptr(self.x), CIN_P,
                         self._stream())
         return n
@@ -256,6 +262,9 @@ class Net:
             self._conv(f"dec{l}b", n, r, self.da[l], c, 0, c, self.db[l], c, 0, GELU, self.zdb[l], c, 0)
             src, hc = self.db[l], c
         self._conv("head", n, self.res, self.db[0], E[0], 0, E[0], None, 0, 0, F32)
+        if self.contact_residual != 0.0:
+            native.tsg_call("tsg_contact_residual", _ptr(self.out), _ptr(self._x32), n * self.res * self.res,
+                            self.contact_residual, self._stream())
 
     def _backward(self, n):
         E, L, s = self.enc, self.L, self._stream()

@@ -57,7 +57,8 @@ def load_compact(path, batch=512):
         meta = {k: json.loads(v) for k, v in f.metadata().items()}
         wb = f.get_tensor("weights_bf16").float()
         bb = f.get_tensor("biases")
-    net = Net(batch=batch, res=meta["res"], enc=tuple(meta["enc"]), mid=meta["mid"])
+    net = Net(batch=batch, res=meta["res"], enc=tuple(meta["enc"]), mid=meta["mid"],
+              contact_residual=meta.get("contact_residual", 0.0))
     ow = ob = 0
     for name, ci, co, t in net.specs:
         w, b = net.param(name)
@@ -75,7 +76,8 @@ def load(path, batch=512):
         meta = {k: json.loads(v) for k, v in f.metadata().items()}
         flat = f.get_tensor("flat")
         feats = f.get_tensor("train_features")
-    net = Net(batch=batch, res=meta["res"], enc=tuple(meta["enc"]), mid=meta["mid"])
+    net = Net(batch=batch, res=meta["res"], enc=tuple(meta["enc"]), mid=meta["mid"],
+              contact_residual=meta.get("contact_residual", 0.0))
     net.flat.copy_(flat)
     net.repack()
     return net, feats.cuda(), meta
@@ -121,6 +123,7 @@ def main(argv=None):
     ap.add_argument("--h", type=float, default=D.H_DATA)
     ap.add_argument("--gen-batch", type=int, default=256)
     ap.add_argument("--no-symmetry", action="store_true", help="train without the mirror/transpose copies")
+    ap.add_argument("--no-residual", action="store_true", help="no FP32 contact term on the output")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
@@ -138,7 +141,7 @@ def main(argv=None):
                    "substeps_per_contact": c0["steps"], "h_m": a.h}
     log(f"data: {json.dumps(rep['data'])}")
 
-    net = Net(batch=a.batch, seed=0)
+    net = Net(batch=a.batch, seed=0, contact_residual=0.0 if a.no_residual else D.X_UNIT / D.Y_UNIT)
     hist = TR.train(net, xtr, ytr, epochs=a.epochs, batch=a.batch, lr=a.lr, symmetry=not a.no_symmetry, log=log)
     tsec = sum(h[2] for h in hist)
     steps = a.epochs * (a.train // a.batch)
@@ -153,6 +156,7 @@ def main(argv=None):
     ftr = RT.features(xtr)
     thr = RT.Router.calibrate(ftr, RT.features(xte))
     meta = {"res": net.res, "enc": list(net.enc), "mid": net.mid, "h_m": a.h, "train_samples": a.train,
+            "contact_residual": net.contact_residual,
             "y_unit_m": D.Y_UNIT, "x_unit_m": D.X_UNIT, "gap_clip_m": D.GAP_CLIP}
     save(os.path.join(a.out, "surrogate.safetensors"), net, ftr, thr, meta)
     save_compact(os.path.join(a.out, "surrogate_compact.safetensors"), net, thr,
@@ -162,7 +166,7 @@ def main(argv=None):
     if a.queries > 0:
         del xtr, ytr
         torch.cuda.empty_cache()
-        serve_net = Net(batch=512, seed=0)
+        serve_net = Net(batch=512, seed=0, contact_residual=net.contact_residual)
         serve_net.flat.copy_(net.flat)
         serve_net.repack()
         rep.update(serve_benchmark(serve_net, ftr, thr, a.h, a.queries, a.plain_sample))

@@ -348,7 +348,7 @@ def test_network_forward_and_gradients_match_reference(T, n, res):
     errors of 1e-2 (output) and 3e-2 (each weight gradient) bound them with
     margin while a wrong index, tap or operand shows up as O(1)."""
     from paper_2301_08343_amd.surrogate import Net
-    net = Net(batch=4, res=res, seed=3)
+    net = Net(batch=4, res=res, seed=3, contact_residual=10.0)
     rng = np.random.default_rng(91 + n)
     # biases away from zero so their gradients and the epilogue are exercised
     for name, ci, co, t in net.specs:
@@ -359,7 +359,8 @@ def test_network_forward_and_gradients_match_reference(T, n, res):
     loss = net.loss_and_grads(torch.tensor(x).cuda(), torch.tensor(y).cuda())
     out = host(net.out)[:n * res * res].reshape(n, res, res, 3)
     P = net_params(net)
-    rl, rout, G = R.loss_and_grads(P, x.astype(np.float64), y.astype(np.float64), storage=R.round_bf16)
+    rl, rout, G = R.loss_and_grads(P, x.astype(np.float64), y.astype(np.float64), storage=R.round_bf16,
+                                   contact_residual=10.0)
     e_out = rel_l2(out, rout)
     print(f"n={n} res={res}: output rel L2 {e_out:.2e}, loss {host(loss)[0]:.6f} vs {rl:.6f}")
     assert e_out <= 1e-2
@@ -453,3 +454,17 @@ def test_symmetry_copies(T):
             ex, ey = ex[::-1].copy(), ey[::-1].copy()
             ey[..., 1] *= -1
         assert np.array_equal(gx[k], ex) and np.array_equal(gy[k], ey), k
+
+
+def test_contact_residual(T):
+    rng = np.random.default_rng(141)
+    npix = 1000
+    out = rng.standard_normal((npix, 3)).astype(np.float32)
+    x = rng.standard_normal((npix, 2)).astype(np.float32)
+    od, xd = f32_dev(out), f32_dev(x)
+    T.tsg_call("tsg_contact_residual", od.data_ptr(), xd.data_ptr(), npix, 10.0, stream())
+    ref = out.astype(np.float64)
+    ref[:, 2] += np.float32(10.0) * np.minimum(x[:, 0], 0).astype(np.float64)
+    got = host(od)
+    assert np.array_equal(got[:, :2], out[:, :2].astype(np.float64))
+    assert np.all(np.abs(got[:, 2] - ref[:, 2]) <= 2.0 ** -23 * (np.abs(ref[:, 2]) + 10 * np.abs(x[:, 0])))

@@ -23,7 +23,7 @@ def to_torch_weight(w):
     return torch.from_numpy(np.ascontiguousarray(w.transpose(0, 2, 1).reshape(co, ci, k, k)))
 
 
-def torch_net(P, x):
+def torch_net(P, x, contact_residual=0.0):
     """The same U-Net written with torch's float64 CPU operators (NCHW)."""
     levels = sum(1 for k in P if k.startswith("enc") and k.endswith("a"))
     T = {k: (to_torch_weight(w).requires_grad_(), torch.from_numpy(b.copy()).requires_grad_()) for k, (w, b) in P.items()}
@@ -43,7 +43,11 @@ def torch_net(P, x):
         h = cg(f"up{l}", F.interpolate(h, scale_factor=2, mode="nearest"))
         h = cg(f"dec{l}b", cg(f"dec{l}a", torch.cat([h, skips[l]], dim=1)))
     w, b = T["head"]
-    return F.conv2d(h, w, b).permute(0, 2, 3, 1), T
+    out = F.conv2d(h, w, b).permute(0, 2, 3, 1)
+    xt = torch.from_numpy(x)
+    res = torch.zeros_like(out)
+    res[..., 2] = contact_residual * torch.clamp(xt[..., 0], max=0.0)
+    return out + res, T
 
 
 def test_parameter_count_of_the_full_network():
@@ -84,8 +88,8 @@ def test_network_forward_and_gradients_match_torch_autograd():
         P[k] = (P[k][0], rng.standard_normal(P[k][1].shape) * 0.1)
     x = rng.standard_normal((2, 8, 8, 2))
     y = rng.standard_normal((2, 8, 8, 3))
-    loss, out, G = R.loss_and_grads(P, x, y)
-    tout, T = torch_net(P, x)
+    loss, out, G = R.loss_and_grads(P, x, y, contact_residual=10.0)
+    tout, T = torch_net(P, x, contact_residual=10.0)
     assert np.abs(out - tout.detach().numpy()).max() <= 1e-12
     tl = ((tout - torch.from_numpy(y)) ** 2).mean()
     tl.backward()
