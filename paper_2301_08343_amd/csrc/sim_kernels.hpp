@@ -49,11 +49,14 @@ __global__ void __launch_bounds__(kWG) k_bin(SimDev<T> S)
 // (ds_add_f64). FP32 accumulates 64-bit fixed point with ds_add_u64: the
 // contributions are pre-scaled so that one particle mass is 2^28 units and one
 // momentum unit m/dt (a particle crossing a cell per substep) is 2^28 units,
-// converted to integers and summed exactly, so the sum does not depend on the
-// order of the atomics; gfx950 also executes ds_add_u64 about 25x faster than
-// ds_add_f32. Each contribution is below 2^31 units (checked per particle:
-// 8 cells per substep, far beyond the CFL limit), so it converts with one
-// FP32 -> int32 instruction and is sign-extended into the 64-bit sum.
+// rounded to the nearest integer and summed exactly, so the sum does not
+// depend on the order of the atomics; gfx950 also executes ds_add_u64 about
+// 25x faster than ds_add_f32. Each contribution is below 2^31 units (checked
+// per particle: 8 cells per substep, far beyond the CFL limit), so it converts
+// with an FP32 round-to-nearest-even and one FP32 -> int32 instruction and is
+// sign-extended into the 64-bit sum. Rounding (not truncation) keeps the
+// quantisation error unbiased: truncation shrinks every contribution toward
+// zero, a bias that a steady configuration repeats every substep.
 template <typename T>
 struct TileAcc;
 
@@ -69,7 +72,7 @@ template <>
 struct TileAcc<float> {
     using Slot = unsigned long long;
     static constexpr bool kFixed = true;
-    __device__ static void add(Slot *s, float v) { atomicAdd(s, (unsigned long long)(long long)(int)v); }
+    __device__ static void add(Slot *s, float v) { atomicAdd(s, (unsigned long long)(long long)(int)rintf(v)); }
     __device__ static float value(Slot s) { return (float)(double)(long long)s; }
 };
 

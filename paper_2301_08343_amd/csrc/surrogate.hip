@@ -218,16 +218,20 @@ tsg_status launch_conv_epi(const ConvArgs &a, int epi, hipStream_t st)
 // ------------------------------------------------------------------ weight gradient
 
 // Partial dw over one pixel range for a tile of 32 output channels x 32
-// input channels of one tap. The pixel chunk (32 pixels) of dout and of the
+// input channels of one tap. Chunks of 128 pixels of dout and of the
 // tap-shifted input are transposed into LDS (channel-major) so that each
 // lane's MFMA fragment is 8 consecutive pixels of one channel; 4 waves each
-// own one 16x16 quarter of the tile.
+// own one 16x16 quarter of the tile and issue 4 MFMAs per chunk. Blocks of
+// the first (tap, input-channel) tile also sum the dout chunk per channel
+// into bpart (the bias gradient's partials), when bpart is given.
+constexpr int kWgChunk = 128;
+
 __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h, int w, int in_ld, int in_off,
                                                int cin_p, const uint16_t *dout, int d_ld, int d_off, int cout,
-                                               int taps, int pix_per_split, float *part)
+                                               int taps, int pix_per_split, float *part, float *bpart)
 {
-    __shared__ __align__(16) uint16_t sA[32][40];  // [co][pixel], padded rows
-    __shared__ __align__(16) uint16_t sB[32][40];  // [ci][pixel]
+    __shared__ __align__(16) uint16_t sA[32][kWgChunk + 8];  // [co][pixel], padded rows
+    __shared__ __align__(16) uint16_t sB[32][kWgChunk + 8];  // [ci][pixel]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = h * w, npix = n * hw;
     const int co0 = blockIdx.x * 32;
@@ -237,32 +241,50 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h,
     const int dh = taps == 9 ? tap / 3 - 1 : 0, dw = taps == 9 ? tap % 3 - 1 : 0;
     const int pbeg = split * pix_per_split, pend = min(npix, pbeg + pix_per_split);
     const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;  // this wave's quarter
+    const bool do_bias = bpart != nullptr && blockIdx.y == 0;
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // loader mapping: 256 threads = 32 pixels x 8 groups of 4 channels
+    float bsum = 0.0f;
+    // loader mapping: 256 threads = 32 pixels x 8 groups of 4 channels, 4 rounds
     const int lp = tid >> 3, lc = (tid & 7) * 4;
-    for (int p0 = pbeg; p0 < pend; p0 += 32) {
-        const int p = p0 + lp;
-        uint2 va = uint2{0u, 0u}, vb = uint2{0u, 0u};
-        if (p < pend) {
-            if (co0 + lc < cout) va = *(const uint2 *)(dout + (int64_t)p * d_ld + d_off + co0 + lc);
-            const int nn = p / hw, rem = p - nn * hw, hh = rem / w + dh, ww = rem % w + dw;
-            if (ci0 + lc < cin_p && (unsigned)hh < (unsigned)h && (unsigned)ww < (unsigned)w)
-                vb = *(const uint2 *)(in + ((int64_t)(nn * h + hh) * w + ww) * in_ld + in_off + ci0 + lc);
+    for (int p0 = pbeg; p0 < pend; p0 += kWgChunk) {
+        uint2 va[kWgChunk / 32], vb[kWgChunk / 32];
+#pragma unroll
+        for (int j = 0; j < kWgChunk / 32; ++j) {
+            const int p = p0 + lp + 32 * j;
+            va[j] = uint2{0u, 0u};
+            vb[j] = uint2{0u, 0u};
+            if (p < pend) {
+                if (co0 + lc < cout) va[j] = *(const uint2 *)(dout + (int64_t)p * d_ld + d_off + co0 + lc);
+                const int nn = p / hw, rem = p - nn * hw, hh = rem / w + dh, ww = rem % w + dw;
+                if (ci0 + lc < cin_p && (unsigned)hh < (unsigned)h && (unsigned)ww < (unsigned)w)
+                    vb[j] = *(const uint2 *)(in + ((int64_t)(nn * h + hh) * w + ww) * in_ld + in_off + ci0 + lc);
+            }
         }
         __syncthreads();
-        sA[lc + 0][lp] = (uint16_t)(va.x & 0xffffu);
-        sA[lc + 1][lp] = (uint16_t)(va.x >> 16);
-        sA[lc + 2][lp] = (uint16_t)(va.y & 0xffffu);
-        sA[lc + 3][lp] = (uint16_t)(va.y >> 16);
-        sB[lc + 0][lp] = (uint16_t)(vb.x & 0xffffu);
-        sB[lc + 1][lp] = (uint16_t)(vb.x >> 16);
-        sB[lc + 2][lp] = (uint16_t)(vb.y & 0xffffu);
-        sB[lc + 3][lp] = (uint16_t)(vb.y >> 16);
+#pragma unroll
+        for (int j = 0; j < kWgChunk / 32; ++j) {
+            const int q = lp + 32 * j;
+            sA[lc + 0][q] = (uint16_t)(va[j].x & 0xffffu);
+            sA[lc + 1][q] = (uint16_t)(va[j].x >> 16);
+            sA[lc + 2][q] = (uint16_t)(va[j].y & 0xffffu);
+            sA[lc + 3][q] = (uint16_t)(va[j].y >> 16);
+            sB[lc + 0][q] = (uint16_t)(vb[j].x & 0xffffu);
+            sB[lc + 1][q] = (uint16_t)(vb[j].x >> 16);
+            sB[lc + 2][q] = (uint16_t)(vb[j].y & 0xffffu);
+            sB[lc + 3][q] = (uint16_t)(vb[j].y >> 16);
+        }
         __syncthreads();
         const int r16 = lane & 15, kg = (lane >> 4) * 8;
-        const bf16x8 a8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[wm + r16][kg]);
-        const bf16x8 b8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sB[wn + r16][kg]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < kWgChunk / 32; ++j) {
+            const bf16x8 a8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[wm + r16][32 * j + kg]);
+            const bf16x8 b8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sB[wn + r16][32 * j + kg]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc, 0, 0, 0);
+        }
+        if (do_bias && tid < 32) {
+            // pixels past pend were loaded as zeros
+            for (int q = 0; q < kWgChunk; ++q) bsum += bf2f(sA[tid][q]);
+        }
     }
     // acc[v] = partial dw[co0 + wm + 4 (lane/16) + v][tap][ci0 + wn + lane%16]
     const int ci = ci0 + wn + (lane & 15);
@@ -272,6 +294,7 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h,
         if (co < cout && ci < cin_p)
             part[(((int64_t)split * cout + co) * taps + tap) * cin_p + ci] = acc[v];
     }
+    if (do_bias && tid < 32 && co0 + tid < cout) bpart[(int64_t)split * cout + co0 + tid] = bsum;
 }
 
 // dw[co][tap][ci] = sum over splits (fixed order) of the partials, ci < cin.
@@ -287,19 +310,7 @@ __global__ void k_wgrad_reduce(const float *part, int splits, int cout, int taps
     dw[idx] = s;
 }
 
-// Column sums of a [npix][c] view: one partial per (split, channel), then a
-// fixed-order reduction. Used for the bias gradients.
-__global__ void k_colsum_bf16(const uint16_t *d, int npix, int c, int ld, int off, int rows_per_split, float *part)
-{
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    const int split = blockIdx.y;
-    if (ch >= c) return;
-    const int r0 = split * rows_per_split, r1 = min(npix, r0 + rows_per_split);
-    float s = 0.0f;
-    for (int r = r0; r < r1; ++r) s += bf2f(d[(int64_t)r * ld + off + ch]);
-    part[(int64_t)split * c + ch] = s;
-}
-
+// Fixed-order sum over splits of per-split partials [splits][c].
 __global__ void k_colsum_reduce(const float *part, int splits, int c, float *out)
 {
     const int ch = blockIdx.x * blockDim.x + threadIdx.x;
@@ -328,21 +339,32 @@ __global__ void k_head_wgrad(const uint16_t *in, int npix, int in_ld, int in_off
     part[(int64_t)split * nval + t] = s;
 }
 
-constexpr int kHeadSplits = 256;
+constexpr int kHeadSplits = 4096;
 
-// Fixed-order sum of the head partials into dw [cout][cin] and db [cout].
-__global__ void k_head_reduce(const float *part, int splits, int cout, int cin, float *dw, float *db)
+// Fixed-order sum of the head partials into dw [cout][cin] and db [cout]:
+// one workgroup per value, each thread a strided share of the splits, then a
+// tree in LDS.
+__global__ void __launch_bounds__(256) k_head_reduce(const float *part, int splits, int cout, int cin, float *dw,
+                                                     float *db)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float red[256];
+    const int t = blockIdx.x;
     const int nval = cout * (cin + 1);
-    if (t >= nval) return;
     float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * nval + t];
-    const int co = t / (cin + 1), ci = t % (cin + 1);
-    if (ci < cin)
-        dw[co * cin + ci] = s;
-    else
-        db[co] = s;
+    for (int k = threadIdx.x; k < splits; k += 256) s += part[(int64_t)k * nval + t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int co = t / (cin + 1), ci = t % (cin + 1);
+        if (ci < cin)
+            dw[co * cin + ci] = red[0];
+        else
+            db[co] = red[0];
+    }
 }
 
 __global__ void k_head_dgrad(const float *dout, int npix, int cout, const float *w, int cin, uint16_t *din, int ld,
@@ -420,6 +442,119 @@ __global__ void k_upsample2_bwd(const uint16_t *dout, int n, int h, int w, int c
         for (int dx = 0; dx < 2; ++dx)
             s += bf2f(dout[((int64_t)(nn * 2 * h + 2 * y + dy) * W2 + 2 * x + dx) * dld + doff + ch]);
     din[q * ild + ioff + ch] = f2bf(s);
+}
+
+// 8-channel vector forms of the pooling/upsampling kernels and their
+// gradients (channel counts, row strides and offsets multiples of 8, 16-byte
+// aligned rows): one thread per (pixel, group of 8 channels).
+__device__ __forceinline__ void unpack8(uint4 v, float f[8])
+{
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = bf2f((uint16_t)(w[k] & 0xffffu));
+        f[2 * k + 1] = bf2f((uint16_t)(w[k] >> 16));
+    }
+}
+
+__device__ __forceinline__ uint4 pack8(const float f[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(f[2 * k]) | ((uint32_t)f2bf(f[2 * k + 1]) << 16);
+    return uint4{w[0], w[1], w[2], w[3]};
+}
+
+__global__ void k_avgpool2_v8(const uint16_t *in, int n, int h, int w, int c, int ld, int off, uint16_t *out, int old,
+                              int ooff)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ho = h / 2, wo = w / 2, g = c / 8;
+    if (idx >= (int64_t)n * ho * wo * g) return;
+    const int cg = (int)(idx % g) * 8;
+    const int64_t q = idx / g;
+    const int x = (int)(q % wo), y = (int)((q / wo) % ho), nn = (int)(q / ((int64_t)wo * ho));
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            float f[8];
+            unpack8(*(const uint4 *)(in + ((int64_t)(nn * h + 2 * y + dy) * w + 2 * x + dx) * ld + off + cg), f);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += f[k];
+        }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] *= 0.25f;
+    *(uint4 *)(out + q * old + ooff + cg) = pack8(acc);
+}
+
+__global__ void k_avgpool2_bwd_v8(const uint16_t *dout, int n, int h, int w, int c, int dld, int doff, uint16_t *din,
+                                  int ild, int ioff, int accumulate)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = c / 8;
+    if (idx >= (int64_t)n * h * w * g) return;
+    const int cg = (int)(idx % g) * 8;
+    const int64_t q = idx / g;
+    const int x = (int)(q % w), y = (int)((q / w) % h), nn = (int)(q / ((int64_t)w * h));
+    const int ho = h / 2, wo = w / 2;
+    float f[8];
+    unpack8(*(const uint4 *)(dout + ((int64_t)(nn * ho + y / 2) * wo + x / 2) * dld + doff + cg), f);
+    uint4 *dst = (uint4 *)(din + q * ild + ioff + cg);
+    float prev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (accumulate) unpack8(*dst, prev);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[k] = 0.25f * f[k] + prev[k];
+    *dst = pack8(f);
+}
+
+__global__ void k_upsample2_v8(const uint16_t *in, int n, int h, int w, int c, int ld, int off, uint16_t *out, int old,
+                               int ooff)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int H2 = 2 * h, W2 = 2 * w, g = c / 8;
+    if (idx >= (int64_t)n * H2 * W2 * g) return;
+    const int cg = (int)(idx % g) * 8;
+    const int64_t q = idx / g;
+    const int x = (int)(q % W2), y = (int)((q / W2) % H2), nn = (int)(q / ((int64_t)W2 * H2));
+    *(uint4 *)(out + q * old + ooff + cg) =
+        *(const uint4 *)(in + ((int64_t)(nn * h + y / 2) * w + x / 2) * ld + off + cg);
+}
+
+__global__ void k_upsample2_bwd_v8(const uint16_t *dout, int n, int h, int w, int c, int dld, int doff, uint16_t *din,
+                                   int ild, int ioff)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = c / 8;
+    if (idx >= (int64_t)n * h * w * g) return;
+    const int cg = (int)(idx % g) * 8;
+    const int64_t q = idx / g;
+    const int x = (int)(q % w), y = (int)((q / w) % h), nn = (int)(q / ((int64_t)w * h));
+    const int W2 = 2 * w;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+            float f[8];
+            unpack8(*(const uint4 *)(dout + ((int64_t)(nn * 2 * h + 2 * y + dy) * W2 + 2 * x + dx) * dld + doff + cg), f);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += f[k];
+        }
+    *(uint4 *)(din + q * ild + ioff + cg) = pack8(acc);
+}
+
+__global__ void k_dgelu_v8(uint16_t *d, int dld, int doff, const uint16_t *z, int zld, int zoff, int npix, int c)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = c / 8;
+    if (idx >= (int64_t)npix * g) return;
+    const int cg = (int)(idx % g) * 8;
+    const int64_t p = idx / g;
+    uint4 *pd = (uint4 *)(d + p * dld + doff + cg);
+    float f[8], zz[8];
+    unpack8(*pd, f);
+    unpack8(*(const uint4 *)(z + p * zld + zoff + cg), zz);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[k] *= dgelu(zz[k]);
+    *pd = pack8(f);
 }
 
 __global__ void k_add_inplace(uint16_t *a, int ald, int aoff, const uint16_t *b, int bld, int boff, int npix, int c)
@@ -627,6 +762,9 @@ unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b)
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
+// a view whose 8-channel groups are 16-byte aligned
+bool v8_ok(const void *p, int c, int ld, int off) { return aligned16(p) && c % 8 == 0 && ld % 8 == 0 && off % 8 == 0; }
+
 }  // namespace tsg
 
 using namespace tsg;
@@ -696,7 +834,7 @@ size_t tsg_wgrad_scratch_bytes(int32_t n, int32_t h, int32_t w, int32_t cin_p, i
     const int64_t npix = (int64_t)n * h * w;
     const int s = wgrad_splits(npix, cout, cin_p, taps);
     const size_t part = (size_t)s * cout * taps * cin_p * sizeof(float);
-    const size_t bias = (size_t)64 * cout * sizeof(float);
+    const size_t bias = (size_t)s * cout * sizeof(float);
     return part + bias;
 }
 
@@ -713,22 +851,17 @@ tsg_status tsg_conv_wgrad(const uint16_t *in, int32_t n, int32_t h, int32_t w, i
     const int64_t npix = (int64_t)n * h * w;
     const int splits = wgrad_splits(npix, cout, cin_p, taps);
     int pps = (int)((npix + splits - 1) / splits);
-    pps = ((pps + 31) / 32) * 32;
+    pps = ((pps + kWgChunk - 1) / kWgChunk) * kWgChunk;
+    float *bpart = db ? scratch + (size_t)splits * cout * taps * cin_p : nullptr;
     const dim3 grid((cout + 31) / 32, taps * ((cin_p + 31) / 32), splits);
     hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld, d_off, cout,
-                       taps, pps, scratch);
+                       taps, pps, scratch, bpart);
     TSG_LAUNCHED();
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout * taps * cin)), dim3(256), 0, st, scratch, splits,
                        cout, taps, cin, cin_p, dw);
     TSG_LAUNCHED();
     if (db) {
-        float *bpart = scratch + (size_t)splits * cout * taps * cin_p;
-        const int bs = 64;
-        const int rps = (int)((npix + bs - 1) / bs);
-        hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks_for(cout, 64), bs), dim3(64), 0, st, dout, (int)npix, cout, d_ld,
-                           d_off, rps, bpart);
-        TSG_LAUNCHED();
-        hipLaunchKernelGGL(k_colsum_reduce, dim3(blocks_for(cout, 64)), dim3(64), 0, st, bpart, bs, cout, db);
+        hipLaunchKernelGGL(k_colsum_reduce, dim3(blocks_for(cout, 64)), dim3(64), 0, st, bpart, splits, cout, db);
         TSG_LAUNCHED();
     }
     return 0;
@@ -754,8 +887,7 @@ tsg_status tsg_conv_wgrad_f32(const uint16_t *in, int32_t n, int32_t h, int32_t 
     hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadSplits), dim3(((nval + 63) / 64) * 64), 0, st, in, (int)npix, in_ld,
                        in_off, cin, dout, cout, rps, scratch);
     TSG_LAUNCHED();
-    hipLaunchKernelGGL(k_head_reduce, dim3(blocks_for(nval, 64)), dim3(64), 0, st, scratch, kHeadSplits, cout, cin, dw,
-                       db);
+    hipLaunchKernelGGL(k_head_reduce, dim3(nval), dim3(256), 0, st, scratch, kHeadSplits, cout, cin, dw, db);
     TSG_LAUNCHED();
     return 0;
 }
@@ -775,6 +907,12 @@ tsg_status tsg_avgpool2(const uint16_t *in, int32_t n, int32_t h, int32_t w, int
                         uint16_t *out, int32_t out_ld, int32_t out_off, void *stream)
 {
     if (!in || !out || h % 2 || w % 2) return fail(-1, "tsg_avgpool2: bad arguments");
+    if (v8_ok(in, c, in_ld, in_off) && v8_ok(out, c, out_ld, out_off)) {
+        hipLaunchKernelGGL(k_avgpool2_v8, dim3(blocks_for((int64_t)n * (h / 2) * (w / 2) * (c / 8))), dim3(256), 0,
+                           (hipStream_t)stream, in, n, h, w, c, in_ld, in_off, out, out_ld, out_off);
+        TSG_LAUNCHED();
+        return 0;
+    }
     hipLaunchKernelGGL(k_avgpool2, dim3(blocks_for((int64_t)n * (h / 2) * (w / 2) * c)), dim3(256), 0,
                        (hipStream_t)stream, in, n, h, w, c, in_ld, in_off, out, out_ld, out_off);
     TSG_LAUNCHED();
@@ -786,6 +924,12 @@ tsg_status tsg_avgpool2_bwd(const uint16_t *dout, int32_t n, int32_t h, int32_t 
                             void *stream)
 {
     if (!dout || !din || h % 2 || w % 2) return fail(-1, "tsg_avgpool2_bwd: bad arguments");
+    if (v8_ok(dout, c, d_ld, d_off) && v8_ok(din, c, din_ld, din_off)) {
+        hipLaunchKernelGGL(k_avgpool2_bwd_v8, dim3(blocks_for((int64_t)n * h * w * (c / 8))), dim3(256), 0,
+                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, accumulate);
+        TSG_LAUNCHED();
+        return 0;
+    }
     hipLaunchKernelGGL(k_avgpool2_bwd, dim3(blocks_for((int64_t)n * h * w * c)), dim3(256), 0, (hipStream_t)stream,
                        dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, accumulate);
     TSG_LAUNCHED();
@@ -796,6 +940,12 @@ tsg_status tsg_upsample2(const uint16_t *in, int32_t n, int32_t h, int32_t w, in
                          int32_t in_off, uint16_t *out, int32_t out_ld, int32_t out_off, void *stream)
 {
     if (!in || !out) return fail(-1, "tsg_upsample2: bad arguments");
+    if (v8_ok(in, c, in_ld, in_off) && v8_ok(out, c, out_ld, out_off)) {
+        hipLaunchKernelGGL(k_upsample2_v8, dim3(blocks_for((int64_t)n * 4 * h * w * (c / 8))), dim3(256), 0,
+                           (hipStream_t)stream, in, n, h, w, c, in_ld, in_off, out, out_ld, out_off);
+        TSG_LAUNCHED();
+        return 0;
+    }
     hipLaunchKernelGGL(k_upsample2, dim3(blocks_for((int64_t)n * 4 * h * w * c)), dim3(256), 0, (hipStream_t)stream,
                        in, n, h, w, c, in_ld, in_off, out, out_ld, out_off);
     TSG_LAUNCHED();
@@ -806,6 +956,12 @@ tsg_status tsg_upsample2_bwd(const uint16_t *dout, int32_t n, int32_t h, int32_t
                              int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, void *stream)
 {
     if (!dout || !din) return fail(-1, "tsg_upsample2_bwd: bad arguments");
+    if (v8_ok(dout, c, d_ld, d_off) && v8_ok(din, c, din_ld, din_off)) {
+        hipLaunchKernelGGL(k_upsample2_bwd_v8, dim3(blocks_for((int64_t)n * h * w * (c / 8))), dim3(256), 0,
+                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off);
+        TSG_LAUNCHED();
+        return 0;
+    }
     hipLaunchKernelGGL(k_upsample2_bwd, dim3(blocks_for((int64_t)n * h * w * c)), dim3(256), 0, (hipStream_t)stream,
                        dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off);
     TSG_LAUNCHED();
@@ -826,6 +982,12 @@ tsg_status tsg_dgelu(uint16_t *d, int32_t d_ld, int32_t d_off, const uint16_t *z
                      int32_t npix, int32_t c, void *stream)
 {
     if (!d || !z) return fail(-1, "tsg_dgelu: bad arguments");
+    if (v8_ok(d, c, d_ld, d_off) && v8_ok(z, c, z_ld, z_off)) {
+        hipLaunchKernelGGL(k_dgelu_v8, dim3(blocks_for((int64_t)npix * (c / 8))), dim3(256), 0, (hipStream_t)stream, d,
+                           d_ld, d_off, z, z_ld, z_off, npix, c);
+        TSG_LAUNCHED();
+        return 0;
+    }
     hipLaunchKernelGGL(k_dgelu, dim3(blocks_for((int64_t)npix * c)), dim3(256), 0, (hipStream_t)stream, d, d_ld, d_off,
                        z, z_ld, z_off, npix, c);
     TSG_LAUNCHED();

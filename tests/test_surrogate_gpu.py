@@ -206,8 +206,9 @@ def test_head_gradients(T):
     assert np.all(np.abs(host(din) - ref) <= U_BF * (np.abs(ref) + LIP * acc) + LIP * acc + 1e-6 * np.abs(dx))
 
 
-def test_pool_upsample_and_elementwise(T):
-    n, h, w, c, ld, off = 2, 6, 10, 16, 24, 8
+@pytest.mark.parametrize("c,ld,off", [(16, 24, 8), (4, 6, 2)])  # 8-channel vector path, scalar path
+def test_pool_upsample_and_elementwise(T, c, ld, off):
+    n, h, w = 2, 6, 10
     rng = np.random.default_rng(41)
     x = R.round_bf16(rng.standard_normal((n, h, w, c)))
     xd = bf16_dev(pad_channels(x, c, off, ld))
