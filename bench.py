@@ -87,7 +87,9 @@ def surrogate_leg(args):
             "served_vs_mpm_height_rmse_um": rep["served_vs_mpm_height_rmse_um"],
             "heldout_height_rmse_um": meta.get("heldout", {}).get("height_rmse_um"),
             "queries": r["queries"], "mpm_fallbacks": r["mpm_fallbacks"], "ood": r["ood"],
-            "audited": r["audited"], "breaker_tripped": r["breaker_tripped"],
+            "audited": r["audited"], "breaker_tripped_families": r["breaker_tripped"],
+            "served_by_surrogate": r["served_by_surrogate"],
+            "audited_height_rmse_um_served_families": r["audited_height_rmse_um_open_classes"],
             "inference_frames_per_s": 512 / inf_s,
             "inference_tflops": 512 * forward_flops(meta["res"]) / inf_s / 1e12,
             "plain_mpm_sample": p["queries"], "data_h_m": meta["h_m"], "train_samples": meta["train_samples"],

@@ -60,8 +60,12 @@ def audit_draws(n, rate, seed):
 
 
 class Router:
+    """Surrogate answers with OOD and audit fallbacks to the MPM. The circuit
+    breaker is kept per indenter family when per_class is set (the query names
+    its indenter), else one breaker covers every query."""
+
     def __init__(self, net: Net, train_features, threshold, audit_rate=0.02, audit_seed=7, rmse_limit_um=5.0,
-                 window=20):
+                 window=20, per_class=True):
         self.net = net
         self.train_features = train_features.contiguous()
         self.threshold = float(threshold)
@@ -69,6 +73,7 @@ class Router:
         self.audit_seed = audit_seed
         self.rmse_limit_um = rmse_limit_um
         self.window = window
+        self.per_class = per_class
 
     @staticmethod
     def calibrate(train_features, heldout_features, q=0.995):
@@ -79,63 +84,78 @@ class Router:
         """Answer every contact; returns (answers [n][res][res][3] in Y_UNIT, report dict)."""
         n = len(contacts)
         audit = audit_draws(n, self.audit_rate, self.audit_seed)
+        key = np.array([c["cfg"]["shape"] if self.per_class else 0 for c in contacts])
         answers = torch.empty(n, D.RES, D.RES, 3, dtype=torch.float32, device="cuda")
         lat = np.zeros(n)
         route = np.zeros(n, dtype=np.int8)  # 0 surrogate, 1 ood, 2 audit, 3 breaker
-        audits_sq = []
-        tripped = False
+        audits_sq = {}
+        tripped = set()
         n_mpm = 0
         torch.cuda.synchronize()
         t_all = time.perf_counter()
         for k0 in range(0, n, batch):
             cs = contacts[k0:k0 + batch]
             m = len(cs)
+            kb = key[k0:k0 + m]
             t0 = time.perf_counter()
+            brk = np.array([k in tripped for k in kb], dtype=bool)
             x = D.inputs(cs)
-            pred = self.net.forward(x).clone() if not tripped else None
-            if tripped:
-                send = np.ones(m, dtype=bool)
-                route[k0:k0 + m] = 3
-            else:
+            pred = None
+            send = brk.copy()
+            if not brk.all():
+                pred = self.net.forward(x).clone()
                 d, _ = nn_distance(features(x), self.train_features)
-                ood = (d > self.threshold).cpu().numpy()
-                aud = audit[k0:k0 + m]
-                send = ood | aud
+                ood = (d > self.threshold).cpu().numpy() & ~brk
+                aud = audit[k0:k0 + m] & ~brk & ~ood
+                send |= ood | aud
                 route[k0:k0 + m][ood] = 1
-                route[k0:k0 + m][aud & ~ood] = 2
+                route[k0:k0 + m][aud] = 2
                 answers[k0:k0 + m] = pred
+            route[k0:k0 + m][brk] = 3
             torch.cuda.synchronize()
-            t_sur = time.perf_counter()
-            lat[k0:k0 + m] = t_sur - t0
+            lat[k0:k0 + m] = time.perf_counter() - t0
             idx = np.nonzero(send)[0]
             if len(idx):
                 ym = D.solve([cs[i] for i in idx])
                 n_mpm += len(idx)
                 it = torch.tensor(idx, device="cuda")
-                if not tripped:
-                    aud_idx = [j for j, i in enumerate(idx) if route[k0 + i] == 2]
-                    if aud_idx:
-                        ai = torch.tensor(aud_idx, device="cuda")
-                        e = per_sample_rmse(pred.index_select(0, it.index_select(0, ai)), ym.index_select(0, ai), 2)
-                        audits_sq += [float(v) ** 2 for v in (e * D.Y_UNIT * 1e6).cpu()]
+                aud_idx = [j for j, i in enumerate(idx) if route[k0 + i] == 2]
+                if aud_idx:
+                    ai = torch.tensor(aud_idx, device="cuda")
+                    e = per_sample_rmse(pred.index_select(0, it.index_select(0, ai)), ym.index_select(0, ai), 2)
+                    for j, v in zip(aud_idx, (e * D.Y_UNIT * 1e6).cpu().tolist()):
+                        audits_sq.setdefault(int(kb[idx[j]]), []).append(v * v)
                 answers.index_copy_(0, it + k0, ym)
                 torch.cuda.synchronize()
                 lat[k0 + idx] = time.perf_counter() - t0
-            recent = audits_sq[-self.window:]
-            if not tripped and recent and math.sqrt(sum(recent) / len(recent)) > self.rmse_limit_um:
-                tripped = True
+            for k, sq in audits_sq.items():
+                recent = sq[-self.window:]
+                if k not in tripped and math.sqrt(sum(recent) / len(recent)) > self.rmse_limit_um:
+                    tripped.add(k)
             if log:
-                log(f"router: {k0 + m}/{n} answered, {n_mpm} by MPM, tripped={tripped}")
+                log(f"router: {k0 + m}/{n} answered, {n_mpm} by MPM, tripped={sorted(tripped)}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_all
-        audited = math.sqrt(sum(audits_sq) / len(audits_sq)) if audits_sq else float("nan")
+        all_sq = [v for sq in audits_sq.values() for v in sq]
+        audited = math.sqrt(sum(all_sq) / len(all_sq)) if all_sq else float("nan")
+        # audits of the classes the breaker left open: the error of what was served
+        open_sq = [v for k, sq in audits_sq.items() if k not in tripped for v in sq]
         rep = {
             "queries": n, "wall_s": wall, "frames_per_s": n / wall,
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mpm_fallbacks": int(n_mpm), "ood": int((route == 1).sum()), "audited": int((route == 2).sum()),
-            "breaker_routed": int((route == 3).sum()), "breaker_tripped": tripped,
+            "breaker_routed": int((route == 3).sum()), "breaker_tripped": sorted(int(k) for k in tripped),
+            "served_by_surrogate": int((route == 0).sum()),
             "audited_height_rmse_um": audited,
+            "audited_height_rmse_um_open_classes": math.sqrt(sum(open_sq) / len(open_sq)) if open_sq else None,
+            "per_class": {str(int(k)): {"queries": int((key == k).sum()),
+                                        "surrogate": int(((key == k) & (route == 0)).sum()),
+                                        "audits": len(audits_sq.get(int(k), [])),
+                                        "audited_rmse_um": (math.sqrt(sum(audits_sq[int(k)]) / len(audits_sq[int(k)]))
+                                                            if audits_sq.get(int(k)) else None),
+                                        "tripped": int(k) in tripped}
+                          for k in np.unique(key)},
         }
         return answers, rep
 

@@ -149,8 +149,8 @@ def main(argv=None):
     rep["train"] = {"epochs": a.epochs, "seconds": tsec, "samples_per_s": steps * a.batch / tsec,
                     "tflops": flops / tsec / 1e12, "final_loss": hist[-1][1],
                     "loss_curve": [h[1] for h in hist]}
-    rep["heldout"] = TR.evaluate(net, xte, yte)
-    rep["train_fit"] = TR.evaluate(net, xtr[:a.heldout], ytr[:a.heldout])
+    rep["heldout"] = TR.evaluate(net, xte, yte, groups=[s % 5 for s in range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout)])
+    rep["train_fit"] = TR.evaluate(net, xtr[:a.heldout], ytr[:a.heldout], groups=[s % 5 for s in range(a.heldout)])
     log(f"held-out: {json.dumps(rep['heldout'])}")
 
     ftr = RT.features(xtr)

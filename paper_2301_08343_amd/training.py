@@ -89,16 +89,18 @@ def per_sample_rmse(a, b, channel) -> torch.Tensor:
     return out.sqrt()
 
 
-def evaluate(net: Net, x, y):
+def evaluate(net: Net, x, y, groups=None):
     """Held-out errors in micrometres: height (uz) RMSE over all pixels and
-    samples, its per-sample distribution, and the RMSE of all components."""
+    samples, its per-sample distribution, and the RMSE of all components;
+    with `groups` (a label per sample, e.g. the indenter family) also the
+    height RMSE per label."""
     p = predict(net, x)
     um = D.Y_UNIT * 1e6
     hz = per_sample_rmse(p, y, 2) * um
     hx = per_sample_rmse(p, y, 0) * um
     hy = per_sample_rmse(p, y, 1) * um
     hz_c = hz.cpu()
-    return {
+    out = {
         "height_rmse_um": float((hz_c ** 2).mean().sqrt()),
         "height_rmse_um_p50": float(hz_c.median()),
         "height_rmse_um_p95": float(hz_c.quantile(0.95)),
@@ -106,3 +108,8 @@ def evaluate(net: Net, x, y):
         "frac_samples_under_5um": float((hz_c <= 5.0).float().mean()),
         "samples": int(x.shape[0]),
     }
+    if groups is not None:
+        g = torch.as_tensor(groups)
+        out["height_rmse_um_by_group"] = {
+            str(int(k)): float((hz_c[g == k] ** 2).mean().sqrt()) for k in torch.unique(g)}
+    return out

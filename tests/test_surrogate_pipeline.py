@@ -42,9 +42,16 @@ def test_breaker_routes_everything_to_mpm(gpu, tmp_path):
     train = D.contacts_for(range(64), 0.5e-3)
     ftr = RT.features(D.inputs(train))
     qs = D.contacts_for(range(1000, 1096), 0.5e-3)
-    r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.5, rmse_limit_um=1e-6)
+    r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.5, rmse_limit_um=1e-6, per_class=False)
     ans, rep = r.serve(qs, batch=32)
-    assert rep["breaker_tripped"]
+    assert rep["breaker_tripped"] == [0]
     assert rep["breaker_routed"] == 64  # batches 2 and 3
     ym = D.solve(qs[32:])
     assert torch.allclose(ans[32:], ym, rtol=0, atol=1e-4)  # 10 nm: the answers are the MPM's
+    # one breaker per indenter family: a family trips once it has an audit
+    r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.5, rmse_limit_um=1e-6, per_class=True)
+    _, rep = r.serve(qs, batch=32)
+    for k, pc in rep["per_class"].items():
+        assert pc["tripped"] == (pc["audits"] > 0)
+    assert rep["breaker_routed"] > 0
+    assert sum(pc["queries"] for pc in rep["per_class"].values()) == 96
