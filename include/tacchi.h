@@ -166,26 +166,30 @@ tacchi_status tacchi_render(tacchi_sim *sim, const tacchi_render_params *rp, flo
 
 /* Displacement field of the contact surface (the depth map of Sec. III-B
  * extended to all three components): out[r][c][a] (metres, float32,
- * res x res x 3) is the displacement x - X of the top face at the centre of
- * cell (c, r) of a res x res partition of the block's top face, bilinear in
- * the top-layer particles' displacements (particle i at (i + 1/2) h; clamped
- * at the border). 1 <= res <= 4096. With out_on_device != 0 the call is
- * asynchronous on the simulation's stream; otherwise it synchronises and
- * reports the device error word. */
-tacchi_status tacchi_surface_displacement(tacchi_sim *sim, int32_t res, float *out, int32_t out_on_device);
+ * res x res x 3) is the mean displacement x - X of the top face over cell
+ * (c, r) of a res x res partition of the block's top face, taken over
+ * sub x sub points spread evenly in the cell (at (c + (q + 1/2)/sub) L/res,
+ * q = 0 .. sub-1, per axis; sub = 1 is the cell centre), each interpolated
+ * bilinearly between the top-layer particles' displacements (particle i at
+ * (i + 1/2) h; clamped at the border). 1 <= res <= 4096, 1 <= sub <= 16.
+ * With out_on_device != 0 the call is asynchronous on the simulation's
+ * stream; otherwise it synchronises and reports the device error word. */
+tacchi_status tacchi_surface_displacement(tacchi_sim *sim, int32_t res, int32_t sub, float *out,
+                                          int32_t out_on_device);
 
 /* Gap field of an indenter over the undeformed top face, the geometric input
  * of the learned surrogate: for n configurations and poses (indenter frame ->
  * world, as in tacchi_step), out[k][r][c] (metres, float32, device memory)
- * = z_ind - z_top at the centre of cell (c, r) of a res x res partition of
- * block k's top face, where z_top = block.origin[2] + block.size[2] and z_ind
- * is the lowest point of the indenter's solid (the inside test of Eq. 10's
- * rigid body) on the vertical through that point; values are clipped to
- * [-clip, clip] (no indenter within clip above: +clip). Found by sampling the
- * inside test at 512 heights from z_top - clip and bisecting the first
- * crossing 40 times. Synchronises. Errors: E_ARG, E_DEVICE. */
+ * is the mean over the sub x sub points of cell (c, r) of block k's top face
+ * (placed as in tacchi_surface_displacement) of the clipped gap
+ * clamp(z_ind - z_top, -clip, clip), where z_top = block.origin[2] +
+ * block.size[2] and z_ind is the lowest point of the indenter's solid (the
+ * inside test of Eq. 10's rigid body) on the vertical through the point (no
+ * indenter within clip above: +clip). z_ind is found by sampling the inside
+ * test at 512 heights from z_top - clip and bisecting the first crossing 40
+ * times. Synchronises. Errors: E_ARG, E_DEVICE. */
 tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n,
-                                  int32_t res, double clip, float *out, void *hip_stream);
+                                  int32_t res, int32_t sub, double clip, float *out, void *hip_stream);
 
 /* Particle state in SoA layout (see the conventions); any pointer may be
  * NULL to skip that array. Synchronises. */
@@ -287,7 +291,7 @@ tacchi_status tacchi_batch_sync(tacchi_batch *batch);
 
 /* tacchi_surface_displacement of every contact: out is [n][res][res][3].
  * Synchronises and reports device errors. */
-tacchi_status tacchi_batch_surface_displacement(tacchi_batch *batch, int32_t res, float *out,
+tacchi_status tacchi_batch_surface_displacement(tacchi_batch *batch, int32_t res, int32_t sub, float *out,
                                                 int32_t out_on_device);
 
 /* Release the batch and its contact handles (host memory only). */

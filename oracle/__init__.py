@@ -273,29 +273,36 @@ def lowest_point(shape: int, sp, seed: int, pose, x, y, zlo, zhi, nscan=20000):
     return lib().orc_lowest_point(shape, _ptr(spc), seed, _ptr(pc), x, y, zlo, zhi, nscan)
 
 
-def indenter_gap(cfg: dict, pose, res: int, clip: float, nscan: int = 20000):
-    """[res][res] gap z_ind - z_top over the centres of a res x res partition
-    of the block's top face (z_top = top face of the undeformed block), where
-    z_ind is the indenter's lowest point on each vertical; clipped to +-clip."""
+def indenter_gap(cfg: dict, pose, res: int, clip: float, nscan: int = 20000, sub: int = 1):
+    """[res][res] gap z_ind - z_top over a res x res partition of the block's
+    top face (z_top = top face of the undeformed block), where z_ind is the
+    indenter's lowest point on a vertical, clipped to +-clip; each cell is the
+    mean over sub x sub points at (c + (q + 1/2)/sub) * width / res."""
     ox, oy, oz = cfg["block_origin"]
     wx, wy, wz = cfg["block_size"]
     ztop = oz + wz
     out = np.zeros((res, res))
     for r in range(res):
         for c in range(res):
-            x = ox + (c + 0.5) * wx / res
-            y = oy + (r + 0.5) * wy / res
-            z = lowest_point(cfg["shape"], cfg["sp"], cfg["seed"], pose, x, y, ztop - clip, ztop + clip, nscan)
-            out[r, c] = min(max(z - ztop, -clip), clip)
+            acc = 0.0
+            for qy in range(sub):
+                for qx in range(sub):
+                    x = ox + (c + (qx + 0.5) / sub) * wx / res
+                    y = oy + (r + (qy + 0.5) / sub) * wy / res
+                    z = lowest_point(cfg["shape"], cfg["sp"], cfg["seed"], pose, x, y, ztop - clip, ztop + clip,
+                                     nscan)
+                    acc += min(max(z - ztop, -clip), clip)
+            out[r, c] = acc / (sub * sub)
     return out
 
 
-def surface_displacement(cfg: dict, x, res: int):
-    """[res][res][3] displacement of the top surface sampled at the centres of
-    a res x res partition of the top face: bilinear interpolation of the
+def surface_displacement(cfg: dict, x, res: int, sub: int = 1):
+    """[res][res][3] displacement of the top surface over a res x res
+    partition of the top face: each cell the mean over sub x sub points at
+    (c + (q + 1/2)/sub) * width / res of the bilinear interpolation of the
     top-layer particles' displacements x - X (x: [N][3] in lattice order
-    i + n0 (j + n1 k), X the cell-centred rest lattice), with the sample
-    clamped to the outermost particles."""
+    i + n0 (j + n1 k), X the cell-centred rest lattice), each point clamped
+    to the outermost particles."""
     n0, n1, n2 = cfg["n"]
     h = [cfg["block_size"][a] / cfg["n"][a] for a in range(3)]
     o = cfg["block_origin"]
@@ -307,11 +314,14 @@ def surface_displacement(cfg: dict, x, res: int):
     out = np.zeros((res, res, 3))
     for r in range(res):
         for c in range(res):
-            si = min(max((c + 0.5) * n0 / res - 0.5, 0.0), n0 - 1.0)
-            sj = min(max((r + 0.5) * n1 / res - 0.5, 0.0), n1 - 1.0)
-            i0 = min(int(np.floor(si)), n0 - 2)
-            j0 = min(int(np.floor(sj)), n1 - 2)
-            tx, ty = si - i0, sj - j0
-            out[r, c] = ((1 - tx) * (1 - ty) * u[j0, i0] + tx * (1 - ty) * u[j0, i0 + 1]
-                         + (1 - tx) * ty * u[j0 + 1, i0] + tx * ty * u[j0 + 1, i0 + 1])
+            for qy in range(sub):
+                for qx in range(sub):
+                    si = min(max((c + (qx + 0.5) / sub) * n0 / res - 0.5, 0.0), n0 - 1.0)
+                    sj = min(max((r + (qy + 0.5) / sub) * n1 / res - 0.5, 0.0), n1 - 1.0)
+                    i0 = min(int(np.floor(si)), n0 - 2)
+                    j0 = min(int(np.floor(sj)), n1 - 2)
+                    tx, ty = si - i0, sj - j0
+                    out[r, c] += ((1 - tx) * (1 - ty) * u[j0, i0] + tx * (1 - ty) * u[j0, i0 + 1]
+                                  + (1 - tx) * ty * u[j0 + 1, i0] + tx * ty * u[j0 + 1, i0 + 1])
+            out[r, c] /= sub * sub
     return out

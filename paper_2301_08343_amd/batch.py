@@ -69,11 +69,12 @@ class Batch:
     def sync(self):
         N.check(N.lib().tacchi_batch_sync(self._h))
 
-    def surface_displacement(self, res: int) -> torch.Tensor:
-        """[n][res][res][3] top-surface displacements (m, float32); synchronises."""
+    def surface_displacement(self, res: int, sub: int = 1) -> torch.Tensor:
+        """[n][res][res][3] top-surface displacements (m, float32, mean of
+        sub x sub points per cell); synchronises."""
         out = torch.empty(self.n, res, res, 3, dtype=torch.float32, device=self.device)
         torch.cuda.current_stream(self.device).synchronize()
-        N.check(N.lib().tacchi_batch_surface_displacement(self._h, res, ctypes.c_void_p(out.data_ptr()), 1))
+        N.check(N.lib().tacchi_batch_surface_displacement(self._h, res, sub, ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
     def close(self):

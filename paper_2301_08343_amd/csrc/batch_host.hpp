@@ -515,18 +515,19 @@ tacchi_status tacchi_batch_tuning(const tacchi_batch *bt, int32_t *tile, int32_t
 
 int64_t tacchi_batch_substeps_done(const tacchi_batch *bt) { return bt ? bt->done : 0; }
 
-tacchi_status tacchi_batch_surface_displacement(tacchi_batch *bt, int32_t res, float *out, int32_t on_device)
+tacchi_status tacchi_batch_surface_displacement(tacchi_batch *bt, int32_t res, int32_t sub, float *out,
+                                                int32_t on_device)
 {
     if (!bt || !out) return fail(TACCHI_E_ARG, "NULL argument");
     if (!on_device) {
         for (int i = 0; i < bt->n; ++i) {
-            tacchi_status st = tacchi_surface_displacement(bt->sims[i], res, out + (size_t)i * res * res * 3, 0);
+            tacchi_status st = tacchi_surface_displacement(bt->sims[i], res, sub, out + (size_t)i * res * res * 3, 0);
             if (st) return st;
         }
         return TACCHI_OK;
     }
     for (int i = 0; i < bt->n; ++i) {
-        tacchi_status st = tacchi_surface_displacement(bt->sims[i], res, out + (size_t)i * res * res * 3, 1);
+        tacchi_status st = tacchi_surface_displacement(bt->sims[i], res, sub, out + (size_t)i * res * res * 3, 1);
         if (st) return st;
     }
     return tacchi_batch_sync(bt);

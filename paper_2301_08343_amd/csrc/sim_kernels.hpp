@@ -576,34 +576,43 @@ __global__ void __launch_bounds__(kWG) k_heightmap(SimDev<T> S, T origin_z, T dx
     out[idx] = origin_z + dx * (zr + S.u[2 * S.Ns + s]);
 }
 
-// Displacement of the top surface at the centres of a res x res partition of
-// the block's top face: out[(r res + c) 3 + a] (metres, FP32), bilinear in
-// the displacements of the top-layer particles (particle i sits at
-// (i + 1/2) h, the sample at (c + 1/2) L / res; clamped at the border).
+// Displacement of the top surface over a res x res partition of the block's
+// top face: out[(r res + c) 3 + a] (metres, FP32) is the mean, over sub x sub
+// points spread evenly inside cell (c, r) (at ((c + (q + 1/2)/sub) L / res),
+// q = 0 .. sub-1, per axis), of the displacement interpolated bilinearly
+// between the top-layer particles (particle i sits at (i + 1/2) h; clamped at
+// the border). sub = 1 samples the cell centre.
 template <typename T, int B>
-__global__ void __launch_bounds__(kWG) k_surface_disp(SimDev<T> S, T dx, int res, float *out)
+__global__ void __launch_bounds__(kWG) k_surface_disp(SimDev<T> S, T dx, int res, int sub, float *out)
 {
     const int idx = blockIdx.x * kWG + threadIdx.x;
     if (idx >= res * res) return;
     const int r = idx / res, c = idx - r * res;
-    T si = (T(c) + T(0.5)) * T(S.n0) / T(res) - T(0.5);
-    T sj = (T(r) + T(0.5)) * T(S.n1) / T(res) - T(0.5);
-    si = si < T(0) ? T(0) : (si > T(S.n0 - 1) ? T(S.n0 - 1) : si);
-    sj = sj < T(0) ? T(0) : (sj > T(S.n1 - 1) ? T(S.n1 - 1) : sj);
-    int i0 = (int)tfloor<T>(si), j0 = (int)tfloor<T>(sj);
-    i0 = i0 > S.n0 - 2 ? S.n0 - 2 : i0;
-    j0 = j0 > S.n1 - 2 ? S.n1 - 2 : j0;
-    const T tx = si - T(i0), ty = sj - T(j0);
     const int k = S.n2 - 1;
-    const uint32_t s00 = lattice_slot<T, B>(S, i0, j0, k), s10 = lattice_slot<T, B>(S, i0 + 1, j0, k);
-    const uint32_t s01 = lattice_slot<T, B>(S, i0, j0 + 1, k), s11 = lattice_slot<T, B>(S, i0 + 1, j0 + 1, k);
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int qy = 0; qy < sub; ++qy)
+        for (int qx = 0; qx < sub; ++qx) {
+            T si = (T(c) + (T(qx) + T(0.5)) / T(sub)) * T(S.n0) / T(res) - T(0.5);
+            T sj = (T(r) + (T(qy) + T(0.5)) / T(sub)) * T(S.n1) / T(res) - T(0.5);
+            si = si < T(0) ? T(0) : (si > T(S.n0 - 1) ? T(S.n0 - 1) : si);
+            sj = sj < T(0) ? T(0) : (sj > T(S.n1 - 1) ? T(S.n1 - 1) : sj);
+            int i0 = (int)tfloor<T>(si), j0 = (int)tfloor<T>(sj);
+            i0 = i0 > S.n0 - 2 ? S.n0 - 2 : i0;
+            j0 = j0 > S.n1 - 2 ? S.n1 - 2 : j0;
+            const T tx = si - T(i0), ty = sj - T(j0);
+            const uint32_t s00 = lattice_slot<T, B>(S, i0, j0, k), s10 = lattice_slot<T, B>(S, i0 + 1, j0, k);
+            const uint32_t s01 = lattice_slot<T, B>(S, i0, j0 + 1, k), s11 = lattice_slot<T, B>(S, i0 + 1, j0 + 1, k);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T *u = S.u + (size_t)a * S.Ns;
-        const T lo = u[s00] + tx * (u[s10] - u[s00]);
-        const T hi = u[s01] + tx * (u[s11] - u[s01]);
-        out[(size_t)idx * 3 + a] = (float)(dx * (lo + ty * (hi - lo)));
-    }
+            for (int a = 0; a < 3; ++a) {
+                const T *u = S.u + (size_t)a * S.Ns;
+                const T lo = u[s00] + tx * (u[s10] - u[s00]);
+                const T hi = u[s01] + tx * (u[s11] - u[s01]);
+                acc[a] += lo + ty * (hi - lo);
+            }
+        }
+    const T w = dx / T(sub * sub);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[(size_t)idx * 3 + a] = (float)(w * acc[a]);
 }
 
 template <typename T>

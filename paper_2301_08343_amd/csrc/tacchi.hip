@@ -677,15 +677,15 @@ tacchi_status heightmap_t(tacchi_sim *s, void *out, int on_device, bool relative
 }
 
 template <typename T>
-tacchi_status surface_disp_t(tacchi_sim *s, int res, float *out)
+tacchi_status surface_disp_t(tacchi_sim *s, int res, int sub, float *out)
 {
     SimDev<T> &S = sdev<T>(s);
     if (s->d.B == 4)
         hipLaunchKernelGGL((k_surface_disp<T, 4>), dim3(grid1d((int64_t)res * res)), dim3(kWG), 0, s->stream, S,
-                           T(s->d.dx), res, out);
+                           T(s->d.dx), res, sub, out);
     else
         hipLaunchKernelGGL((k_surface_disp<T, 8>), dim3(grid1d((int64_t)res * res)), dim3(kWG), 0, s->stream, S,
-                           T(s->d.dx), res, out);
+                           T(s->d.dx), res, sub, out);
     TC_LAUNCHED();
     return TACCHI_OK;
 }
@@ -698,19 +698,12 @@ struct GapDev {
     double ztop;            // undeformed top face height
 };
 
-// out[k][r][c] = (lowest z of indenter k on the vertical through the sample
-// point) - ztop, clipped to [-clip, clip]. The indenter's signed distance is
-// sampled upward from ztop - clip in 512 steps; the first sample inside is
-// refined by 40 bisections.
-__global__ void __launch_bounds__(kWG) k_indenter_gap(const GapDev *q, int n, int res, double clip, float *out)
+// Clipped gap at one point: (lowest z of the indenter on the vertical through
+// (x, y)) - ztop, clipped to [-clip, clip]. The inside test is sampled upward
+// from ztop - clip in 512 steps; the first sample inside is refined by 40
+// bisections.
+__device__ double gap_at(const GapDev &g, double x, double y, double clip)
 {
-    const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (idx >= (int64_t)n * res * res) return;
-    const int k = (int)(idx / ((int64_t)res * res));
-    const int rem = (int)(idx - (int64_t)k * res * res);
-    const int r = rem / res, c = rem - r * res;
-    const GapDev &g = q[k];
-    const double x = g.x0 + (c + 0.5) * g.wx / res, y = g.y0 + (r + 0.5) * g.wy / res;
     const double r0 = x - g.pos[0], r1 = y - g.pos[1];
     auto inside = [&](double z) {
         const double r2 = z - g.pos[2];
@@ -743,7 +736,29 @@ __global__ void __launch_bounds__(kWG) k_indenter_gap(const GapDev *q, int n, in
             a = b;
         }
     }
-    out[idx] = (float)gap;
+    return gap;
+}
+
+// out[k][r][c] = mean of gap_at over sub x sub points spread evenly inside
+// cell (c, r) of the res x res partition of block k's top face (sub = 1: the
+// cell centre).
+__global__ void __launch_bounds__(kWG) k_indenter_gap(const GapDev *q, int n, int res, int sub, double clip,
+                                                      float *out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (idx >= (int64_t)n * res * res) return;
+    const int k = (int)(idx / ((int64_t)res * res));
+    const int rem = (int)(idx - (int64_t)k * res * res);
+    const int r = rem / res, c = rem - r * res;
+    const GapDev &g = q[k];
+    double acc = 0.0;
+    for (int qy = 0; qy < sub; ++qy)
+        for (int qx = 0; qx < sub; ++qx) {
+            const double x = g.x0 + (c + (qx + 0.5) / sub) * g.wx / res;
+            const double y = g.y0 + (r + (qy + 0.5) / sub) * g.wy / res;
+            acc += gap_at(g, x, y, clip);
+        }
+    out[idx] = (float)(acc / (sub * sub));
 }
 
 template <typename T>
@@ -968,20 +983,22 @@ tacchi_status tacchi_heightmap(tacchi_sim *s, void *out, int32_t on_device)
     return read_error_word(s);
 }
 
-tacchi_status tacchi_surface_displacement(tacchi_sim *s, int32_t res, float *out, int32_t on_device)
+tacchi_status tacchi_surface_displacement(tacchi_sim *s, int32_t res, int32_t sub, float *out, int32_t on_device)
 {
     if (!s || !out) return fail(TACCHI_E_ARG, "NULL argument");
     if (res < 1 || res > 4096) return fail(TACCHI_E_ARG, "res must be in [1, 4096]");
+    if (sub < 1 || sub > 16) return fail(TACCHI_E_ARG, "sub must be in [1, 16]");
     if (s->d.n[0] < 2 || s->d.n[1] < 2) return fail(TACCHI_E_ARG, "the top layer needs at least 2 x 2 particles");
     tacchi_status st = set_device(s);
     if (st) return st;
     if (on_device)
-        return s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, out)
-                                              : surface_disp_t<float>(s, res, out);
+        return s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, sub, out)
+                                              : surface_disp_t<float>(s, res, sub, out);
     const size_t bytes = (size_t)res * res * 3 * sizeof(float);
     float *dst = nullptr;
     TC_HIP(hipMallocAsync((void **)&dst, bytes, s->stream));
-    st = s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, dst) : surface_disp_t<float>(s, res, dst);
+    st = s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, sub, dst)
+                                        : surface_disp_t<float>(s, res, sub, dst);
     hipError_t e = st ? hipSuccess : hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, s->stream);
     const hipError_t ef = hipFreeAsync(dst, s->stream);
     const hipError_t es = hipStreamSynchronize(s->stream);
@@ -992,9 +1009,10 @@ tacchi_status tacchi_surface_displacement(tacchi_sim *s, int32_t res, float *out
 }
 
 tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res,
-                                  double clip, float *out, void *hip_stream)
+                                  int32_t sub, double clip, float *out, void *hip_stream)
 {
-    if (!cfgs || !poses || !out || n < 1 || res < 1 || res > 4096 || !(clip > 0.0) || !std::isfinite(clip))
+    if (!cfgs || !poses || !out || n < 1 || res < 1 || res > 4096 || sub < 1 || sub > 16 || !(clip > 0.0) ||
+        !std::isfinite(clip))
         return fail(TACCHI_E_ARG, "tacchi_indenter_gap: bad arguments");
     std::vector<GapDev> q((size_t)n);
     for (int k = 0; k < n; ++k) {
@@ -1019,8 +1037,8 @@ tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *
     TC_HIP(hipMallocAsync((void **)&dq, q.size() * sizeof(GapDev), st));
     hipError_t e = hipMemcpyAsync(dq, q.data(), q.size() * sizeof(GapDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_indenter_gap, dim3(grid1d((int64_t)n * res * res)), dim3(kWG), 0, st, dq, n, res, clip,
-                           out);
+        hipLaunchKernelGGL(k_indenter_gap, dim3(grid1d((int64_t)n * res * res)), dim3(kWG), 0, st, dq, n, res, sub,
+                           clip, out);
         e = hipGetLastError();
     }
     const hipError_t ef = hipFreeAsync(dq, st);

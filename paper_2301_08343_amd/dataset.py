@@ -7,6 +7,9 @@ position and depth drawn from its seed) solved at lattice spacing h:
          depth broadcast, both in mm;
   target y[res][res][3]: the top surface's displacement (ux, uy, uz) after
          the press, in units of Y_UNIT.
+Both fields are cell means over SUB x SUB points, so an edge or a texture
+finer than a cell enters as its covered fraction rather than as an aliased
+point sample.
 All of it is computed by the library (gap field kernel, batched substeps,
 displacement resampling kernel); this module only batches the calls.
 """
@@ -24,6 +27,7 @@ GAP_CLIP = 2e-3   # m
 X_UNIT = 1e-3     # inputs in mm
 Y_UNIT = 1e-4     # targets in 0.1 mm
 RES = 64
+SUB = 4           # each input and target cell is the mean of SUB x SUB points
 H_DATA = 0.2e-3   # lattice spacing of the training solves
 
 
@@ -39,7 +43,8 @@ def _full(c):
 
 def inputs(contacts, res=RES, device="cuda") -> torch.Tensor:
     """[n][res][res][2] float32 surrogate inputs (gap, depth) in mm."""
-    gap = indenter_gap([c["cfg"] for c in contacts], [c["end_pose"] for c in contacts], res, GAP_CLIP, device)
+    gap = indenter_gap([c["cfg"] for c in contacts], [c["end_pose"] for c in contacts], res, GAP_CLIP, device,
+                       sub=SUB)
     x = torch.empty(len(contacts), res, res, 2, dtype=torch.float32, device=device)
     x[..., 0] = gap / X_UNIT
     x[..., 1] = torch.tensor([c["depth"] / X_UNIT for c in contacts], dtype=torch.float32,
@@ -57,7 +62,7 @@ def solve(contacts, res=RES, tune_cache=None, device="cuda") -> torch.Tensor:
     b = Batch(contacts, steps, tune_cache=tune_cache, device=device)
     try:
         b.run(steps)
-        u = b.surface_displacement(res)
+        u = b.surface_displacement(res, SUB)
     finally:
         b.close()
     return u / Y_UNIT

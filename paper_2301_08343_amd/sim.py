@@ -90,10 +90,11 @@ class Sim:
         N.check(N.lib().tacchi_heightmap(self._h, ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
-    def surface_displacement(self, res: int) -> torch.Tensor:
-        """Top-surface displacement resampled to res x res x 3 (m, float32)."""
+    def surface_displacement(self, res: int, sub: int = 1) -> torch.Tensor:
+        """Top-surface displacement over res x res cells (mean of sub x sub
+        points per cell), [res][res][3] (m, float32)."""
         out = self._empty(res, res, 3, dtype=torch.float32)
-        N.check(N.lib().tacchi_surface_displacement(self._h, res, ctypes.c_void_p(out.data_ptr()), 1))
+        N.check(N.lib().tacchi_surface_displacement(self._h, res, sub, ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
     def render(self, rp: dict) -> torch.Tensor:
@@ -161,9 +162,10 @@ def aos_to_soa(x, v, C, F):
             np.ascontiguousarray(np.asarray(C).reshape(n, 9).T), np.ascontiguousarray(np.asarray(F).reshape(n, 9).T))
 
 
-def indenter_gap(cfgs, poses, res: int, clip: float = 2e-3, device="cuda") -> torch.Tensor:
+def indenter_gap(cfgs, poses, res: int, clip: float = 2e-3, device="cuda", sub: int = 1) -> torch.Tensor:
     """Gap fields [n][res][res] (m, float32) of each config's indenter at the
-    given pose over its block's undeformed top face, clipped to +-clip."""
+    given pose over its block's undeformed top face, clipped to +-clip, each
+    cell the mean of sub x sub points."""
     n = len(cfgs)
     carr = (N.Config * n)()
     parr = (N.Pose * n)()
@@ -171,6 +173,6 @@ def indenter_gap(cfgs, poses, res: int, clip: float = 2e-3, device="cuda") -> to
         carr[k] = N.make_config(cfgs[k], poses[k], N.F32, 0)
         parr[k] = N.make_pose(poses[k])
     out = torch.empty(n, res, res, dtype=torch.float32, device=device)
-    N.check(N.lib().tacchi_indenter_gap(carr, parr, n, res, clip, ctypes.c_void_p(out.data_ptr()),
+    N.check(N.lib().tacchi_indenter_gap(carr, parr, n, res, sub, clip, ctypes.c_void_p(out.data_ptr()),
                                         ctypes.c_void_p(torch.cuda.current_stream(out.device).cuda_stream)))
     return out

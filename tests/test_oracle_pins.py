@@ -574,20 +574,25 @@ def _flat_cfg(shape, sp, n=(12, 10, 4), h=0.5e-3):
                       rho=1000.0, model=W.NEOHOOKEAN, shape=shape, sp=sp, seed=3)
 
 
-def test_gap_of_an_upright_sphere_is_its_lower_cap(oracle_lib):
+@pytest.mark.parametrize("sub", [1, 3])
+def test_gap_of_an_upright_sphere_is_its_lower_cap(oracle_lib, sub):
     R = 2e-3
     cfg = _flat_cfg(W.SPHERE, [R])
     ztop = cfg["block_origin"][2] + cfg["block_size"][2]
     pose = (4.6e-3, 5.4e-3, ztop - 0.7e-3, 1.0, 0.0, 0.0, 0.0)
     res, clip = 9, 1.5e-3
-    g = oracle_lib.indenter_gap(cfg, pose, res, clip)
+    g = oracle_lib.indenter_gap(cfg, pose, res, clip, sub=sub)
     for r in range(res):
         for c in range(res):
-            x = cfg["block_origin"][0] + (c + 0.5) * cfg["block_size"][0] / res
-            y = cfg["block_origin"][1] + (r + 0.5) * cfg["block_size"][1] / res
-            rho2 = (x - pose[0]) ** 2 + (y - pose[1]) ** 2
-            exact = clip if rho2 >= R * R else pose[2] + R - math.sqrt(R * R - rho2) - ztop
-            assert abs(g[r, c] - min(max(exact, -clip), clip)) <= 1e-12
+            acc = 0.0
+            for qy in range(sub):
+                for qx in range(sub):
+                    x = cfg["block_origin"][0] + (c + (qx + 0.5) / sub) * cfg["block_size"][0] / res
+                    y = cfg["block_origin"][1] + (r + (qy + 0.5) / sub) * cfg["block_size"][1] / res
+                    rho2 = (x - pose[0]) ** 2 + (y - pose[1]) ** 2
+                    exact = clip if rho2 >= R * R else pose[2] + R - math.sqrt(R * R - rho2) - ztop
+                    acc += min(max(exact, -clip), clip)
+            assert abs(g[r, c] - acc / sub ** 2) <= 1e-12
 
 
 def test_gap_of_a_tilted_punch_is_its_bottom_plane(oracle_lib):
@@ -629,13 +634,18 @@ def test_surface_displacement_reproduces_affine_fields(oracle_lib):
     x = X + X @ A.T + b
     res = 5
     u = oracle_lib.surface_displacement(cfg, x, res)
+    u4 = oracle_lib.surface_displacement(cfg, x, res, sub=4)
     ztop = o[2] + (n2 - 0.5) * h[2]
     for r in range(res):
         for c in range(res):
             P = np.array([o[0] + (c + 0.5) * cfg["block_size"][0] / res,
                           o[1] + (r + 0.5) * cfg["block_size"][1] / res, ztop])
-            # every sample of a 5 x 5 partition of 9 x 7 particles lies inside the lattice hull
+            # every centre of a 5 x 5 partition of 9 x 7 particles lies inside the lattice hull
             assert np.abs(u[r, c] - (A @ P + b)).max() <= 1e-15
+            # the mean of an affine field over points symmetric about the centre is its
+            # value there (interior cells: no point is clamped)
+            if 0 < r < res - 1 and 0 < c < res - 1:
+                assert np.abs(u4[r, c] - (A @ P + b)).max() <= 1e-15
     # on a square lattice at res = n0 the samples are the top particles themselves (row r = j, column c = i)
     cfg8 = _flat_cfg(W.SPHERE, [1e-3], n=(8, 8, 3))
     rng = np.random.default_rng(5)

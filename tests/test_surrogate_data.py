@@ -20,12 +20,13 @@ def gpu():
 
 @pytest.mark.parametrize("seed", range(8))
 def test_gap_field_matches_oracle(oracle_lib, gpu, seed):
-    """All five indenter families, upright (GelSight draws) and tilted (batch draws)."""
+    """All five indenter families, upright (GelSight draws) and tilted (batch
+    draws); cell centres, and means of 3 x 3 points per cell for odd seeds."""
     c = W.gelsight_contact(seed, steps=20) if seed < 5 else W.batch_contact(seed, steps=20)
     cfg, pose = c["cfg"], c["poses"][-1]
-    res, clip = 16, 2e-3
-    got = gpu.indenter_gap([cfg], [pose], res, clip)[0].cpu().double().numpy()
-    ref = oracle_lib.indenter_gap(cfg, pose, res, clip)
+    res, clip, sub = 16, 2e-3, 1 + 2 * (seed % 2)
+    got = gpu.indenter_gap([cfg], [pose], res, clip, sub=sub)[0].cpu().double().numpy()
+    ref = oracle_lib.indenter_gap(cfg, pose, res, clip, nscan=20000 if sub == 1 else 5000, sub=sub)
     # the kernel brackets the crossing to 2 clip / 512 / 2^40 and rounds to FP32
     err = np.abs(got - ref)
     print(f"seed {seed} shape {cfg['shape']}: max |d gap| = {err.max():.3e} m, min gap {ref.min():.3e}")
@@ -48,9 +49,9 @@ def test_surface_displacement_matches_oracle(oracle_lib, gpu):
     sim.run(c["poses"][1:S + 1], c["dt"])
     orc = oracle_lib.OracleSim(c["cfg"], c["poses"][0])
     orc.run(c["poses"], c["dt"], 0, S)
-    for res in (7, 48, 64):
-        got = sim.surface_displacement(res).cpu().double().numpy()
-        ref = oracle_lib.surface_displacement(c["cfg"], orc.particles()[0], res)
+    for res, sub in ((7, 1), (48, 1), (64, 1), (64, 4)):
+        got = sim.surface_displacement(res, sub).cpu().double().numpy()
+        ref = oracle_lib.surface_displacement(c["cfg"], orc.particles()[0], res, sub)
         err = np.abs(got - ref).max()
         print(f"res {res}: max |du| = {err:.3e} m, max |u| = {np.abs(ref).max():.3e} m")
         # FP64 trajectories agree to ~1e-16 m; the output is FP32
@@ -65,8 +66,8 @@ def test_batch_surface_displacement_equals_per_contact(gpu):
     b = Batch(contacts, S)
     b.run(S)
     b.sync()
-    all_u = b.surface_displacement(32)
+    all_u = b.surface_displacement(32, 2)
     for i in range(3):
-        one = b.contact(i).surface_displacement(32)
+        one = b.contact(i).surface_displacement(32, 2)
         torch.cuda.synchronize()
         assert torch.equal(all_u[i], one)
