@@ -181,15 +181,17 @@ tacchi_status tacchi_surface_displacement(tacchi_sim *sim, int32_t res, int32_t 
  * of the learned surrogate: for n configurations and poses (indenter frame ->
  * world, as in tacchi_step), out[k][r][c] (metres, float32, device memory)
  * is the mean over the sub x sub points of cell (c, r) of block k's top face
- * (placed as in tacchi_surface_displacement) of the clipped gap
- * clamp(z_ind - z_top, -clip, clip), where z_top = block.origin[2] +
+ * (placed as in tacchi_surface_displacement) of the clamped gap
+ * clamp(z_ind - z_top, lo, hi), where z_top = block.origin[2] +
  * block.size[2] and z_ind is the lowest point of the indenter's solid (the
  * inside test of Eq. 10's rigid body) on the vertical through the point (no
- * indenter within clip above: +clip). z_ind is found by sampling the inside
- * test at 512 heights from z_top - clip and bisecting the first crossing 40
- * times. Synchronises. Errors: E_ARG, E_DEVICE. */
+ * indenter up to z_top + hi: hi). With hi = 0 this is the penetration of the
+ * indenter into the undeformed face. z_ind is found by sampling the inside
+ * test at 512 heights from z_top + lo to z_top + hi and bisecting the first
+ * crossing 40 times. lo < hi, hi - lo <= 1 m. Synchronises. Errors: E_ARG,
+ * E_DEVICE. */
 tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n,
-                                  int32_t res, int32_t sub, double clip, float *out, void *hip_stream);
+                                  int32_t res, int32_t sub, double lo, double hi, float *out, void *hip_stream);
 
 /* Particle state in SoA layout (see the conventions); any pointer may be
  * NULL to skip that array. Synchronises. */

@@ -273,11 +273,11 @@ def lowest_point(shape: int, sp, seed: int, pose, x, y, zlo, zhi, nscan=20000):
     return lib().orc_lowest_point(shape, _ptr(spc), seed, _ptr(pc), x, y, zlo, zhi, nscan)
 
 
-def indenter_gap(cfg: dict, pose, res: int, clip: float, nscan: int = 20000, sub: int = 1):
+def indenter_gap(cfg: dict, pose, res: int, lo: float, hi: float, nscan: int = 20000, sub: int = 1):
     """[res][res] gap z_ind - z_top over a res x res partition of the block's
     top face (z_top = top face of the undeformed block), where z_ind is the
-    indenter's lowest point on a vertical, clipped to +-clip; each cell is the
-    mean over sub x sub points at (c + (q + 1/2)/sub) * width / res."""
+    indenter's lowest point on a vertical, clamped to [lo, hi]; each cell is
+    the mean over sub x sub points at (c + (q + 1/2)/sub) * width / res."""
     ox, oy, oz = cfg["block_origin"]
     wx, wy, wz = cfg["block_size"]
     ztop = oz + wz
@@ -289,9 +289,8 @@ def indenter_gap(cfg: dict, pose, res: int, clip: float, nscan: int = 20000, sub
                 for qx in range(sub):
                     x = ox + (c + (qx + 0.5) / sub) * wx / res
                     y = oy + (r + (qy + 0.5) / sub) * wy / res
-                    z = lowest_point(cfg["shape"], cfg["sp"], cfg["seed"], pose, x, y, ztop - clip, ztop + clip,
-                                     nscan)
-                    acc += min(max(z - ztop, -clip), clip)
+                    z = lowest_point(cfg["shape"], cfg["sp"], cfg["seed"], pose, x, y, ztop + lo, ztop + hi, nscan)
+                    acc += min(max(z - ztop, lo), hi)
             out[r, c] = acc / (sub * sub)
     return out
 

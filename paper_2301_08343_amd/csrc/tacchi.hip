@@ -699,10 +699,10 @@ struct GapDev {
 };
 
 // Clipped gap at one point: (lowest z of the indenter on the vertical through
-// (x, y)) - ztop, clipped to [-clip, clip]. The inside test is sampled upward
-// from ztop - clip in 512 steps; the first sample inside is refined by 40
+// (x, y)) - ztop, clamped to [lo, hi]. The inside test is sampled upward
+// from ztop + lo to ztop + hi in 512 steps; the first sample inside is refined by 40
 // bisections.
-__device__ double gap_at(const GapDev &g, double x, double y, double clip)
+__device__ double gap_at(const GapDev &g, double x, double y, double lo, double hi)
 {
     const double r0 = x - g.pos[0], r1 = y - g.pos[1];
     auto inside = [&](double z) {
@@ -713,10 +713,10 @@ __device__ double gap_at(const GapDev &g, double x, double y, double clip)
         return indenter_phi<double>(g.I, px, py, pz) <= 0.0;
     };
     constexpr int kSamples = 512;
-    const double zlo = g.ztop - clip, step = 2.0 * clip / kSamples;
-    double gap = clip;
+    const double zlo = g.ztop + lo, step = (hi - lo) / kSamples;
+    double gap = hi;
     if (inside(zlo)) {
-        gap = -clip;
+        gap = lo;
     } else {
         double a = zlo;
         for (int s = 1; s <= kSamples; ++s) {
@@ -742,7 +742,7 @@ __device__ double gap_at(const GapDev &g, double x, double y, double clip)
 // out[k][r][c] = mean of gap_at over sub x sub points spread evenly inside
 // cell (c, r) of the res x res partition of block k's top face (sub = 1: the
 // cell centre).
-__global__ void __launch_bounds__(kWG) k_indenter_gap(const GapDev *q, int n, int res, int sub, double clip,
+__global__ void __launch_bounds__(kWG) k_indenter_gap(const GapDev *q, int n, int res, int sub, double lo, double hi,
                                                       float *out)
 {
     const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(kWG) k_indenter_gap(const GapDev *q, int n, in
         for (int qx = 0; qx < sub; ++qx) {
             const double x = g.x0 + (c + (qx + 0.5) / sub) * g.wx / res;
             const double y = g.y0 + (r + (qy + 0.5) / sub) * g.wy / res;
-            acc += gap_at(g, x, y, clip);
+            acc += gap_at(g, x, y, lo, hi);
         }
     out[idx] = (float)(acc / (sub * sub));
 }
@@ -1009,10 +1009,10 @@ tacchi_status tacchi_surface_displacement(tacchi_sim *s, int32_t res, int32_t su
 }
 
 tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res,
-                                  int32_t sub, double clip, float *out, void *hip_stream)
+                                  int32_t sub, double lo, double hi, float *out, void *hip_stream)
 {
-    if (!cfgs || !poses || !out || n < 1 || res < 1 || res > 4096 || sub < 1 || sub > 16 || !(clip > 0.0) ||
-        !std::isfinite(clip))
+    if (!cfgs || !poses || !out || n < 1 || res < 1 || res > 4096 || sub < 1 || sub > 16 || !(hi > lo) ||
+        !std::isfinite(lo) || !std::isfinite(hi) || hi - lo > 1.0)
         return fail(TACCHI_E_ARG, "tacchi_indenter_gap: bad arguments");
     std::vector<GapDev> q((size_t)n);
     for (int k = 0; k < n; ++k) {
@@ -1038,7 +1038,7 @@ tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *
     hipError_t e = hipMemcpyAsync(dq, q.data(), q.size() * sizeof(GapDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_indenter_gap, dim3(grid1d((int64_t)n * res * res)), dim3(kWG), 0, st, dq, n, res, sub,
-                           clip, out);
+                           lo, hi, out);
         e = hipGetLastError();
     }
     const hipError_t ef = hipFreeAsync(dq, st);

@@ -2,14 +2,16 @@
 
 A sample is one GelSight-sized contact (indenter family, shape parameters,
 position and depth drawn from its seed) solved at lattice spacing h:
-  input  x[res][res][2]: the gap between the indenter at its final pose and
-         the undeformed top face (clipped to +-GAP_CLIP), and the press
-         depth broadcast, both in mm;
+  input  x[res][res][2]: the penetration of the indenter at its final pose
+         into the undeformed top face (the gap clamped to [-GAP_CLIP, 0]:
+         the elastomer only feels the indenter where they touch), and the
+         press depth broadcast, both in mm;
   target y[res][res][3]: the top surface's displacement (ux, uy, uz) after
          the press, in units of Y_UNIT.
 Both fields are cell means over SUB x SUB points, so an edge or a texture
 finer than a cell enters as its covered fraction rather than as an aliased
-point sample.
+point sample, and the cell mean of the penetration is also the contact term
+the network's output adds in FP32 (Net.contact_residual).
 All of it is computed by the library (gap field kernel, batched substeps,
 displacement resampling kernel); this module only batches the calls.
 """
@@ -23,7 +25,7 @@ from . import workloads as W
 from .batch import Batch
 from .sim import indenter_gap
 
-GAP_CLIP = 2e-3   # m
+GAP_CLIP = 2e-3   # m: the input is the penetration, clamped to [-GAP_CLIP, 0]
 X_UNIT = 1e-3     # inputs in mm
 Y_UNIT = 1e-4     # targets in 0.1 mm
 RES = 64
@@ -43,8 +45,8 @@ def _full(c):
 
 def inputs(contacts, res=RES, device="cuda") -> torch.Tensor:
     """[n][res][res][2] float32 surrogate inputs (gap, depth) in mm."""
-    gap = indenter_gap([c["cfg"] for c in contacts], [c["end_pose"] for c in contacts], res, GAP_CLIP, device,
-                       sub=SUB)
+    gap = indenter_gap([c["cfg"] for c in contacts], [c["end_pose"] for c in contacts], res, -GAP_CLIP, 0.0,
+                       device, sub=SUB)
     x = torch.empty(len(contacts), res, res, 2, dtype=torch.float32, device=device)
     x[..., 0] = gap / X_UNIT
     x[..., 1] = torch.tensor([c["depth"] / X_UNIT for c in contacts], dtype=torch.float32,

@@ -149,7 +149,7 @@ def lib():
         L.tacchi_surface_displacement.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32]
         L.tacchi_indenter_gap.restype = ctypes.c_int32
         L.tacchi_indenter_gap.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(Pose), ctypes.c_int32,
-                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _vp, _vp]
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp, _vp]
         L.tacchi_batch_surface_displacement.restype = ctypes.c_int32
         L.tacchi_batch_surface_displacement.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32]
         L.tacchi_last_error.restype = ctypes.c_char_p

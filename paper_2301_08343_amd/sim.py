@@ -162,10 +162,11 @@ def aos_to_soa(x, v, C, F):
             np.ascontiguousarray(np.asarray(C).reshape(n, 9).T), np.ascontiguousarray(np.asarray(F).reshape(n, 9).T))
 
 
-def indenter_gap(cfgs, poses, res: int, clip: float = 2e-3, device="cuda", sub: int = 1) -> torch.Tensor:
+def indenter_gap(cfgs, poses, res: int, lo: float = -2e-3, hi: float = 2e-3, device="cuda",
+                 sub: int = 1) -> torch.Tensor:
     """Gap fields [n][res][res] (m, float32) of each config's indenter at the
-    given pose over its block's undeformed top face, clipped to +-clip, each
-    cell the mean of sub x sub points."""
+    given pose over its block's undeformed top face, clamped to [lo, hi], each
+    cell the mean of sub x sub points (hi = 0: the penetration field)."""
     n = len(cfgs)
     carr = (N.Config * n)()
     parr = (N.Pose * n)()
@@ -173,6 +174,6 @@ def indenter_gap(cfgs, poses, res: int, clip: float = 2e-3, device="cuda", sub: 
         carr[k] = N.make_config(cfgs[k], poses[k], N.F32, 0)
         parr[k] = N.make_pose(poses[k])
     out = torch.empty(n, res, res, dtype=torch.float32, device=device)
-    N.check(N.lib().tacchi_indenter_gap(carr, parr, n, res, sub, clip, ctypes.c_void_p(out.data_ptr()),
+    N.check(N.lib().tacchi_indenter_gap(carr, parr, n, res, sub, lo, hi, ctypes.c_void_p(out.data_ptr()),
                                         ctypes.c_void_p(torch.cuda.current_stream(out.device).cuda_stream)))
     return out

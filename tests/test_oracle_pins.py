@@ -581,18 +581,19 @@ def test_gap_of_an_upright_sphere_is_its_lower_cap(oracle_lib, sub):
     ztop = cfg["block_origin"][2] + cfg["block_size"][2]
     pose = (4.6e-3, 5.4e-3, ztop - 0.7e-3, 1.0, 0.0, 0.0, 0.0)
     res, clip = 9, 1.5e-3
-    g = oracle_lib.indenter_gap(cfg, pose, res, clip, sub=sub)
-    for r in range(res):
-        for c in range(res):
-            acc = 0.0
-            for qy in range(sub):
-                for qx in range(sub):
-                    x = cfg["block_origin"][0] + (c + (qx + 0.5) / sub) * cfg["block_size"][0] / res
-                    y = cfg["block_origin"][1] + (r + (qy + 0.5) / sub) * cfg["block_size"][1] / res
-                    rho2 = (x - pose[0]) ** 2 + (y - pose[1]) ** 2
-                    exact = clip if rho2 >= R * R else pose[2] + R - math.sqrt(R * R - rho2) - ztop
-                    acc += min(max(exact, -clip), clip)
-            assert abs(g[r, c] - acc / sub ** 2) <= 1e-12
+    for hi in (clip, 0.0):  # the clamped gap, and the penetration field
+        g = oracle_lib.indenter_gap(cfg, pose, res, -clip, hi, sub=sub)
+        for r in range(res):
+            for c in range(res):
+                acc = 0.0
+                for qy in range(sub):
+                    for qx in range(sub):
+                        x = cfg["block_origin"][0] + (c + (qx + 0.5) / sub) * cfg["block_size"][0] / res
+                        y = cfg["block_origin"][1] + (r + (qy + 0.5) / sub) * cfg["block_size"][1] / res
+                        rho2 = (x - pose[0]) ** 2 + (y - pose[1]) ** 2
+                        exact = clip if rho2 >= R * R else pose[2] + R - math.sqrt(R * R - rho2) - ztop
+                        acc += min(max(exact, -clip), hi)
+                assert abs(g[r, c] - acc / sub ** 2) <= 1e-12
 
 
 def test_gap_of_a_tilted_punch_is_its_bottom_plane(oracle_lib):
@@ -605,7 +606,7 @@ def test_gap_of_a_tilted_punch_is_its_bottom_plane(oracle_lib):
     w, x_, y_, z_ = q
     nz = (2 * (x_ * z_ + w * y_), 2 * (y_ * z_ - w * x_), 1 - 2 * (x_ * x_ + y_ * y_))
     res, clip = 10, 1.5e-3
-    g = oracle_lib.indenter_gap(cfg, pose, res, clip)
+    g = oracle_lib.indenter_gap(cfg, pose, res, -clip, clip)
     checked = 0
     for r in range(res):
         for c in range(res):

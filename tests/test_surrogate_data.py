@@ -24,21 +24,23 @@ def test_gap_field_matches_oracle(oracle_lib, gpu, seed):
     draws); cell centres, and means of 3 x 3 points per cell for odd seeds."""
     c = W.gelsight_contact(seed, steps=20) if seed < 5 else W.batch_contact(seed, steps=20)
     cfg, pose = c["cfg"], c["poses"][-1]
+    # odd seeds: 3 x 3 points per cell and the penetration range [-clip, 0]
     res, clip, sub = 16, 2e-3, 1 + 2 * (seed % 2)
-    got = gpu.indenter_gap([cfg], [pose], res, clip, sub=sub)[0].cpu().double().numpy()
-    ref = oracle_lib.indenter_gap(cfg, pose, res, clip, nscan=20000 if sub == 1 else 5000, sub=sub)
+    hi = clip if sub == 1 else 0.0
+    got = gpu.indenter_gap([cfg], [pose], res, -clip, hi, sub=sub)[0].cpu().double().numpy()
+    ref = oracle_lib.indenter_gap(cfg, pose, res, -clip, hi, nscan=20000 if sub == 1 else 5000, sub=sub)
     # the kernel brackets the crossing to 2 clip / 512 / 2^40 and rounds to FP32
     err = np.abs(got - ref)
     print(f"seed {seed} shape {cfg['shape']}: max |d gap| = {err.max():.3e} m, min gap {ref.min():.3e}")
     assert np.all(err <= 1e-9 + 2.0 ** -24 * np.abs(ref))
-    assert ref.min() < clip  # the indenter is seen over the face
+    assert ref.min() < hi  # the indenter is seen over the face
 
 
 def test_gap_field_batches_many_contacts(oracle_lib, gpu):
     cs = [W.gelsight_contact(s, steps=10) for s in range(20, 26)]
-    got = gpu.indenter_gap([c["cfg"] for c in cs], [c["poses"][-1] for c in cs], 8, 1.5e-3).cpu().double().numpy()
+    got = gpu.indenter_gap([c["cfg"] for c in cs], [c["poses"][-1] for c in cs], 8, -1.5e-3, 1.5e-3).cpu().double().numpy()
     for k, c in enumerate(cs):
-        ref = oracle_lib.indenter_gap(c["cfg"], c["poses"][-1], 8, 1.5e-3)
+        ref = oracle_lib.indenter_gap(c["cfg"], c["poses"][-1], 8, -1.5e-3, 1.5e-3)
         assert np.all(np.abs(got[k] - ref) <= 1e-9 + 2.0 ** -24 * np.abs(ref))
 
 
