@@ -111,12 +111,14 @@ struct TileRegions {
         const int sy = size(ry);
         const int rx = s < sz * sy ? 0 : (s < sz * sy * (B + 1) ? 1 : 2);
         s -= sz * sy * start(rx);
-        const int sx = size(rx);
-        const int ux = s % sx, q = s / sx;
+        // region sizes are 1, B or 2: powers of two, so shifts and masks
+        const int lx = lg(rx), ly = lg(ry);
+        const int ux = s & ((1 << lx) - 1), q = s >> lx;
         x = start(rx) + ux;
-        y = start(ry) + q % sy;
-        z = start(rz) + q / sy;
+        y = start(ry) + (q & ((1 << ly) - 1));
+        z = start(rz) + (q >> ly);
     }
+    __device__ static int lg(int r) { return r == 0 ? 0 : (r == 1 ? Log2B<B>::v : 1); }
 };
 
 constexpr double kFixedUnits = 268435456.0;     // 2^28 units per particle mass and per m/dt
