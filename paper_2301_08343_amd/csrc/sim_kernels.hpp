@@ -249,10 +249,15 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     }
 }
 
+// 512 threads: the LDS tile allows three workgroups per CU, so a larger
+// workgroup is what raises the resident waves (24 per CU) that hide the
+// latency between the VALU work and the LDS atomics.
+constexpr int kP2GWG = 512;
+
 template <typename T, int B, bool FIXDT, int MODEL>
-__global__ void __launch_bounds__(kWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, T pscale, T munit, T punit)
+__global__ void __launch_bounds__(kP2GWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, T pscale, T munit, T punit)
 {
-    p2g_block<T, B, FIXDT, MODEL, kWG>(S, blockIdx.x, fix_coef, mscale, pscale, munit, punit);
+    p2g_block<T, B, FIXDT, MODEL, kP2GWG>(S, blockIdx.x, fix_coef, mscale, pscale, munit, punit);
 }
 
 // Mass and momentum of grid node (block (bx,by,bz), local (lx,ly,lz)): the sum,

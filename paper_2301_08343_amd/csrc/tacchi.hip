@@ -432,10 +432,10 @@ void launch_p2g_model(tacchi_sim *s, T fix, const P2GScales &k)
 {
     SimDev<T> &S = sdev<T>(s);
     if (s->cfg.mat.model == TACCHI_NEOHOOKEAN)
-        hipLaunchKernelGGL((k_p2g<T, B, FIX, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix, T(k.mscale),
+        hipLaunchKernelGGL((k_p2g<T, B, FIX, 0>), dim3(S.nblk), dim3(kP2GWG), 0, s->stream, S, fix, T(k.mscale),
                            T(k.pscale), T(k.munit), T(k.punit));
     else
-        hipLaunchKernelGGL((k_p2g<T, B, FIX, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, fix, T(k.mscale),
+        hipLaunchKernelGGL((k_p2g<T, B, FIX, 1>), dim3(S.nblk), dim3(kP2GWG), 0, s->stream, S, fix, T(k.mscale),
                            T(k.pscale), T(k.munit), T(k.punit));
 }
 
