@@ -83,7 +83,7 @@ def parse():
                                                         "surrogate_h0.2mm.safetensors"),
                     help="trained surrogate; its query-stream leg runs when the file exists")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--queries", type=int, default=10000)
+    ap.add_argument("--queries", type=int, default=5000)
     ap.add_argument("--plain-sample", type=int, default=512)
     return ap.parse_args()
 

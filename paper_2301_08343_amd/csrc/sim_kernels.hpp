@@ -138,10 +138,15 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     using Acc = TileAcc<T>;
     using Slot = typename Acc::Slot;
     constexpr int TB = B + 3, TN = TB * TB * TB;
-    // LDS rows padded to 12 nodes for B = 8: the 8 x 8 particle patch of a
-    // wave then hits every bank the same number of times in each atomic
-    constexpr int PX = B == 8 ? 12 : TB, TL = TB * TB * PX;
-    __shared__ Slot tile[4 * TL];
+    // LDS layout: a row (y, z) of the tile holds two channels side by side,
+    // channel 0 (or 2) at x and channel 1 (or 3) at HALF + x, and channels 2
+    // and 3 follow in a second plane of TLP slots. For B = 8 a row is 24
+    // 8-byte slots (48 banks): the four rows y..y+3 that a half wave of an
+    // 8 x 8 particle patch touches then start 16 banks apart modulo 64 and
+    // each 64-bit atomic is conflict free, where rows of 11 or 12 slots
+    // conflict two-way; the two channels per row cost no extra LDS.
+    constexpr int HALF = B == 8 ? 12 : TB, RP = 2 * HALF, TLP = TB * TB * RP;
+    __shared__ Slot tile[2 * TLP];
     // the next substep's bin counts start from zero; the force of the coming
     // grid update too
     if (threadIdx.x == 0) S.cnt_next[b] = 0;
@@ -150,7 +155,7 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     const int count = min(S.cnt_cur[b], S.cap);
     if (count == 0) return;
     const int *plist = S.perm_cur + (int64_t)b * S.cap;
-    for (int i = threadIdx.x; i < 4 * TL; i += WG) tile[i] = Slot(0);
+    for (int i = threadIdx.x; i < 2 * TLP; i += WG) tile[i] = Slot(0);
     __syncthreads();
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
@@ -165,6 +170,17 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
         T xr[3];
         rest_position(S, li0, li1, li2, xr);
         const T uu[3] = {S.u[p], S.u[N + p], S.u[2 * N + p]};
+        // A and v are loaded with u and kept there by an empty use: one
+        // memory round trip for all of the particle's state
+        T Am[9], vp[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Am[k] = S.A[k * N + p];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) vp[r] = S.v[r * N + p];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(Am[k]));
+#pragma unroll
+        for (int r = 0; r < 3; ++r) asm volatile("" ::"v"(vp[r]));
         if (!finite3(uu[0], uu[1], uu[2])) {
             atomicOr(S.err, ERR_NONFINITE);
             continue;
@@ -182,9 +198,6 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
         bspline3(f[0], wx);
         bspline3(f[1], wy);
         bspline3(f[2], wz);
-        T Am[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Am[k] = S.A[k * N + p];
         if (FIXDT) {
             T Hm[9], tau[9];
 #pragma unroll
@@ -201,7 +214,7 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
         T q[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            q[r] = pscale * (S.m * S.v[r * N + p] - (Am[r * 3 + 0] * f[0] + Am[r * 3 + 1] * f[1] + Am[r * 3 + 2] * f[2]));
+            q[r] = pscale * (S.m * vp[r] - (Am[r * 3 + 0] * f[0] + Am[r * 3 + 1] * f[1] + Am[r * 3 + 2] * f[2]));
 #pragma unroll
         for (int k = 0; k < 9; ++k) Am[k] *= pscale;
         if (Acc::kFixed) {
@@ -225,11 +238,11 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const T wt = wab * wz[c];
-                    const int li = ((l2 + c) * TB + (l1 + bb)) * PX + (l0 + a);
+                    const int li = ((l2 + c) * TB + (l1 + bb)) * RP + (l0 + a);
                     Acc::add(&tile[li], wt * m);
-                    Acc::add(&tile[TL + li], wt * (qa[0] + Am[2] * T(c)));
-                    Acc::add(&tile[2 * TL + li], wt * (qa[1] + Am[5] * T(c)));
-                    Acc::add(&tile[3 * TL + li], wt * (qa[2] + Am[8] * T(c)));
+                    Acc::add(&tile[HALF + li], wt * (qa[0] + Am[2] * T(c)));
+                    Acc::add(&tile[TLP + li], wt * (qa[1] + Am[5] * T(c)));
+                    Acc::add(&tile[TLP + HALF + li], wt * (qa[2] + Am[8] * T(c)));
                 }
             }
     }
@@ -241,11 +254,11 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
         T *d = dst + 4 * si;
         int x, y, z;
         TileRegions<B>::coords(si, x, y, z);
-        const int ls = (z * TB + y) * PX + x;
+        const int ls = (z * TB + y) * RP + x;
         d[0] = Acc::value(tile[ls]) * munit;
-        d[1] = Acc::value(tile[TL + ls]) * punit;
-        d[2] = Acc::value(tile[2 * TL + ls]) * punit;
-        d[3] = Acc::value(tile[3 * TL + ls]) * punit;
+        d[1] = Acc::value(tile[HALF + ls]) * punit;
+        d[2] = Acc::value(tile[TLP + ls]) * punit;
+        d[3] = Acc::value(tile[TLP + HALF + ls]) * punit;
     }
 }
 
@@ -265,41 +278,74 @@ __global__ void __launch_bounds__(kP2GWG) k_p2g(SimDev<T> S, T fix_coef, T mscal
 // Block c's tile spans nodes lo_c - 1 .. lo_c + B + 1, so along each axis the
 // node is covered by its own block, by the lower neighbour when l <= 1 and by
 // the upper neighbour when l = B-1. Blocks without particles wrote no tile.
-// nc27, when given, holds the particle counts of the 27 blocks around (bx,
-// by, bz) at index (oz+1)*9 + (oy+1)*3 + (ox+1) (0 outside the grid).
+// Bit (oz+1)*9 + (oy+1)*3 + (ox+1) of live27 is set when block (bx+ox,
+// by+oy, bz+oz) lies in the grid and holds particles.
+template <typename T>
+__device__ __forceinline__ uint32_t live_mask(const SimDev<T> &S, int bx, int by, int bz)
+{
+    uint32_t m = 0;
+    for (int t = 0; t < 27; ++t) {
+        const int cx = bx + t % 3 - 1, cy = by + (t / 3) % 3 - 1, cz = bz + t / 9 - 1;
+        if (cx >= 0 && cy >= 0 && cz >= 0 && cx < S.nb0 && cy < S.nb1 && cz < S.nb2 &&
+            S.cnt_cur[(cz * S.nb1 + cy) * S.nb0 + cx] > 0)
+            m |= 1u << t;
+    }
+    return m;
+}
+
 template <typename T, int B>
 __device__ __forceinline__ void gather_node(const SimDev<T> &S, int bx, int by, int bz, int lx, int ly, int lz,
-                                            T out[4], const int *nc27 = nullptr)
+                                            T out[4], uint32_t live27)
 {
     constexpr int TB = B + 3, TN = TB * TB * TB;
-    out[0] = out[1] = out[2] = out[3] = T(0);
+    // per axis at most two covering blocks, in increasing offset: (-1, 0)
+    // when l <= 1, (0, +1) when l = B-1, else (0) alone
     const int l[3] = {lx, ly, lz};
-    int lo[3], hi[3];
+    int o[3][2];
+    bool two[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        lo[a] = l[a] <= 1 ? -1 : 0;
-        hi[a] = l[a] == B - 1 ? 1 : 0;
+        const int nb = l[a] <= 1 ? -1 : (l[a] == B - 1 ? 1 : 0);
+        o[a][0] = min(nb, 0);
+        o[a][1] = max(nb, 0);
+        two[a] = nb != 0;
     }
-    for (int oz = lo[2]; oz <= hi[2]; ++oz)
-        for (int oy = lo[1]; oy <= hi[1]; ++oy)
-            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-                const int cx = bx + ox, cy = by + oy, cz = bz + oz;
-                if (nc27) {
-                    if (nc27[(oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)] == 0) continue;
-                } else {
-                    if (cx < 0 || cy < 0 || cz < 0 || cx >= S.nb0 || cy >= S.nb1 || cz >= S.nb2) continue;
-                    if (S.cnt_cur[(cz * S.nb1 + cy) * S.nb0 + cx] == 0) continue;
-                }
-                const int c = (cz * S.nb1 + cy) * S.nb0 + cx;
-                // slot of the node in block c's tile (tile origin lo_c - 1; the
-                // offset -1/0/+1 selects region 2/1/0 along each axis)
-                const int ti = TileRegions<B>::slot_of(lx - ox * B + 1, ly - oy * B + 1, lz - oz * B + 1);
-                const T *src = S.tiles + ((int64_t)c * TN + ti) * 4;
-                out[0] += src[0];
-                out[1] += src[1];
-                out[2] += src[2];
-                out[3] += src[3];
-            }
+    // all eight candidate loads are issued before the sum (one memory round
+    // trip); a candidate that does not cover the node or wrote no tile reads
+    // the node's own slot in its own block, in bounds, and is dropped
+    const int64_t own = ((int64_t)((bz * S.nb1 + by) * S.nb0 + bx) * TN +
+                         TileRegions<B>::slot_of(lx + 1, ly + 1, lz + 1)) * 4;
+    T v[8][4];
+    bool use[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+        const int ox = o[0][kx], oy = o[1][ky], oz = o[2][kz];
+        const int cx = bx + ox, cy = by + oy, cz = bz + oz;
+        const bool ok = (kx == 0 || two[0]) && (ky == 0 || two[1]) && (kz == 0 || two[2]) &&
+                        ((live27 >> ((oz + 1) * 9 + (oy + 1) * 3 + (ox + 1))) & 1u);
+        // slot of the node in block c's tile (tile origin lo_c - 1; the
+        // offset -1/0/+1 selects region 2/1/0 along each axis)
+        const int64_t at = ok ? ((int64_t)((cz * S.nb1 + cy) * S.nb0 + cx) * TN +
+                                 TileRegions<B>::slot_of(lx - ox * B + 1, ly - oy * B + 1, lz - oz * B + 1)) * 4
+                              : own;
+        const T *src = S.tiles + at;
+        v[k][0] = src[0];
+        v[k][1] = src[1];
+        v[k][2] = src[2];
+        v[k][3] = src[3];
+        use[k] = ok;
+    }
+    // summed in the fixed order z, then y, then x offset ascending
+    out[0] = out[1] = out[2] = out[3] = T(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (use[k]) {
+            out[0] += v[k][0];
+            out[1] += v[k][1];
+            out[2] += v[k][2];
+            out[3] += v[k][3];
+        }
 }
 
 // True when a G2P tile may read this block's velocities: one of the 27
@@ -351,10 +397,10 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
         nc27[t] = in ? S.cnt_cur[(cz * S.nb1 + cy) * S.nb0 + cx] : 0;
     }
     __syncthreads();
-    bool live = false;
+    uint32_t live27 = 0;
 #pragma unroll
-    for (int t = 0; t < 27; ++t) live = live || nc27[t] > 0;
-    if (!live) return;
+    for (int t = 0; t < 27; ++t) live27 |= nc27[t] > 0 ? 1u << t : 0u;
+    if (!live27) return;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const T inv_dt = T(1) / dt;
     for (int l = threadIdx.x; l < B3; l += WG) {
@@ -362,7 +408,7 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
         const int64_t addr = (int64_t)b * B3 + node_local<B>(lx, ly, lz);
         T mp[4];
-        gather_node<T, B>(S, bx, by, bz, lx, ly, lz, mp, nc27);
+        gather_node<T, B>(S, bx, by, bz, lx, ly, lz, mp, live27);
         const T m = mp[0];
         T V0 = T(0), V1 = T(0), V2 = T(0);
         if (m > S.m_floor && gx < S.g0 && gy < S.g1 && gz < S.g2) {
@@ -430,7 +476,13 @@ template <typename T, int B, int MODEL, int WG>
 __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt, T stress_coef)
 {
     constexpr int TB = B + 3, TN = TB * TB * TB;
-    __shared__ T tile[3 * TN];
+    // LDS layout: row (y, z) holds the three velocity components side by
+    // side (component r at r*TB + x). For B = 8 a row is 40 words: the eight
+    // rows of an 8 x 8 particle patch then start on distinct multiples of 8
+    // banks modulo 64 and every LDS read of the gather is conflict free,
+    // where rows of 11 words conflict.
+    constexpr int RP = B == 8 ? 40 : 3 * TB;
+    __shared__ T tile[TB * TB * RP];
     const int count = min(S.cnt_cur[b], S.cap);
     if (count == 0) return;
     const int *plist = S.perm_cur + (int64_t)b * S.cap;
@@ -438,17 +490,31 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
     // whose cell lies in the block, so their stencil base is lo-1 .. lo+B-1
     const int lo0 = bx * B - 1, lo1 = by * B - 1, lo2 = bz * B - 1;
-    for (int li = threadIdx.x; li < TN; li += WG) {
+    // every load of a thread's share of the tile is issued before the first
+    // LDS write, so the staging costs one memory round trip, not one per node
+    constexpr int NPT = (TN + WG - 1) / WG;
+    T st[NPT][3];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int li = threadIdx.x + k * WG;
         const int x = li % TB, yz = li / TB, y = yz % TB, z = yz / TB;
         const int gx = lo0 + x, gy = lo1 + y, gz = lo2 + z;
-        T a0 = T(0), a1 = T(0), a2 = T(0);
-        if ((unsigned)gx < (unsigned)S.g0 && (unsigned)gy < (unsigned)S.g1 && (unsigned)gz < (unsigned)S.g2) {
+        st[k][0] = st[k][1] = st[k][2] = T(0);
+        if (li < TN && (unsigned)gx < (unsigned)S.g0 && (unsigned)gy < (unsigned)S.g1 &&
+            (unsigned)gz < (unsigned)S.g2) {
             const T *src = S.V + 4 * node_addr<B>(S.nb0, S.nb1, gx, gy, gz);
-            a0 = src[0]; a1 = src[1]; a2 = src[2];
+            st[k][0] = src[0]; st[k][1] = src[1]; st[k][2] = src[2];
         }
-        tile[li] = a0;
-        tile[TN + li] = a1;
-        tile[2 * TN + li] = a2;
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int li = threadIdx.x + k * WG;
+        if (li < TN) {
+            const int x = li % TB, yz = li / TB;
+            tile[yz * RP + x] = st[k][0];
+            tile[yz * RP + TB + x] = st[k][1];
+            tile[yz * RP + 2 * TB + x] = st[k][2];
+        }
     }
     __syncthreads();
     const int64_t N = S.Ns;
@@ -463,6 +529,16 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
             T xr[3];
             rest_position(S, li0, li1, li2, xr);
             T uu[3] = {S.u[p], S.u[N + p], S.u[2 * N + p]};
+            // H is loaded with u, before the stores below: the compiler
+            // cannot move loads across stores to other arrays, and the
+            // stores would otherwise add a second memory round trip
+            T h[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) h[k] = S.H[k * N + p];
+            // an empty use keeps the H loads here, next to the u loads (one
+            // wait for both), instead of sunk to the F update
+#pragma unroll
+            for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(h[k]));
             int base[3] = {0, 0, 0};
             T f[3];
             const bool fin = finite3(uu[0], uu[1], uu[2]);
@@ -482,8 +558,8 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
                 bspline3(f[2], wz);
                 // velocities relative to the stencil centre keep the affine
                 // sums well conditioned in FP32
-                const int lc = ((l2 + 1) * TB + (l1 + 1)) * TB + (l0 + 1);
-                const T vr[3] = {tile[lc], tile[TN + lc], tile[2 * TN + lc]};
+                const int lc = ((l2 + 1) * TB + (l1 + 1)) * RP + (l0 + 1);
+                const T vr[3] = {tile[lc], tile[TB + lc], tile[2 * TB + lc]};
                 // The weights are a tensor product, so the sums over the 27
                 // nodes of w D, w D a, w D b, w D c (D = V - vr, offsets a, b,
                 // c along x, y, z) are taken one axis at a time: over c, then
@@ -497,10 +573,10 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
                         T t[3], tz[3];
 #pragma unroll
                         for (int bb = 0; bb < 3; ++bb) {
-                            const int li = ((l2 * TB + (l1 + bb)) * TB + l0 + a) + r * TN;
+                            const int li = ((l2 * TB + (l1 + bb)) * RP + l0 + a) + r * TB;
                             const T d0 = tile[li] - vr[r];
-                            const T d1 = tile[li + TB * TB] - vr[r];
-                            const T d2 = tile[li + 2 * TB * TB] - vr[r];
+                            const T d1 = tile[li + TB * RP] - vr[r];
+                            const T d2 = tile[li + 2 * TB * RP] - vr[r];
                             t[bb] = wz[0] * d0 + wz[1] * d1 + wz[2] * d2;
                             tz[bb] = wz[1] * d1 + T(2) * wz[2] * d2;
                         }
@@ -537,8 +613,7 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
                 T Hn[9];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const T h0 = S.H[(0 * 3 + c) * N + p], h1 = S.H[(1 * 3 + c) * N + p],
-                            h2 = S.H[(2 * 3 + c) * N + p];
+                    const T h0 = h[0 * 3 + c], h1 = h[1 * 3 + c], h2 = h[2 * 3 + c];
 #pragma unroll
                     for (int r = 0; r < 3; ++r) {
                         const T hrc = r == 0 ? h0 : (r == 1 ? h1 : h2);
@@ -777,7 +852,8 @@ __global__ void __launch_bounds__(kWG) k_read_grid(SimDev<T> S, int which, T sca
     const int64_t a = node_addr<B>(S.nb0, S.nb1, gx, gy, gz);
     T mp[4];
     constexpr int LB0 = Log2B<B>::v;
-    gather_node<T, B>(S, gx >> LB0, gy >> LB0, gz >> LB0, gx & (B - 1), gy & (B - 1), gz & (B - 1), mp);
+    const int bx = gx >> LB0, by = gy >> LB0, bz = gz >> LB0;
+    gather_node<T, B>(S, bx, by, bz, gx & (B - 1), gy & (B - 1), gz & (B - 1), mp, live_mask(S, bx, by, bz));
     const T *src = which == 0 ? mp : S.V + 4 * a;
     if (M && which == 0) M[q] = src[0];
     // velocities exist only in blocks the last grid update visited (a block
