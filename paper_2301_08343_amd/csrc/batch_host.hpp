@@ -183,9 +183,14 @@ template <int B, int MODEL, int WG>
 void launch_group_phase(tacchi_batch *bt, const tacchi_batch::Group &g, int phase, int parity, int bump)
 {
     const dim3 grid(g.count), blk(WG);
+    // P2G at B = 8 always runs kP2GWG-thread workgroups, as in the
+    // single-contact path: its LDS tile allows few workgroups per CU, so the
+    // resident waves come from the workgroup size (the tuned size applies to
+    // the grid update and G2P)
+    constexpr int P2G_WG = B == 8 ? kP2GWG : WG;
     if (phase == 0)
-        hipLaunchKernelGGL((k_p2g_batch<B, MODEL, WG>), grid, blk, 0, bt->stream, g.items, bt->descs[parity],
-                           bt->consts, bt->step, bump);
+        hipLaunchKernelGGL((k_p2g_batch<B, MODEL, P2G_WG>), grid, dim3(P2G_WG), 0, bt->stream, g.items,
+                           bt->descs[parity], bt->consts, bt->step, bump);
     else if (phase == 1)
         hipLaunchKernelGGL((k_grid_batch<B, WG>), grid, blk, 0, bt->stream, g.items, bt->descs[parity], bt->consts,
                            bt->itab, bt->nsteps, bt->step);

@@ -111,6 +111,47 @@ def serve_benchmark(net, ftr, thr, h, queries, plain_sample, log=log):
     return rep
 
 
+def resolution_check(weights, n, h_full=0.1e-3, gen_batch=64, log=log):
+    """The data spacing's own error: the held-out contacts 50000 .. 50000+n-1
+    solved at the surrogate's data spacing and again at h_full (the 0.1 mm
+    lattice of the benchmark press: 1.6M particles, 2000 substeps), both
+    resampled to the same top-surface cells. Reports the height RMSE between
+    the two solves (the resolution error of the training data), and the
+    surrogate's error against each."""
+    net, meta = load_compact(weights, batch=256)
+    h = meta["h_m"]
+    seeds = list(range(HELDOUT_SEED0, HELDOUT_SEED0 + n))
+    groups = [s % 5 for s in seeds]
+    t = time.perf_counter()
+    x, y_c = D.generate(seeds, h=h, batch=256, log=log)
+    torch.cuda.synchronize()
+    t_c = time.perf_counter() - t
+    t = time.perf_counter()
+    x_f, y_f = D.generate(seeds, h=h_full, batch=gen_batch, log=log)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t
+    cf = D.contacts_for([seeds[0]], h_full, full=False)[0]
+    um = D.Y_UNIT * 1e6
+    dz = TR.per_sample_rmse(y_c, y_f, 2).cpu() * um
+    g = torch.as_tensor(groups)
+    rep = {
+        "samples": n, "h_data_m": h, "h_full_m": h_full,
+        "full_particles_per_contact": cf["particles"], "full_substeps": cf["steps"],
+        "full_solve_seconds": t_f, "data_solve_seconds": t_c,
+        "full_particle_substeps_per_s": n * cf["particles"] * cf["steps"] / t_f,
+        # the inputs do not depend on the lattice spacing: the same indenter
+        # pose over the same top face
+        "input_max_abs_diff_mm": float((x - x_f).abs().max()),
+        "data_vs_full_height_rmse_um": float((dz ** 2).mean().sqrt()),
+        "data_vs_full_height_rmse_um_by_group": {
+            str(int(k)): float((dz[g == k] ** 2).mean().sqrt()) for k in torch.unique(g)},
+        "surrogate_vs_data": TR.evaluate(net, x, y_c, groups=groups),
+        "surrogate_vs_full": TR.evaluate(net, x, y_f, groups=groups),
+    }
+    log(f"resolution: {json.dumps(rep)}")
+    return rep
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=16384)
@@ -124,10 +165,21 @@ def main(argv=None):
     ap.add_argument("--gen-batch", type=int, default=256)
     ap.add_argument("--no-symmetry", action="store_true", help="train without the mirror/transpose copies")
     ap.add_argument("--no-residual", action="store_true", help="no FP32 contact term on the output")
+    ap.add_argument("--resolution-check", type=int, default=0, metavar="N",
+                    help="only compare N held-out solves at the data spacing with 0.1 mm solves "
+                         "(and the --weights model against both)")
+    ap.add_argument("--weights", default=None, help="compact weights for --resolution-check")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     rep = {"args": vars(a)}
+    if a.resolution_check > 0:
+        if not a.weights:
+            ap.error("--resolution-check needs --weights")
+        rep["resolution"] = resolution_check(a.weights, a.resolution_check, gen_batch=min(a.gen_batch, 64))
+        with open(os.path.join(a.out, "resolution.json"), "w") as f:
+            json.dump(rep, f, indent=1)
+        return 0
 
     t = time.perf_counter()
     xtr, ytr = D.generate(range(a.train), h=a.h, batch=a.gen_batch, log=log)
