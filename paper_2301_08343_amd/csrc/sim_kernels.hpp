@@ -53,12 +53,10 @@ __global__ void __launch_bounds__(kWG) k_bin(SimDev<T> S)
 // depend on the order of the atomics; gfx950 also executes ds_add_u64 about
 // 25x faster than ds_add_f32. Each contribution is below 2^31 units (checked
 // per particle: 8 cells per substep, far beyond the CFL limit), so it converts
-// with one round-to-nearest FP32 -> int32 instruction and is sign-extended
-// into the 64-bit sum (mass, never negative, is zero-extended). Rounding (not
-// truncation) keeps the quantisation error unbiased: truncation shrinks every
-// contribution toward zero, a bias that a steady configuration repeats every
-// substep; ties (exact halves) round up, a bias of at most half a unit on a
-// set of measure zero.
+// with an FP32 round-to-nearest-even and one FP32 -> int32 instruction and is
+// sign-extended into the 64-bit sum. Rounding (not truncation) keeps the
+// quantisation error unbiased: truncation shrinks every contribution toward
+// zero, a bias that a steady configuration repeats every substep.
 template <typename T>
 struct TileAcc;
 
@@ -67,31 +65,14 @@ struct TileAcc<double> {
     using Slot = double;
     static constexpr bool kFixed = false;
     __device__ static void add(Slot *s, double v) { atomicAdd(s, v); }
-    __device__ static void add_nonneg(Slot *s, double v) { atomicAdd(s, v); }
     __device__ static double value(Slot s) { return s; }
 };
-
-// floor(v + 0.5) in one instruction (round to nearest, ties up); |v| < 2^31
-__device__ __forceinline__ int round_half_up(float v)
-{
-    int r;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-    return r;
-}
 
 template <>
 struct TileAcc<float> {
     using Slot = unsigned long long;
     static constexpr bool kFixed = true;
-    __device__ static void add(Slot *s, float v)
-    {
-        atomicAdd(s, (unsigned long long)(long long)round_half_up(v));
-    }
-    // v >= 0 (mass): the rounded value needs no sign extension
-    __device__ static void add_nonneg(Slot *s, float v)
-    {
-        atomicAdd(s, (unsigned long long)(unsigned)round_half_up(v));
-    }
+    __device__ static void add(Slot *s, float v) { atomicAdd(s, (unsigned long long)(long long)(int)rintf(v)); }
     __device__ static float value(Slot s) { return (float)(double)(long long)s; }
 };
 
@@ -258,7 +239,7 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
                 for (int c = 0; c < 3; ++c) {
                     const T wt = wab * wz[c];
                     const int li = ((l2 + c) * TB + (l1 + bb)) * RP + (l0 + a);
-                    Acc::add_nonneg(&tile[li], wt * m);
+                    Acc::add(&tile[li], wt * m);
                     Acc::add(&tile[HALF + li], wt * (qa[0] + Am[2] * T(c)));
                     Acc::add(&tile[TLP + li], wt * (qa[1] + Am[5] * T(c)));
                     Acc::add(&tile[TLP + HALF + li], wt * (qa[2] + Am[8] * T(c)));
@@ -477,16 +458,10 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
     }
 }
 
-// Single-contact grid update and G2P at B = 8: 512-thread workgroups, one
-// node (grid) or about one particle (G2P) per thread, so a block makes one
-// pass of memory round trips instead of two.
-template <int B>
-constexpr int block_wg() { return B == 8 ? 512 : kWG; }
-
 template <typename T, int B>
-__global__ void __launch_bounds__(block_wg<B>()) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
+__global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
 {
-    grid_block<T, B, block_wg<B>()>(S, blockIdx.x, I, dt);
+    grid_block<T, B, kWG>(S, blockIdx.x, I, dt);
 }
 
 // ---------------------------------------------------------------- G2P
@@ -664,9 +639,9 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
 }
 
 template <typename T, int B, int MODEL>
-__global__ void __launch_bounds__(block_wg<B>()) k_g2p(SimDev<T> S, T dt, T stress_coef)
+__global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
 {
-    g2p_block<T, B, MODEL, block_wg<B>()>(S, blockIdx.x, dt, stress_coef);
+    g2p_block<T, B, MODEL, kWG>(S, blockIdx.x, dt, stress_coef);
 }
 
 // ---------------------------------------------------------------- outputs

@@ -471,9 +471,9 @@ tacchi_status do_grid(tacchi_sim *s, const double pose_end[7], double dt)
     IndenterDev<double> I = make_indenter<double>(s->cfg, s->pose, pose_end, dt);
     KernelTimer t(s, KC_GRID);
     if (s->d.B == 4)
-        hipLaunchKernelGGL((k_grid<T, 4>), dim3(S.nblk), dim3(block_wg<4>()), 0, s->stream, S, I, T(dt));
+        hipLaunchKernelGGL((k_grid<T, 4>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, I, T(dt));
     else
-        hipLaunchKernelGGL((k_grid<T, 8>), dim3(S.nblk), dim3(block_wg<8>()), 0, s->stream, S, I, T(dt));
+        hipLaunchKernelGGL((k_grid<T, 8>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, I, T(dt));
     TC_LAUNCHED();
     return TACCHI_OK;
 }
@@ -487,14 +487,14 @@ tacchi_status do_g2p(tacchi_sim *s, double dt)
     KernelTimer t(s, KC_G2P);
     if (s->d.B == 4) {
         if (neo)
-            hipLaunchKernelGGL((k_g2p<T, 4, 0>), dim3(S.nblk), dim3(block_wg<4>()), 0, s->stream, S, T(dt), coef);
+            hipLaunchKernelGGL((k_g2p<T, 4, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
         else
-            hipLaunchKernelGGL((k_g2p<T, 4, 1>), dim3(S.nblk), dim3(block_wg<4>()), 0, s->stream, S, T(dt), coef);
+            hipLaunchKernelGGL((k_g2p<T, 4, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
     } else {
         if (neo)
-            hipLaunchKernelGGL((k_g2p<T, 8, 0>), dim3(S.nblk), dim3(block_wg<8>()), 0, s->stream, S, T(dt), coef);
+            hipLaunchKernelGGL((k_g2p<T, 8, 0>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
         else
-            hipLaunchKernelGGL((k_g2p<T, 8, 1>), dim3(S.nblk), dim3(block_wg<8>()), 0, s->stream, S, T(dt), coef);
+            hipLaunchKernelGGL((k_g2p<T, 8, 1>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, T(dt), coef);
     }
     TC_LAUNCHED();
     return TACCHI_OK;
