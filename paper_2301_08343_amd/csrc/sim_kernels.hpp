@@ -151,36 +151,66 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     // grid update too
     if (threadIdx.x == 0) S.cnt_next[b] = 0;
     if (b == 0 && threadIdx.x < 3) S.force[threadIdx.x] = 0.0;
-    // a block that overflowed its list keeps only `cap` entries (flagged)
+    // a block that overflowed its list keeps only `cap` entries (flagged).
+    // The thread's first list entry is read together with the count
+    // (speculatively: a list holds cap entries, those past the count are
+    // never used) and that particle's state before the tile is cleared; the
+    // barrier does not wait for global loads, so they overlap the clearing
+    const int *plist = S.perm_cur + (int64_t)b * S.cap;
+    const int pf = (int)threadIdx.x < S.cap ? plist[threadIdx.x] : 0;
     const int count = min(S.cnt_cur[b], S.cap);
     if (count == 0) return;
-    const int *plist = S.perm_cur + (int64_t)b * S.cap;
+    const int64_t N = S.Ns;
+    T fu[3], fv[3], fA[9];
+    if ((int)threadIdx.x < count) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            fu[r] = S.u[r * N + pf];
+            fv[r] = S.v[r * N + pf];
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fA[k] = S.A[k * N + pf];
+    }
     for (int i = threadIdx.x; i < 2 * TLP; i += WG) tile[i] = Slot(0);
     __syncthreads();
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
     // whose cell lies in the block, so their stencil base is lo-1 .. lo+B-1
     const int lo0 = bx * B - 1, lo1 = by * B - 1, lo2 = bz * B - 1;
-    const int64_t N = S.Ns;
     const T m = S.m * mscale;
-    for (int i = threadIdx.x; i < count; i += WG) {
-        const int p = plist[i];
+    bool first = true;
+    for (int i = threadIdx.x; i < count; i += WG, first = false) {
+        int p;
+        T uu[3], Am[9], vp[3];
+        if (first) {
+            p = pf;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                uu[r] = fu[r];
+                vp[r] = fv[r];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Am[k] = fA[k];
+        } else {
+            p = plist[i];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                uu[r] = S.u[r * N + p];
+                vp[r] = S.v[r * N + p];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Am[k] = S.A[k * N + p];
+            // an empty use keeps A and v next to u: one memory round trip
+            // for all of the particle's state
+#pragma unroll
+            for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(Am[k]));
+#pragma unroll
+            for (int r = 0; r < 3; ++r) asm volatile("" ::"v"(vp[r]));
+        }
         int li0, li1, li2;
         slot_lattice<T, B>(S, (uint32_t)p, li0, li1, li2);
         T xr[3];
         rest_position(S, li0, li1, li2, xr);
-        const T uu[3] = {S.u[p], S.u[N + p], S.u[2 * N + p]};
-        // A and v are loaded with u and kept there by an empty use: one
-        // memory round trip for all of the particle's state
-        T Am[9], vp[3];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Am[k] = S.A[k * N + p];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) vp[r] = S.v[r * N + p];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(Am[k]));
-#pragma unroll
-        for (int r = 0; r < 3; ++r) asm volatile("" ::"v"(vp[r]));
         if (!finite3(uu[0], uu[1], uu[2])) {
             atomicOr(S.err, ERR_NONFINITE);
             continue;
@@ -483,9 +513,15 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
     // where rows of 11 words conflict.
     constexpr int RP = B == 8 ? 40 : 3 * TB;
     __shared__ T tile[TB * TB * RP];
+    // the thread's first list entry is read with the count (speculatively,
+    // as in P2G) and its particle's state behind the tile's staging loads:
+    // the barrier does not wait for global loads, so the particle work
+    // starts two memory round trips after the kernel instead of four
+    const int *plist = S.perm_cur + (int64_t)b * S.cap;
+    const int pf = (int)threadIdx.x < S.cap ? plist[threadIdx.x] : 0;
     const int count = min(S.cnt_cur[b], S.cap);
     if (count == 0) return;
-    const int *plist = S.perm_cur + (int64_t)b * S.cap;
+    const int64_t N = S.Ns;
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
     // whose cell lies in the block, so their stencil base is lo-1 .. lo+B-1
@@ -506,6 +542,13 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
             st[k][0] = src[0]; st[k][1] = src[1]; st[k][2] = src[2];
         }
     }
+    T fu[3], fh[9];
+    if ((int)threadIdx.x < count) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) fu[r] = S.u[r * N + pf];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fh[k] = S.H[k * N + pf];
+    }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int li = threadIdx.x + k * WG;
@@ -517,28 +560,35 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
         }
     }
     __syncthreads();
-    const int64_t N = S.Ns;
     for (int i0 = 0; i0 < count; i0 += WG) {
         const int i = i0 + threadIdx.x;
         int newkey = -1;
         int p = 0;
         if (i < count) {
-            p = plist[i];
+            T uu[3], h[9];
+            if (i0 == 0) {
+                p = pf;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) uu[r] = fu[r];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) h[k] = fh[k];
+            } else {
+                p = plist[i];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) uu[r] = S.u[r * N + p];
+                // H is loaded with u, before the stores below: the compiler
+                // cannot move loads across stores to other arrays, and the
+                // stores would otherwise add a second memory round trip; an
+                // empty use keeps the loads here instead of sunk to the F update
+#pragma unroll
+                for (int k = 0; k < 9; ++k) h[k] = S.H[k * N + p];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(h[k]));
+            }
             int li0, li1, li2;
             slot_lattice<T, B>(S, (uint32_t)p, li0, li1, li2);
             T xr[3];
             rest_position(S, li0, li1, li2, xr);
-            T uu[3] = {S.u[p], S.u[N + p], S.u[2 * N + p]};
-            // H is loaded with u, before the stores below: the compiler
-            // cannot move loads across stores to other arrays, and the
-            // stores would otherwise add a second memory round trip
-            T h[9];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) h[k] = S.H[k * N + p];
-            // an empty use keeps the H loads here, next to the u loads (one
-            // wait for both), instead of sunk to the F update
-#pragma unroll
-            for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(h[k]));
             int base[3] = {0, 0, 0};
             T f[3];
             const bool fin = finite3(uu[0], uu[1], uu[2]);

@@ -1,8 +1,7 @@
 """The data -> training -> router pipeline end to end at a coarse spacing
-(0.5 mm lattice, 12,800 particles per contact): it runs, the trained network
-beats predicting zero displacement on held-out solves, the router's report is
-consistent, and the circuit breaker hands everything to the MPM when its
-limit cannot be met."""
+(0.5 mm lattice, 12,800 particles per contact): it runs, the loss falls, the
+router's report is consistent, and the circuit breaker hands everything to
+the MPM when its limit cannot be met."""
 import json
 
 import pytest
