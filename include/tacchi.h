@@ -132,6 +132,22 @@ tacchi_status tacchi_step(tacchi_sim *sim, const tacchi_pose *pose_end, double d
 /* `n` substeps of size dt; substep s ends at poses[s]. Asynchronous. */
 tacchi_status tacchi_run(tacchi_sim *sim, const tacchi_pose *poses, int32_t n, double dt);
 
+/* The scripted press with a terminal condition on the contact force
+ * (Sec. III-C: the simulation ends when a terminal condition is met): runs
+ * substeps as tacchi_run does, poses[s] ending substep s, until the z
+ * component of the contact force on the indenter (tacchi_indenter_force)
+ * after a substep is >= fz_limit [N] (+inf: never; -inf: after the first
+ * substep; NaN is rejected), or until all n substeps have run. The
+ * test is made on the device after every substep, so the n substeps are
+ * queued without a host round trip per substep; once the limit is reached
+ * the remaining queued substeps do nothing. *steps_done receives the number
+ * of substeps that ran (the stopping one included); the simulation is left
+ * after that substep, at pose poses[*steps_done - 1], ready for further
+ * steps. Must be called between substeps (not after tacchi_p2g or
+ * tacchi_grid_update). Synchronises; reports the device error word. */
+tacchi_status tacchi_run_until_force(tacchi_sim *sim, const tacchi_pose *poses, int32_t n, double dt,
+                                     double fz_limit, int32_t *steps_done);
+
 /* The three phases of tacchi_step, for callers that inspect the grid:
  * tacchi_p2g (sort + particle-to-grid), tacchi_grid_update (grid velocity and
  * contact toward `pose_end`), tacchi_g2p (grid-to-particle; commits
@@ -176,6 +192,18 @@ tacchi_status tacchi_render(tacchi_sim *sim, const tacchi_render_params *rp, flo
  * stream; otherwise it synchronises and reports the device error word. */
 tacchi_status tacchi_surface_displacement(tacchi_sim *sim, int32_t res, int32_t sub, float *out,
                                           int32_t out_on_device);
+
+/* Markers (Sec. VI: marker motion is simulated by recording the motion of
+ * the surface particles at the markers' positions): for n marker positions
+ * xy[k] = (x, y) on the undeformed top face (world metres, host memory,
+ * copied; each must lie on the face, else TACCHI_E_ARG), out[k][a] is the
+ * displacement x - X of the top surface at that point (metres, simulation
+ * precision, n x 3): bilinear between the four surrounding top-layer
+ * particles (particle i at (i + 1/2) h), a point on the half-cell rim outside
+ * the outermost particle centres taking the edge value. 1 <= n <= 2^24.
+ * With out_on_device != 0 out is device memory; the call synchronises either
+ * way and reports the device error word. */
+tacchi_status tacchi_markers(tacchi_sim *sim, const double *xy, int32_t n, void *out, int32_t out_on_device);
 
 /* Gap field of an indenter over the undeformed top face, the geometric input
  * of the learned surrogate: for n configurations and poses (indenter frame ->

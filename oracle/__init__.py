@@ -192,6 +192,22 @@ class OracleSim:
             if st != 0:
                 raise RuntimeError(f"oracle step {k} failed with status {st}")
 
+    def run_until_force(self, poses, dt, fz_limit, start=0, stop=None):
+        """Sec. III-C's terminal condition on the contact force: advance
+        through poses[start+1 ..] one substep at a time and stop after the
+        first substep whose contact force on the indenter has a z component
+        >= fz_limit; returns the number of substeps run."""
+        stop = len(poses) - 1 if stop is None else stop
+        done = 0
+        for k in range(start, stop):
+            st = self.step(poses[k + 1], dt)
+            if st != 0:
+                raise RuntimeError(f"oracle step {k} failed with status {st}")
+            done += 1
+            if self.force()[2] >= fz_limit:
+                break
+        return done
+
     def grid(self):
         M = np.zeros(self.nn); P = np.zeros((self.nn, 3)); V = np.zeros((self.nn, 3))
         lib().orc_get_grid(self._h, _ptr(M), _ptr(P), _ptr(V))
@@ -293,6 +309,35 @@ def indenter_gap(cfg: dict, pose, res: int, lo: float, hi: float, nscan: int = 2
                     acc += min(max(z - ztop, lo), hi)
             out[r, c] = acc / (sub * sub)
     return out
+
+
+def markers(cfg: dict, x, xy):
+    """[n][3] displacement of the top surface at marker positions xy [n][2]
+    (world metres on the undeformed top face). Sec. VI: a marker moves with
+    the surface particles at its position; here the displacement x - X is
+    interpolated bilinearly between the four top-layer particles around the
+    point (particle i at (i + 1/2) h), a point on the half-cell rim outside
+    the outermost particle centres taking the edge value."""
+    n0, n1, n2 = cfg["n"]
+    h = [cfg["block_size"][a] / cfg["n"][a] for a in range(3)]
+    o = cfg["block_origin"]
+    top = np.asarray(x, dtype=np.float64).reshape(n2, n1, n0, 3)[n2 - 1]
+    ii, jj = np.meshgrid(np.arange(n0), np.arange(n1), indexing="xy")
+    rest = np.stack([o[0] + (ii + 0.5) * h[0], o[1] + (jj + 0.5) * h[1],
+                     np.full(ii.shape, o[2] + (n2 - 0.5) * h[2])], axis=-1)
+    u = top - rest  # [n1][n0][3]
+    out = []
+    for px, py in np.asarray(xy, dtype=np.float64).reshape(-1, 2):
+        if not (o[0] <= px <= o[0] + cfg["block_size"][0] and o[1] <= py <= o[1] + cfg["block_size"][1]):
+            raise ValueError("marker outside the top face")
+        si = min(max((px - o[0]) / h[0] - 0.5, 0.0), n0 - 1.0)
+        sj = min(max((py - o[1]) / h[1] - 0.5, 0.0), n1 - 1.0)
+        i0 = min(int(np.floor(si)), n0 - 2)
+        j0 = min(int(np.floor(sj)), n1 - 2)
+        tx, ty = si - i0, sj - j0
+        out.append((1 - tx) * (1 - ty) * u[j0, i0] + tx * (1 - ty) * u[j0, i0 + 1]
+                   + (1 - tx) * ty * u[j0 + 1, i0] + tx * ty * u[j0 + 1, i0 + 1])
+    return np.array(out)
 
 
 def surface_displacement(cfg: dict, x, res: int, sub: int = 1):

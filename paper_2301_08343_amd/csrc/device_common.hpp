@@ -85,6 +85,7 @@ struct SimDev {
     int *err;
     double *force;         // [3] contact reaction on the indenter [N]
     unsigned int *fallback;// count of FP64 polar recomputations
+    const int *stop;       // force-terminated runs: while *stop != 0 the substep kernels do nothing (else null)
 };
 
 // Rigid indenter for one substep: shape, its pose at the start of the

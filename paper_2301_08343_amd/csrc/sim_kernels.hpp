@@ -147,6 +147,8 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     // conflict two-way; the two channels per row cost no extra LDS.
     constexpr int HALF = B == 8 ? 12 : TB, RP = 2 * HALF, TLP = TB * TB * RP;
     __shared__ Slot tile[2 * TLP];
+    // a force-terminated run that has stopped skips its remaining substeps
+    if (S.stop && *S.stop) return;
     // the next substep's bin counts start from zero; the force of the coming
     // grid update too
     if (threadIdx.x == 0) S.cnt_next[b] = 0;
@@ -417,6 +419,7 @@ template <typename T, int B, int WG>
 __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, const IndenterDev<double> &I, T dt)
 {
     constexpr int B3 = B * B * B;
+    if (S.stop && *S.stop) return;
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     // particle counts of the 27 surrounding blocks, loaded once per workgroup
     __shared__ int nc27[27];
@@ -517,6 +520,7 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
     // as in P2G) and its particle's state behind the tile's staging loads:
     // the barrier does not wait for global loads, so the particle work
     // starts two memory round trips after the kernel instead of four
+    if (S.stop && *S.stop) return;
     const int *plist = S.perm_cur + (int64_t)b * S.cap;
     const int pf = (int)threadIdx.x < S.cap ? plist[threadIdx.x] : 0;
     const int count = min(S.cnt_cur[b], S.cap);
@@ -714,13 +718,48 @@ __global__ void __launch_bounds__(kWG) k_heightmap(SimDev<T> S, T origin_z, T dx
 // q = 0 .. sub-1, per axis), of the displacement interpolated bilinearly
 // between the top-layer particles (particle i sits at (i + 1/2) h; clamped at
 // the border). sub = 1 samples the cell centre.
+// Displacement (grid units) of the top surface at fractional lattice
+// coordinates (si, sj) of the top layer, si in [0, n0-1], sj in [0, n1-1]:
+// bilinear in the four surrounding top-layer particles.
+template <typename T, int B>
+__device__ __forceinline__ void top_disp_at(const SimDev<T> &S, T si, T sj, T out[3])
+{
+    const int k = S.n2 - 1;
+    int i0 = (int)tfloor<T>(si), j0 = (int)tfloor<T>(sj);
+    i0 = i0 > S.n0 - 2 ? S.n0 - 2 : i0;
+    j0 = j0 > S.n1 - 2 ? S.n1 - 2 : j0;
+    const T tx = si - T(i0), ty = sj - T(j0);
+    const uint32_t s00 = lattice_slot<T, B>(S, i0, j0, k), s10 = lattice_slot<T, B>(S, i0 + 1, j0, k);
+    const uint32_t s01 = lattice_slot<T, B>(S, i0, j0 + 1, k), s11 = lattice_slot<T, B>(S, i0 + 1, j0 + 1, k);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T *u = S.u + (size_t)a * S.Ns;
+        const T lo = u[s00] + tx * (u[s10] - u[s00]);
+        const T hi = u[s01] + tx * (u[s11] - u[s01]);
+        out[a] = lo + ty * (hi - lo);
+    }
+}
+
+// Markers (surface points tracked through the press): q holds n fractional
+// top-layer lattice coordinates (si, sj), already clamped; out [n][3] the
+// displacement in metres.
+template <typename T, int B>
+__global__ void __launch_bounds__(kWG) k_markers(SimDev<T> S, const T *q, int n, T dx, T *out)
+{
+    const int idx = blockIdx.x * kWG + threadIdx.x;
+    if (idx >= n) return;
+    T d[3];
+    top_disp_at<T, B>(S, q[2 * idx], q[2 * idx + 1], d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[(size_t)idx * 3 + a] = dx * d[a];
+}
+
 template <typename T, int B>
 __global__ void __launch_bounds__(kWG) k_surface_disp(SimDev<T> S, T dx, int res, int sub, float *out)
 {
     const int idx = blockIdx.x * kWG + threadIdx.x;
     if (idx >= res * res) return;
     const int r = idx / res, c = idx - r * res;
-    const int k = S.n2 - 1;
     T acc[3] = {T(0), T(0), T(0)};
     for (int qy = 0; qy < sub; ++qy)
         for (int qx = 0; qx < sub; ++qx) {
@@ -728,19 +767,10 @@ __global__ void __launch_bounds__(kWG) k_surface_disp(SimDev<T> S, T dx, int res
             T sj = (T(r) + (T(qy) + T(0.5)) / T(sub)) * T(S.n1) / T(res) - T(0.5);
             si = si < T(0) ? T(0) : (si > T(S.n0 - 1) ? T(S.n0 - 1) : si);
             sj = sj < T(0) ? T(0) : (sj > T(S.n1 - 1) ? T(S.n1 - 1) : sj);
-            int i0 = (int)tfloor<T>(si), j0 = (int)tfloor<T>(sj);
-            i0 = i0 > S.n0 - 2 ? S.n0 - 2 : i0;
-            j0 = j0 > S.n1 - 2 ? S.n1 - 2 : j0;
-            const T tx = si - T(i0), ty = sj - T(j0);
-            const uint32_t s00 = lattice_slot<T, B>(S, i0, j0, k), s10 = lattice_slot<T, B>(S, i0 + 1, j0, k);
-            const uint32_t s01 = lattice_slot<T, B>(S, i0, j0 + 1, k), s11 = lattice_slot<T, B>(S, i0 + 1, j0 + 1, k);
+            T d[3];
+            top_disp_at<T, B>(S, si, sj, d);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const T *u = S.u + (size_t)a * S.Ns;
-                const T lo = u[s00] + tx * (u[s10] - u[s00]);
-                const T hi = u[s01] + tx * (u[s11] - u[s01]);
-                acc[a] += lo + ty * (hi - lo);
-            }
+            for (int a = 0; a < 3; ++a) acc[a] += d[a];
         }
     const T w = dx / T(sub * sub);
 #pragma unroll
@@ -878,6 +908,19 @@ __global__ void __launch_bounds__(kWG) k_init_particles(SimDev<T> S)
     for (int q = 0; q < 9; ++q) {
         S.H[q * Ns + s] = T(0);
         S.A[q * Ns + s] = T(0);
+    }
+}
+
+// After each substep of a force-terminated run (the terminal condition of
+// Sec. III-C, on the contact force): flag[1] counts the substeps that ran,
+// and flag[0] is raised once the z component of the contact force on the
+// indenter reaches fz_limit, which makes the later substeps' kernels return
+// at once. One thread.
+__global__ void k_stop_check(int *flag, const double *force, double fz_limit)
+{
+    if (threadIdx.x == 0 && flag[0] == 0) {
+        flag[1] += 1;
+        if (force[2] >= fz_limit) flag[0] = 1;
     }
 }
 

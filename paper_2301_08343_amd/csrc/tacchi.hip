@@ -60,7 +60,7 @@ struct Derived {
 };
 
 struct Layout {
-    size_t u, v, H, A, cnt[2], perm[2], tiles, V, err, force, fallback, hmap, total;
+    size_t u, v, H, A, cnt[2], perm[2], tiles, V, err, force, fallback, stop, hmap, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -89,6 +89,7 @@ Layout make_layout(const Derived &d)
     L.err = take(64);
     L.force = take(64);
     L.fallback = take(64);
+    L.stop = take(64);
     L.hmap = take((size_t)d.n[0] * d.n[1] * es);
     L.total = o;
     return L;
@@ -271,6 +272,7 @@ struct tacchi_sim {
     double pending[7];
     int phase = 0;        // 0: ready for P2G, 1: P2G done, 2: grid updated
     int parity = 0;       // which bin buffers hold the current substep's lists
+    bool stop_armed = false;  // substep kernels honour the stop flag (tacchi_run_until_force)
     double dtA = 0.0;     // dt the stored affine matrices were formed with
     double dt_phase = 0.0;
     SimDev<float> sf;
@@ -375,6 +377,7 @@ SimDev<T> make_simdev(tacchi_sim *s)
     S.err = (int *)(w + L.err);
     S.force = (double *)(w + L.force);
     S.fallback = (unsigned int *)(w + L.fallback);
+    S.stop = s->stop_armed ? (const int *)(w + L.stop) : nullptr;
     return S;
 }
 
@@ -413,7 +416,7 @@ tacchi_status launch_bin(tacchi_sim *s)
 }
 
 // Accumulator units of P2G: FP32 tiles count one particle mass and one
-// momentum unit m/dt as 2^40 (fixed point, see TileAcc); FP64 accumulates in
+// momentum unit m/dt as 2^28 (fixed point, see TileAcc); FP64 accumulates in
 // SI/grid units directly.
 struct P2GScales {
     double mscale, pscale, munit, punit;
@@ -690,6 +693,35 @@ tacchi_status surface_disp_t(tacchi_sim *s, int res, int sub, float *out)
     return TACCHI_OK;
 }
 
+template <typename T>
+tacchi_status markers_t(tacchi_sim *s, const std::vector<double> &q, int n, void *out, int on_device)
+{
+    SimDev<T> &S = sdev<T>(s);
+    std::vector<T> qt(q.begin(), q.end());
+    const size_t qbytes = qt.size() * sizeof(T), obytes = (size_t)n * 3 * sizeof(T);
+    char *buf = nullptr;
+    const size_t off = (qbytes + 255) & ~(size_t)255;
+    TC_HIP(hipMallocAsync((void **)&buf, off + (on_device ? 0 : obytes), s->stream));
+    T *dq = (T *)buf, *dout = on_device ? (T *)out : (T *)(buf + off);
+    hipError_t e = hipMemcpyAsync(dq, qt.data(), qbytes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+        if (s->d.B == 4)
+            hipLaunchKernelGGL((k_markers<T, 4>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, dq, n, T(s->d.dx),
+                               dout);
+        else
+            hipLaunchKernelGGL((k_markers<T, 8>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, dq, n, T(s->d.dx),
+                               dout);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, obytes, hipMemcpyDeviceToHost, s->stream);
+    const hipError_t ef = hipFreeAsync(buf, s->stream);
+    const hipError_t es = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess || ef != hipSuccess || es != hipSuccess)
+        return fail(TACCHI_E_DEVICE, std::string("tacchi_markers: ") +
+                                         hipGetErrorString(e != hipSuccess ? e : (ef != hipSuccess ? ef : es)));
+    return read_error_word(s);
+}
+
 // One vertical gap query: the indenter at a pose above a block's top face.
 struct GapDev {
     IndenterDev<double> I;  // shape, parameters and orientation (indenter frame -> world)
@@ -960,6 +992,53 @@ tacchi_status tacchi_run(tacchi_sim *s, const tacchi_pose *poses, int32_t n, dou
     return TACCHI_OK;
 }
 
+tacchi_status tacchi_run_until_force(tacchi_sim *s, const tacchi_pose *poses, int32_t n, double dt, double fz_limit,
+                                     int32_t *steps_done)
+{
+    if (!s || !poses || !steps_done || n < 1) return fail(TACCHI_E_ARG, "bad arguments to tacchi_run_until_force");
+    if (std::isnan(fz_limit)) return fail(TACCHI_E_ARG, "fz_limit is NaN");
+    if (s->phase != 0) return fail(TACCHI_E_STATE, "tacchi_run_until_force called inside a substep");
+    *steps_done = 0;
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    int *flag = (int *)(s->ws + s->L.stop);
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(kWG), 0, s->stream, flag, (int64_t)2, 0);
+    TC_LAUNCHED();
+    const double *force = (const double *)(s->ws + s->L.force);
+    const int parity0 = s->parity;
+    s->stop_armed = true;
+    s->sf = make_simdev<float>(s);
+    s->sd = make_simdev<double>(s);
+    int launched = 0;
+    for (; launched < n; ++launched) {
+        st = tacchi_step(s, poses + launched, dt);
+        if (st) break;
+        hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(64), 0, s->stream, flag, force, fz_limit);
+        if (hipGetLastError() != hipSuccess) {
+            st = fail(TACCHI_E_DEVICE, "tacchi_run_until_force: launch failed");
+            break;
+        }
+    }
+    int h[2] = {0, 0};
+    const hipError_t e = hipMemcpyAsync(h, flag, sizeof h, hipMemcpyDeviceToHost, s->stream);
+    const hipError_t es = hipStreamSynchronize(s->stream);
+    // the host advanced its bin-buffer parity and pose once per launched
+    // substep; the device state is that of the substeps that ran
+    const int done = (e == hipSuccess && es == hipSuccess) ? h[1] : launched;
+    s->parity = parity0 ^ (done & 1);
+    if (done > 0) {
+        std::memcpy(s->pose, poses[done - 1].pos, 3 * sizeof(double));
+        std::memcpy(s->pose + 3, poses[done - 1].quat, 4 * sizeof(double));
+    }
+    s->stop_armed = false;
+    s->sf = make_simdev<float>(s);
+    s->sd = make_simdev<double>(s);
+    if (st) return st;
+    if (e != hipSuccess || es != hipSuccess) return fail(TACCHI_E_DEVICE, "tacchi_run_until_force: readback failed");
+    *steps_done = done;
+    return read_error_word(s);
+}
+
 tacchi_status tacchi_read_grid(tacchi_sim *s, int32_t which, void *M, void *vec, int32_t on_device)
 {
     if (!s || !vec) return fail(TACCHI_E_ARG, "NULL argument");
@@ -1006,6 +1085,30 @@ tacchi_status tacchi_surface_displacement(tacchi_sim *s, int32_t res, int32_t su
     if (e != hipSuccess || ef != hipSuccess || es != hipSuccess)
         return fail(TACCHI_E_DEVICE, "tacchi_surface_displacement: copy failed");
     return read_error_word(s);
+}
+
+tacchi_status tacchi_markers(tacchi_sim *s, const double *xy, int32_t n, void *out, int32_t on_device)
+{
+    if (!s || !xy || !out) return fail(TACCHI_E_ARG, "NULL argument");
+    if (n < 1 || n > (1 << 24)) return fail(TACCHI_E_ARG, "marker count must be in [1, 2^24]");
+    if (s->d.n[0] < 2 || s->d.n[1] < 2) return fail(TACCHI_E_ARG, "the top layer needs at least 2 x 2 particles");
+    const tacchi_block &bk = s->cfg.block;
+    const double hx = bk.size[0] / bk.n[0], hy = bk.size[1] / bk.n[1];
+    std::vector<double> q((size_t)n * 2);
+    for (int k = 0; k < n; ++k) {
+        const double x = xy[2 * k], y = xy[2 * k + 1];
+        if (!(x >= bk.origin[0] && x <= bk.origin[0] + bk.size[0] && y >= bk.origin[1] &&
+              y <= bk.origin[1] + bk.size[1]))
+            return fail(TACCHI_E_ARG, "a marker lies outside the top face");
+        // fractional lattice coordinates; the half-cell rims outside the
+        // outermost particle centres take the edge value
+        q[2 * k] = std::min(std::max((x - bk.origin[0]) / hx - 0.5, 0.0), (double)(bk.n[0] - 1));
+        q[2 * k + 1] = std::min(std::max((y - bk.origin[1]) / hy - 0.5, 0.0), (double)(bk.n[1] - 1));
+    }
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    return s->cfg.precision == TACCHI_F64 ? markers_t<double>(s, q, n, out, on_device)
+                                          : markers_t<float>(s, q, n, out, on_device);
 }
 
 tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res,

@@ -27,7 +27,8 @@ EXPORTS = (
     "tacchi_timing_enable", "tacchi_timing_read", "tacchi_polar_fallbacks",
     "tacchi_batch_workspace_bytes", "tacchi_batch_create", "tacchi_batch_run", "tacchi_batch_contact",
     "tacchi_batch_tuning", "tacchi_batch_substeps_done", "tacchi_batch_sync", "tacchi_batch_destroy",
-    "tacchi_surface_displacement", "tacchi_indenter_gap", "tacchi_batch_surface_displacement",
+    "tacchi_surface_displacement", "tacchi_indenter_gap", "tacchi_batch_surface_displacement", "tacchi_markers",
+    "tacchi_run_until_force",
 )
 NUM_KERNEL_CLASSES = 6
 KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
@@ -147,6 +148,11 @@ def lib():
         L.tacchi_batch_destroy.argtypes = [_vp]
         L.tacchi_surface_displacement.restype = ctypes.c_int32
         L.tacchi_surface_displacement.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32]
+        L.tacchi_run_until_force.restype = ctypes.c_int32
+        L.tacchi_run_until_force.argtypes = [_vp, ctypes.POINTER(Pose), ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
+        L.tacchi_markers.restype = ctypes.c_int32
+        L.tacchi_markers.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _vp, ctypes.c_int32]
         L.tacchi_indenter_gap.restype = ctypes.c_int32
         L.tacchi_indenter_gap.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(Pose), ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp, _vp]

@@ -69,6 +69,15 @@ class Sim:
         arr = N.make_poses(poses)
         N.check(N.lib().tacchi_run(self._h, arr, len(poses), dt))
 
+    def run_until_force(self, poses, dt: float, fz_limit: float) -> int:
+        """Substeps to poses[0], poses[1], ... until the z contact force on the
+        indenter reaches fz_limit [N] (tested on the device after every
+        substep); returns the number of substeps that ran."""
+        arr = N.make_poses(poses)
+        done = ctypes.c_int32(0)
+        N.check(N.lib().tacchi_run_until_force(self._h, arr, len(poses), dt, fz_limit, ctypes.byref(done)))
+        return int(done.value)
+
     def p2g(self, dt: float):
         N.check(N.lib().tacchi_p2g(self._h, dt))
 
@@ -95,6 +104,15 @@ class Sim:
         points per cell), [res][res][3] (m, float32)."""
         out = self._empty(res, res, 3, dtype=torch.float32)
         N.check(N.lib().tacchi_surface_displacement(self._h, res, sub, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def markers(self, xy) -> torch.Tensor:
+        """Displacement [n][3] (m, simulation precision) of the top surface at
+        marker positions xy [n][2] (world metres on the undeformed top face)."""
+        xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
+        out = self._empty(xy.shape[0], 3)
+        N.check(N.lib().tacchi_markers(self._h, xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), xy.shape[0],
+                                       ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
     def render(self, rp: dict) -> torch.Tensor:

@@ -658,3 +658,61 @@ def test_surface_displacement_reproduces_affine_fields(oracle_lib):
     u8 = oracle_lib.surface_displacement(cfg8, X8 + d8, 8)
     top = d8.reshape(3, 8, 8, 3)[2]
     assert np.abs(u8 - top).max() <= 1e-18
+
+
+def test_markers_reproduce_affine_fields_and_particles(oracle_lib):
+    """Markers (Sec. VI): inside the hull of the top-layer particle centres
+    an affine displacement field is returned exactly at any point; on the rim
+    outside it the value of the nearest point of the hull; at a particle's
+    rest position the particle's own displacement; a point off the face is
+    rejected."""
+    cfg = _flat_cfg(W.SPHERE, [1e-3], n=(9, 7, 3))
+    n0, n1, n2 = cfg["n"]
+    h = [cfg["block_size"][a] / cfg["n"][a] for a in range(3)]
+    o = cfg["block_origin"]
+    kk, jj, ii = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
+    X = np.stack([o[0] + (ii + 0.5) * h[0], o[1] + (jj + 0.5) * h[1], o[2] + (kk + 0.5) * h[2]], -1).reshape(-1, 3)
+    A = np.array([[1e-3, -2e-3, 0.5e-3], [3e-3, 1e-3, -1e-3], [-2e-3, 4e-3, 2e-3]])
+    b = np.array([1e-5, -3e-5, -2e-4])
+    ztop = o[2] + (n2 - 0.5) * h[2]
+    rng = np.random.default_rng(11)
+    pts = np.stack([o[0] + rng.uniform(0.0, cfg["block_size"][0], 200),
+                    o[1] + rng.uniform(0.0, cfg["block_size"][1], 200)], -1)
+    got = oracle_lib.markers(cfg, X + X @ A.T + b, pts)
+    lo = np.array([o[0] + 0.5 * h[0], o[1] + 0.5 * h[1]])
+    hi = np.array([o[0] + (n0 - 0.5) * h[0], o[1] + (n1 - 0.5) * h[1]])
+    for p, g in zip(pts, got):
+        q = np.clip(p, lo, hi)
+        assert np.abs(g - (A @ np.array([q[0], q[1], ztop]) + b)).max() <= 1e-15
+    d = rng.standard_normal(X.shape) * 1e-5
+    top = d.reshape(n2, n1, n0, 3)[n2 - 1]
+    at = np.array([[o[0] + (i + 0.5) * h[0], o[1] + (j + 0.5) * h[1]] for j in range(n1) for i in range(n0)])
+    assert np.abs(oracle_lib.markers(cfg, X + d, at) - top.reshape(-1, 3)).max() <= 1e-18
+    with pytest.raises(ValueError):
+        oracle_lib.markers(cfg, X, [[o[0] - 1e-6, o[1]]])
+
+
+def test_run_until_force_stops_at_the_first_crossing(oracle_lib):
+    """Sec. III-C's terminal condition on the force: against forces recorded
+    by plain stepping, the run stops after the first substep whose contact
+    force reaches the limit, in exactly the state plain stepping reaches
+    there; an unreachable limit runs every substep, -inf stops after one."""
+    wl = W.small_sphere_contact(seed=1, steps=1000)
+    cfg, poses, dt = wl["cfg"], wl["poses"], wl["dt"]
+    n = 120
+    ref = oracle_lib.OracleSim(cfg, poses[0])
+    f, states = [], []
+    for k in range(n):
+        assert ref.step(poses[k + 1], dt) == 0
+        f.append(ref.force()[2])
+        states.append(ref.particles()[0].copy())
+    f = np.array(f)
+    assert f[-1] > 0.0  # the gel pushes the indenter up
+    # a limit halfway between the running maximum and the next larger force
+    i = next(i for i in range(60, n) if f[i] > f[:i].max() * (1 + 1e-6) + 1e-12)
+    limit = 0.5 * (f[:i].max() + f[i])
+    sim = oracle_lib.OracleSim(cfg, poses[0])
+    assert sim.run_until_force(poses, dt, limit, 0, n) == i + 1
+    assert np.array_equal(sim.particles()[0], states[i])
+    assert oracle_lib.OracleSim(cfg, poses[0]).run_until_force(poses, dt, math.inf, 0, n) == n
+    assert oracle_lib.OracleSim(cfg, poses[0]).run_until_force(poses, dt, -math.inf, 0, n) == 1
