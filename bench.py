@@ -137,6 +137,7 @@ def streaming_leg(n=200):
     substep, limit never reached); on the GelSight press (1.6M particles,
     FP32) and on the 18,432-particle sphere press (FP64, launch-bound)."""
     import math
+    import numpy as np
     import torch
     from paper_2301_08343_amd import workloads as W
     from paper_2301_08343_amd.sim import Sim
@@ -162,6 +163,33 @@ def streaming_leg(n=200):
             sim.sync()
             res[mode + "_us_per_substep"] = (time.perf_counter() - t0) / n * 1e6
             k += n
+        if prec == "f32":
+            # the grid update (where the contact model acts) under no-slip and
+            # Coulomb contact, mid-press, from the library's HIP events
+            for model, label in ((Sim.STICKY, "sticky"), (Sim.COULOMB, "coulomb")):
+                sim.set_contact(model, 0.3)
+                sim.timing_enable(("grid",))
+                sim.timing_read(reset=True)
+                sim.run(poses[k:k + n], dt)
+                sim.sync()
+                g = sim.timing_read(reset=True)["grid"]
+                res[f"grid_ms_{label}"] = g[0] / max(1, g[1])
+                k += n
+            sim.timing_enable(())
+            sim.set_contact(Sim.STICKY)
+            # the indenter as 1e4 / 1e5 / 1e6 points (the paper's three point
+            # cloud densities), 0.5 mm shell of the press's sphere
+            m = wl["cfg"]["rho"] * (wl["cfg"]["block_size"][0] / wl["cfg"]["n"][0]) ** 3
+            for npts in (10_000, 100_000, 1_000_000):
+                sim.set_indenter_points(W.sphere_points(wl["cfg"]["sp"][0], npts, 0.5e-3, 0), 10 * m)
+                sim.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.run(poses[k:k + n], dt)
+                sim.sync()
+                res[f"points_{npts}_us_per_substep"] = (time.perf_counter() - t0) / n * 1e6
+                k += n
+            sim.set_indenter_points(np.zeros((0, 3)), 0.0)
         res["particles"] = sim.N
         sim.close()
         out[name] = res

@@ -132,6 +132,36 @@ tacchi_status tacchi_step(tacchi_sim *sim, const tacchi_pose *pose_end, double d
 /* `n` substeps of size dt; substep s ends at poses[s]. Asynchronous. */
 tacchi_status tacchi_run(tacchi_sim *sim, const tacchi_pose *poses, int32_t n, double dt);
 
+/* Contact model of the indenter (beyond the paper, whose contact is
+ * no-slip and which leaves surface friction to future work, Sec. VI):
+ * TACCHI_CONTACT_STICKY (the default) gives every grid node inside the
+ * indenter the rigid velocity; TACCHI_CONTACT_COULOMB with coefficient
+ * mu >= 0 (+inf allowed) splits a contact node's velocity relative to the
+ * indenter along the outward normal n (central differences of the shape's
+ * signed distance, step 1e-3 dx): a node moving apart keeps its velocity,
+ * an approaching one loses its normal component and its tangential
+ * component shrinks by mu times the normal speed, stopping where it is
+ * smaller (stick). Takes effect from the next substep; TACCHI_E_ARG for an
+ * unknown model or a negative or NaN mu. */
+enum { TACCHI_CONTACT_STICKY = 0, TACCHI_CONTACT_COULOMB = 1 };
+tacchi_status tacchi_set_contact(tacchi_sim *sim, int32_t model, double mu);
+
+/* The indenter as particles (Eq. 10: the particles representing the indenter
+ * take its velocity; Sec. IV-B: objects enter as point clouds, whose density
+ * the paper varies): n points xyz[k] in the indenter frame (metres, host
+ * memory, copied), each of mass `mass` [kg]. Every substep the points are
+ * placed rigidly at the pose of the substep's start and scatter their mass to
+ * the grid with the weights of Eq. 2 (points whose 3x3x3 nodes leave the grid
+ * are ignored); their momentum there is that mass times the indenter's rigid
+ * velocity at the node (APIC with the rigid body's velocity gradient is exact
+ * for it), and a grid node carrying indenter mass M_I takes the velocity
+ * (M V + M_I v_indenter)/(M + M_I) in place of the shape's contact; the
+ * contact force is still the gel's momentum change. n = 0 returns to the
+ * shape's contact (tacchi_set_contact). The handle allocates its own device
+ * buffers for the points and an FP64 mass per grid node (freed by
+ * tacchi_destroy). Must be called between substeps. Synchronises. */
+tacchi_status tacchi_set_indenter_points(tacchi_sim *sim, const double *xyz, int32_t n, double mass);
+
 /* The scripted press with a terminal condition on the contact force
  * (Sec. III-C: the simulation ends when a terminal condition is met): runs
  * substeps as tacchi_run does, poses[s] ending substep s, until the z

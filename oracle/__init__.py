@@ -74,6 +74,12 @@ def lib():
             getattr(L, name).restype = ctypes.c_int
         L.orc_get_grid.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         L.orc_force.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_set_contact.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
+        L.orc_set_contact.restype = None
+        L.orc_set_indenter_points.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int64, ctypes.c_double]
+        L.orc_set_indenter_points.restype = ctypes.c_int
+        L.orc_indenter_mass.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_indenter_mass.restype = None
         L.orc_heightmap.argtypes = [ctypes.c_void_p, _dp]
         L.orc_render.argtypes = [ctypes.c_void_p, ctypes.POINTER(OrcRender), ctypes.c_int32,
                                  ctypes.c_int32, _dp]
@@ -212,6 +218,21 @@ class OracleSim:
         M = np.zeros(self.nn); P = np.zeros((self.nn, 3)); V = np.zeros((self.nn, 3))
         lib().orc_get_grid(self._h, _ptr(M), _ptr(P), _ptr(V))
         return M, P, V
+
+    def set_contact(self, model: int, mu: float = 0.0):
+        """0: no-slip contact (default); 1: Coulomb friction with coefficient mu."""
+        lib().orc_set_contact(self._h, int(model), float(mu))
+
+    def set_indenter_points(self, xyz, mass: float):
+        """The indenter as particles: points [n][3] in the indenter frame, mass each."""
+        pts = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        assert lib().orc_set_indenter_points(self._h, _ptr(pts), pts.shape[0], float(mass)) == 0
+
+    def indenter_mass(self):
+        """Indenter mass per grid node (node order x fastest) of the last grid update."""
+        out = np.zeros(self.nn)
+        lib().orc_indenter_mass(self._h, _ptr(out))
+        return out
 
     def force(self):
         f = np.zeros(3)

@@ -42,6 +42,12 @@ struct orc_sim {
     double pose[7];       /* indenter pose at the start of the current substep */
     double force[3];
     int status;
+    int contact;          /* 0 no-slip, 1 Coulomb friction */
+    double friction;      /* Coulomb coefficient */
+    double *ipts;         /* particle indenter: points in the indenter frame [ni][3] */
+    int64_t ni;
+    double imass;         /* mass per indenter point */
+    double *MI;           /* indenter mass per node of the last grid update */
 };
 
 /* ---------------------------------------------------------------- small 3x3 helpers */
@@ -402,6 +408,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     free(s->x); free(s->v); free(s->C); free(s->F);
     free(s->M); free(s->P); free(s->V);
+    free(s->ipts); free(s->MI);
     free(s);
 }
 
@@ -492,15 +499,92 @@ int orc_p2g(orc_sim *s, double dt)
 
 /* ---------------------------------------------------------------- grid update */
 
+void orc_set_contact(orc_sim *s, int model, double mu)
+{
+    s->contact = model;
+    s->friction = mu;
+}
+
+/* The indenter as particles (Eq. 10's set I, the object's point cloud):
+ * n points in the indenter frame, each of mass `mass`; n = 0 returns to the
+ * implicit solid. */
+int orc_set_indenter_points(orc_sim *s, const double *xyz, int64_t n, double mass)
+{
+    free(s->ipts);
+    s->ipts = NULL;
+    s->ni = 0;
+    if (n <= 0) return ORC_OK;
+    s->ipts = (double *)malloc((size_t)n * 3 * sizeof(double));
+    if (!s->MI) s->MI = (double *)calloc((size_t)s->nn, sizeof(double));
+    if (!s->ipts || !s->MI) return ORC_E_ARG;
+    memcpy(s->ipts, xyz, (size_t)n * 3 * sizeof(double));
+    s->ni = n;
+    s->imass = mass;
+    return ORC_OK;
+}
+
+void orc_indenter_mass(const orc_sim *s, double *out)
+{
+    for (int64_t q = 0; q < s->nn; ++q) out[q] = s->MI ? s->MI[q] : 0.0;
+}
+
+/* Mass of the particle indenter on the grid: every point placed rigidly at
+ * the pose of the substep's start scatters w m_I to its 3x3x3 nodes (the
+ * weights of Eq. 2); points whose nodes leave the grid are ignored. */
+static void scatter_indenter(orc_sim *s)
+{
+    double R[9];
+    quat_to_matrix(s->pose + 3, R);
+    memset(s->MI, 0, (size_t)s->nn * sizeof(double));
+    for (int64_t k = 0; k < s->ni; ++k) {
+        const double *l = s->ipts + k * 3;
+        double X[3], w[3][3];
+        int64_t base[3];
+        for (int r = 0; r < 3; ++r) X[r] = s->pose[r] + R[r * 3 + 0] * l[0] + R[r * 3 + 1] * l[1] + R[r * 3 + 2] * l[2];
+        if (stencil(s, X, base, w) != ORC_OK) continue;
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a)
+                    s->MI[node_index(s, base[0] + a, base[1] + b, base[2] + c)] += w[0][a] * w[1][b] * w[2][c] * s->imass;
+    }
+}
+
+/* Outward unit normal of the posed indenter at world point X: the gradient
+ * of its signed distance by central differences of step eps along the world
+ * axes. Returns 0 where the gradient vanishes. */
+static int contact_normal(const orc_sim *s, const double X[3], double eps, double n[3])
+{
+    double g[3], norm = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double a[3] = {X[0], X[1], X[2]}, b[3] = {X[0], X[1], X[2]};
+        a[k] += eps;
+        b[k] -= eps;
+        g[k] = (phi_world(s, s->pose, a) - phi_world(s, s->pose, b)) / (2.0 * eps);
+        norm += g[k] * g[k];
+    }
+    norm = sqrt(norm);
+    if (!(norm > 1e-12)) return 0;
+    for (int k = 0; k < 3; ++k) n[k] = g[k] / norm;
+    return 1;
+}
+
 /* Eq. 6 plus gravity, then the rigid-indenter contact (Eq. 10's indenter
  * case, applied at the nodes inside the indenter at the start pose), the
  * held floor and the grid walls. The contact reaction on the indenter is
- * sum M (V_before - V_indenter) / dt over the contact nodes. */
+ * sum M (V_before - V_after) / dt over the contact nodes. No-slip contact
+ * gives a contact node the indenter's velocity. Coulomb contact (friction is
+ * left to future work in the paper) takes the node's velocity relative to the
+ * indenter, u = V - v_ind, and the outward normal n: if u.n >= 0 the node
+ * moves apart and keeps V; otherwise the normal part of u is removed and the
+ * tangential part u_t scaled by max(0, 1 - mu |u.n| / |u_t|) (zero if u_t is
+ * zero), i.e. sliding against a friction bounded by mu times the normal
+ * impulse, or sticking. */
 int orc_grid_update(orc_sim *s, const double pose_end[7], double dt)
 {
     const double dx = s->cfg.dx;
     const int wall = s->cfg.wall_nodes;
     s->force[0] = s->force[1] = s->force[2] = 0.0;
+    if (s->ni > 0) scatter_indenter(s);
     for (int64_t c = 0; c < s->cfg.gn[2]; ++c)
         for (int64_t b = 0; b < s->cfg.gn[1]; ++b)
             for (int64_t a = 0; a < s->cfg.gn[0]; ++a) {
@@ -513,12 +597,47 @@ int orc_grid_update(orc_sim *s, const double pose_end[7], double dt)
                 for (int r = 0; r < 3; ++r) V[r] = s->P[q * 3 + r] / s->M[q] + dt * s->cfg.gravity[r];
                 double X[3] = {s->cfg.grid_origin[0] + a * dx, s->cfg.grid_origin[1] + b * dx,
                                s->cfg.grid_origin[2] + c * dx};
-                if (s->cfg.shape >= 0 && phi_world(s, s->pose, X) <= 0.0) {
-                    double vi[3];
+                if (s->ni > 0) {
+                    /* particle indenter: its points move with the rigid velocity
+                     * (Eq. 10), so their momentum on node i is M_I v_ind(X_i) (APIC
+                     * with the rigid body's velocity gradient is exact for it), and
+                     * the node's velocity is that of the summed momentum */
+                    if (s->MI[q] > 0.0) {
+                        double vi[3];
+                        orc_indenter_velocity(s->pose, pose_end, dt, X, vi);
+                        for (int r = 0; r < 3; ++r) {
+                            const double after = (s->M[q] * V[r] + s->MI[q] * vi[r]) / (s->M[q] + s->MI[q]);
+                            s->force[r] += s->M[q] * (V[r] - after) / dt;
+                            V[r] = after;
+                        }
+                    }
+                } else if (s->cfg.shape >= 0 && phi_world(s, s->pose, X) <= 0.0) {
+                    double vi[3], after[3] = {0.0, 0.0, 0.0}, n[3];
                     orc_indenter_velocity(s->pose, pose_end, dt, X, vi);
+                    for (int r = 0; r < 3; ++r) after[r] = vi[r];
+                    if (s->contact == 1 && contact_normal(s, X, 1e-3 * dx, n)) {
+                        double u[3], un = 0.0;
+                        for (int r = 0; r < 3; ++r) {
+                            u[r] = V[r] - vi[r];
+                            un += u[r] * n[r];
+                        }
+                        if (un >= 0.0) {
+                            for (int r = 0; r < 3; ++r) after[r] = V[r];
+                        } else {
+                            double ut[3], tn = 0.0;
+                            for (int r = 0; r < 3; ++r) {
+                                ut[r] = u[r] - un * n[r];
+                                tn += ut[r] * ut[r];
+                            }
+                            tn = sqrt(tn);
+                            double k = tn > 0.0 ? 1.0 + s->friction * un / tn : 0.0;
+                            if (k < 0.0) k = 0.0;
+                            for (int r = 0; r < 3; ++r) after[r] = vi[r] + k * ut[r];
+                        }
+                    }
                     for (int r = 0; r < 3; ++r) {
-                        s->force[r] += s->M[q] * (V[r] - vi[r]) / dt;
-                        V[r] = vi[r];
+                        s->force[r] += s->M[q] * (V[r] - after[r]) / dt;
+                        V[r] = after[r];
                     }
                 }
                 if (c <= s->cfg.floor_node) V[0] = V[1] = V[2] = 0.0;

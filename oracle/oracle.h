@@ -71,6 +71,14 @@ int orc_step(orc_sim *s, const double pose_end[7], double dt);
 
 void orc_get_grid(const orc_sim *s, double *M, double *P, double *V); /* [n], [n][3], [n][3] */
 void orc_force(const orc_sim *s, double f[3]);
+/* Contact model from the next grid update: 0 no-slip (default), 1 Coulomb
+ * friction with coefficient mu (see orc_grid_update). */
+void orc_set_contact(orc_sim *s, int model, double mu);
+/* Particle indenter: n points (indenter frame, [n][3]) of mass `mass` each;
+ * n = 0 returns to the implicit solid. orc_indenter_mass copies the
+ * indenter's mass per grid node of the last grid update. */
+int orc_set_indenter_points(orc_sim *s, const double *xyz, int64_t n, double mass);
+void orc_indenter_mass(const orc_sim *s, double *out);
 
 void orc_heightmap(const orc_sim *s, double *H);                      /* [n1][n0] */
 void orc_render(const orc_sim *s, const orc_render_params *rp, int32_t h, int32_t w,

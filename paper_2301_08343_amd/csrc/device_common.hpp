@@ -100,6 +100,9 @@ struct IndenterDev {
     T vc[3];               // translation velocity [cells/s]
     T om[3];               // angular velocity [rad/s]
     T dx;                  // [m] converts grid units to metres for the shape
+    T mu;                  // Coulomb friction coefficient (grid kernels instantiated with friction)
+    T eps;                 // [m] step of the central differences giving the contact normal
+    const double *MI;      // particle indenter: its mass per grid node (x fastest), else null
 };
 
 template <typename T> __device__ __forceinline__ T tfloor(T x);

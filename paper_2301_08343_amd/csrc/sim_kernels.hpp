@@ -405,17 +405,68 @@ __device__ __forceinline__ T wave_sum(T x)
     return x;
 }
 
+// Outward unit normal of the indenter at the node r (metres from the
+// indenter origin, world frame; p = R^T r in the indenter frame): the
+// gradient of phi with respect to r by central differences of step I.eps
+// along the world axes. False where the gradient vanishes.
+__device__ __forceinline__ bool indenter_normal(const IndenterDev<double> &I, double px, double py, double pz,
+                                                double n[3])
+{
+    double g[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // d p / d r_k is column k of R^T, i.e. row k of R
+        const double cx = I.R[3 * k] * I.eps, cy = I.R[3 * k + 1] * I.eps, cz = I.R[3 * k + 2] * I.eps;
+        g[k] = (indenter_phi<double>(I, px + cx, py + cy, pz + cz) - indenter_phi<double>(I, px - cx, py - cy, pz - cz)) /
+               (2.0 * I.eps);
+    }
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (!(gn > 1e-12)) return false;
+    n[0] = g[0] / gn;
+    n[1] = g[1] / gn;
+    n[2] = g[2] / gn;
+    return true;
+}
+
+// Velocity of a contact node (cells/s) under Coulomb friction against the
+// rigid velocity w (beyond the paper, which leaves friction to future work):
+// with the relative velocity split along the outward normal n, a node
+// moving apart (vn >= 0) keeps its velocity; an approaching node loses its
+// normal component and its tangential one shrinks by mu |vn| (to zero when
+// the tangential speed is smaller: stick).
+__device__ __forceinline__ void coulomb_contact(const double V[3], const double w[3], const double n[3], double mu,
+                                                double out[3])
+{
+    const double vr[3] = {V[0] - w[0], V[1] - w[1], V[2] - w[2]};
+    const double vn = vr[0] * n[0] + vr[1] * n[1] + vr[2] * n[2];
+    if (vn >= 0.0) {
+        out[0] = V[0]; out[1] = V[1]; out[2] = V[2];
+        return;
+    }
+    const double vt[3] = {vr[0] - vn * n[0], vr[1] - vn * n[1], vr[2] - vn * n[2]};
+    const double t = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
+    const double k = t > 0.0 ? fmax(0.0, 1.0 + mu * vn / t) : 0.0;
+    out[0] = w[0] + k * vt[0];
+    out[1] = w[1] + k * vt[1];
+    out[2] = w[2] + k * vt[2];
+}
+
 // One workgroup per grid block that a G2P tile may read (the block or one of
 // its 26 neighbours has particles). Per node with mass above S.m_floor
 // (0 in FP64; in FP32 2^-22 of a particle's mass, below which P/M is
 // dominated by fixed-point quantisation and the node's weight in any particle
 // is negligible): V = P/M + dt g (Eq. 6);
-// inside the indenter V takes the rigid indenter velocity (sticky contact;
-// the reaction M (V_before - V_indenter)/dt is summed into the force);
+// inside the indenter V takes the rigid indenter velocity (sticky contact)
+// or the Coulomb update (CONTACT_COULOMB), or, for an indenter represented
+// by particles (CONTACT_PARTICLES), the velocity of the node's gel momentum
+// plus the indenter points' momentum; the reaction M (V_before - V_after)/dt
+// is summed into the force;
 // floor nodes are held; wall nodes drop their outward component. The inside test and the
 // rigid velocity are evaluated in FP64 in both precisions, so the discrete
 // contact decision does not depend on the simulation precision.
-template <typename T, int B, int WG>
+constexpr int CONTACT_STICKY = 0, CONTACT_COULOMB = 1, CONTACT_PARTICLES = 2;
+
+template <typename T, int B, int WG, int CONTACT = CONTACT_STICKY>
 __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, const IndenterDev<double> &I, T dt)
 {
     constexpr int B3 = B * B * B;
@@ -456,12 +507,35 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
                 const double px = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
                 const double py = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
                 const double pz = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
-                if (indenter_phi<double>(I, px, py, pz) <= 0.0) {
+                // particle indenter: the node is in contact where the points
+                // scattered mass; else where the shape's signed distance is <= 0
+                const double mi = CONTACT == CONTACT_PARTICLES
+                                      ? I.MI[gx + (int64_t)S.g0 * (gy + (int64_t)S.g1 * gz)]
+                                      : 0.0;
+                if (CONTACT == CONTACT_PARTICLES ? mi > 0.0 : indenter_phi<double>(I, px, py, pz) <= 0.0) {
                     // rigid velocity v_c + omega x r, converted to cells/s
                     const double ir = 1.0 / I.dx;
-                    const T w0 = T(I.vc[0] + (I.om[1] * r2 - I.om[2] * r1) * ir);
-                    const T w1 = T(I.vc[1] + (I.om[2] * r0 - I.om[0] * r2) * ir);
-                    const T w2 = T(I.vc[2] + (I.om[0] * r1 - I.om[1] * r0) * ir);
+                    const double wd[3] = {I.vc[0] + (I.om[1] * r2 - I.om[2] * r1) * ir,
+                                          I.vc[1] + (I.om[2] * r0 - I.om[0] * r2) * ir,
+                                          I.vc[2] + (I.om[0] * r1 - I.om[1] * r0) * ir};
+                    T w0 = T(wd[0]), w1 = T(wd[1]), w2 = T(wd[2]);
+                    double nrm[3];
+                    if (CONTACT == CONTACT_COULOMB && indenter_normal(I, px, py, pz, nrm)) {
+                        const double Vd[3] = {(double)V0, (double)V1, (double)V2};
+                        double Va[3];
+                        coulomb_contact(Vd, wd, nrm, I.mu, Va);
+                        w0 = T(Va[0]); w1 = T(Va[1]); w2 = T(Va[2]);
+                    }
+                    if (CONTACT == CONTACT_PARTICLES) {
+                        // the points move with the rigid velocity (Eq. 10): their
+                        // momentum on the node is mi w (APIC with the rigid velocity
+                        // gradient is exact), and the node takes the velocity of
+                        // the summed momentum
+                        const double md = (double)m;
+                        w0 = T((md * (double)V0 + mi * wd[0]) / (md + mi));
+                        w1 = T((md * (double)V1 + mi * wd[1]) / (md + mi));
+                        w2 = T((md * (double)V2 + mi * wd[2]) / (md + mi));
+                    }
                     const T s = m * T(I.dx) * inv_dt;
                     fx += (double)(s * (V0 - w0));
                     fy += (double)(s * (V1 - w1));
@@ -491,10 +565,45 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
     }
 }
 
-template <typename T, int B>
+// One instantiation per contact model: the no-slip kernel carries none of
+// the Coulomb code (the normal's six extra shape evaluations would otherwise
+// raise the register count of every grid update)
+template <typename T, int B, int CONTACT>
 __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
 {
-    grid_block<T, B, kWG>(S, blockIdx.x, I, dt);
+    grid_block<T, B, kWG, CONTACT>(S, blockIdx.x, I, dt);
+}
+
+// Particle indenter: each point (indenter frame, metres) placed at the pose
+// of the substep's start scatters w * mass to its 3x3x3 nodes (the weights
+// of Eq. 2) in the dense node array MI (x fastest, cleared before); points
+// whose nodes leave the grid are ignored. FP64 atomics.
+__global__ void __launch_bounds__(kWG) k_indenter_scatter(const double *pts, int n, IndenterDev<double> I, int g0,
+                                                          int g1, int g2, double mass, double *MI)
+{
+    const int k = blockIdx.x * kWG + threadIdx.x;
+    if (k >= n) return;
+    const double l0 = pts[3 * k], l1 = pts[3 * k + 1], l2 = pts[3 * k + 2];
+    const double ir = 1.0 / I.dx;
+    // grid coordinates: origin + R l (R indenter frame -> world, row-major)
+    const double xg[3] = {I.tip[0] + (I.R[0] * l0 + I.R[1] * l1 + I.R[2] * l2) * ir,
+                          I.tip[1] + (I.R[3] * l0 + I.R[4] * l1 + I.R[5] * l2) * ir,
+                          I.tip[2] + (I.R[6] * l0 + I.R[7] * l1 + I.R[8] * l2) * ir};
+    const int gn[3] = {g0, g1, g2};
+    int base[3];
+    double w[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double b = floor(xg[a] - 0.5);
+        if (!(b >= 0.0 && b <= (double)(gn[a] - 3))) return;
+        base[a] = (int)b;
+        bspline3<double>(xg[a] - b, w[a]);
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int bb = 0; bb < 3; ++bb)
+            for (int a = 0; a < 3; ++a)
+                atomicAdd(&MI[(base[0] + a) + (int64_t)g0 * ((base[1] + bb) + (int64_t)g1 * (base[2] + c))],
+                          w[0][a] * w[1][bb] * w[2][c] * mass);
 }
 
 // ---------------------------------------------------------------- G2P

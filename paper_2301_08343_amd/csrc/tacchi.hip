@@ -273,6 +273,13 @@ struct tacchi_sim {
     int phase = 0;        // 0: ready for P2G, 1: P2G done, 2: grid updated
     int parity = 0;       // which bin buffers hold the current substep's lists
     bool stop_armed = false;  // substep kernels honour the stop flag (tacchi_run_until_force)
+    int contact_model = TACCHI_CONTACT_STICKY;
+    double friction = 0.0;    // Coulomb coefficient (TACCHI_CONTACT_COULOMB)
+    // particle indenter (tacchi_set_indenter_points): device buffers owned by the handle
+    double *ipts = nullptr;   // [ni][3] points, indenter frame [m]
+    int ni = 0;
+    double imass = 0.0;       // mass per point [kg]
+    double *MI = nullptr;     // indenter mass per grid node
     double dtA = 0.0;     // dt the stored affine matrices were formed with
     double dt_phase = 0.0;
     SimDev<float> sf;
@@ -472,11 +479,35 @@ tacchi_status do_grid(tacchi_sim *s, const double pose_end[7], double dt)
 {
     SimDev<T> &S = sdev<T>(s);
     IndenterDev<double> I = make_indenter<double>(s->cfg, s->pose, pose_end, dt);
+    I.mu = s->friction;
+    I.eps = 1e-3 * s->d.dx;
+    const int contact = s->ni > 0 ? CONTACT_PARTICLES
+                                  : (s->contact_model == TACCHI_CONTACT_COULOMB ? CONTACT_COULOMB : CONTACT_STICKY);
     KernelTimer t(s, KC_GRID);
-    if (s->d.B == 4)
-        hipLaunchKernelGGL((k_grid<T, 4>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, I, T(dt));
-    else
-        hipLaunchKernelGGL((k_grid<T, 8>), dim3(S.nblk), dim3(kWG), 0, s->stream, S, I, T(dt));
+    if (contact == CONTACT_PARTICLES) {
+        // the points' mass on the grid at the substep's start pose
+        const int64_t nn = (int64_t)S.g0 * S.g1 * S.g2;
+        I.MI = s->MI;
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid1d(nn)), dim3(kWG), 0, s->stream, s->MI, nn, 0.0);
+        hipLaunchKernelGGL(k_indenter_scatter, dim3(grid1d(s->ni)), dim3(kWG), 0, s->stream, s->ipts, s->ni, I, S.g0,
+                           S.g1, S.g2, s->imass, s->MI);
+    }
+    const dim3 g(S.nblk), b(kWG);
+    if (s->d.B == 4) {
+        if (contact == CONTACT_PARTICLES)
+            hipLaunchKernelGGL((k_grid<T, 4, CONTACT_PARTICLES>), g, b, 0, s->stream, S, I, T(dt));
+        else if (contact == CONTACT_COULOMB)
+            hipLaunchKernelGGL((k_grid<T, 4, CONTACT_COULOMB>), g, b, 0, s->stream, S, I, T(dt));
+        else
+            hipLaunchKernelGGL((k_grid<T, 4, CONTACT_STICKY>), g, b, 0, s->stream, S, I, T(dt));
+    } else {
+        if (contact == CONTACT_PARTICLES)
+            hipLaunchKernelGGL((k_grid<T, 8, CONTACT_PARTICLES>), g, b, 0, s->stream, S, I, T(dt));
+        else if (contact == CONTACT_COULOMB)
+            hipLaunchKernelGGL((k_grid<T, 8, CONTACT_COULOMB>), g, b, 0, s->stream, S, I, T(dt));
+        else
+            hipLaunchKernelGGL((k_grid<T, 8, CONTACT_STICKY>), g, b, 0, s->stream, S, I, T(dt));
+    }
     TC_LAUNCHED();
     return TACCHI_OK;
 }
@@ -992,6 +1023,40 @@ tacchi_status tacchi_run(tacchi_sim *s, const tacchi_pose *poses, int32_t n, dou
     return TACCHI_OK;
 }
 
+tacchi_status tacchi_set_indenter_points(tacchi_sim *s, const double *xyz, int32_t n, double mass)
+{
+    if (!s || (n > 0 && !xyz)) return fail(TACCHI_E_ARG, "NULL argument");
+    if (n < 0 || n > (1 << 24)) return fail(TACCHI_E_ARG, "point count must be in [0, 2^24]");
+    if (!(mass >= 0.0) || !std::isfinite(mass)) return fail(TACCHI_E_ARG, "mass per point must be finite and >= 0");
+    if (s->phase != 0) return fail(TACCHI_E_STATE, "tacchi_set_indenter_points called inside a substep");
+    for (int64_t k = 0; k < 3 * (int64_t)n; ++k)
+        if (!std::isfinite(xyz[k])) return fail(TACCHI_E_ARG, "non-finite point coordinate");
+    tacchi_status st = set_device(s);
+    if (st) return st;
+    TC_HIP(hipStreamSynchronize(s->stream));
+    if (s->ipts) TC_HIP(hipFree(s->ipts));
+    s->ipts = nullptr;
+    s->ni = 0;
+    if (n == 0) return TACCHI_OK;
+    const size_t nn = (size_t)s->d.g[0] * s->d.g[1] * s->d.g[2];
+    if (!s->MI) TC_HIP(hipMalloc((void **)&s->MI, nn * sizeof(double)));
+    TC_HIP(hipMalloc((void **)&s->ipts, (size_t)n * 3 * sizeof(double)));
+    TC_HIP(hipMemcpy(s->ipts, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice));
+    s->ni = n;
+    s->imass = mass;
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_set_contact(tacchi_sim *s, int32_t model, double mu)
+{
+    if (!s) return fail(TACCHI_E_ARG, "sim is NULL");
+    if (model != TACCHI_CONTACT_STICKY && model != TACCHI_CONTACT_COULOMB) return fail(TACCHI_E_ARG, "unknown contact model");
+    if (std::isnan(mu) || mu < 0.0) return fail(TACCHI_E_ARG, "friction coefficient must be >= 0");
+    s->contact_model = model;
+    s->friction = model == TACCHI_CONTACT_COULOMB ? mu : 0.0;
+    return TACCHI_OK;
+}
+
 tacchi_status tacchi_run_until_force(tacchi_sim *s, const tacchi_pose *poses, int32_t n, double dt, double fz_limit,
                                      int32_t *steps_done)
 {
@@ -1265,6 +1330,11 @@ void tacchi_destroy(tacchi_sim *s)
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    if (s->ipts || s->MI) {
+        (void)hipStreamSynchronize(s->stream);
+        if (s->ipts) (void)hipFree(s->ipts);
+        if (s->MI) (void)hipFree(s->MI);
+    }
     delete s;
 }
 

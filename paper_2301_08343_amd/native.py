@@ -28,7 +28,7 @@ EXPORTS = (
     "tacchi_batch_workspace_bytes", "tacchi_batch_create", "tacchi_batch_run", "tacchi_batch_contact",
     "tacchi_batch_tuning", "tacchi_batch_substeps_done", "tacchi_batch_sync", "tacchi_batch_destroy",
     "tacchi_surface_displacement", "tacchi_indenter_gap", "tacchi_batch_surface_displacement", "tacchi_markers",
-    "tacchi_run_until_force",
+    "tacchi_run_until_force", "tacchi_set_contact", "tacchi_set_indenter_points",
 )
 NUM_KERNEL_CLASSES = 6
 KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
@@ -148,6 +148,11 @@ def lib():
         L.tacchi_batch_destroy.argtypes = [_vp]
         L.tacchi_surface_displacement.restype = ctypes.c_int32
         L.tacchi_surface_displacement.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32]
+        L.tacchi_set_indenter_points.restype = ctypes.c_int32
+        L.tacchi_set_indenter_points.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                                 ctypes.c_double]
+        L.tacchi_set_contact.restype = ctypes.c_int32
+        L.tacchi_set_contact.argtypes = [_vp, ctypes.c_int32, ctypes.c_double]
         L.tacchi_run_until_force.restype = ctypes.c_int32
         L.tacchi_run_until_force.argtypes = [_vp, ctypes.POINTER(Pose), ctypes.c_int32, ctypes.c_double,
                                              ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]

@@ -69,6 +69,20 @@ class Sim:
         arr = N.make_poses(poses)
         N.check(N.lib().tacchi_run(self._h, arr, len(poses), dt))
 
+    STICKY, COULOMB = 0, 1
+
+    def set_contact(self, model: int, mu: float = 0.0):
+        """Contact model from the next substep: Sim.STICKY (no-slip, the
+        default) or Sim.COULOMB with friction coefficient mu."""
+        N.check(N.lib().tacchi_set_contact(self._h, int(model), float(mu)))
+
+    def set_indenter_points(self, xyz, mass: float):
+        """Represent the indenter by points [n][3] (indenter frame, metres) of
+        `mass` kg each; an empty array returns to the shape's contact."""
+        pts = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        N.check(N.lib().tacchi_set_indenter_points(self._h, pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                   pts.shape[0], float(mass)))
+
     def run_until_force(self, poses, dt: float, fz_limit: float) -> int:
         """Substeps to poses[0], poses[1], ... until the z contact force on the
         indenter reaches fz_limit [N] (tested on the device after every

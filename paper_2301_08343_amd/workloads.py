@@ -159,6 +159,55 @@ def small_sphere_contact(seed: int = 0, steps: int = 1000, jitter: bool = True):
                 render=default_render(0.25e-3, 96, 96))
 
 
+def sphere_points(radius: float, n: int, shell: float, seed: int = 0):
+    """Point cloud of a sphere indenter for the particle-represented indenter
+    (Sec. IV-B: objects enter as point clouds): n points uniform in the
+    spherical shell of the given thickness under the surface, in the indenter
+    frame (origin at the lowest point, +z up, centre at (0, 0, radius))."""
+    rng = np.random.default_rng(0x5EED + seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r_in = max(radius - shell, 0.0)
+    r = (r_in ** 3 + rng.uniform(0.0, 1.0, n) * (radius ** 3 - r_in ** 3)) ** (1.0 / 3.0)
+    return d * r[:, None] + np.array([0.0, 0.0, radius])
+
+
+def slide_contact(radius: float = 3e-3, depth: float = 0.3e-3, slide=(2e-3, 0.0), steps_press: int = 300,
+                  steps_slide: int = 600, retract: int = 0, seed: int = 0):
+    """Sliding over the 18,432-particle block of small_sphere_contact (no
+    jitter): a sphere of the given radius pressed `depth` into the top face
+    over steps_press substeps, then moved by `slide` (x, y) at that depth over
+    steps_slide substeps, then (retract > 0) lifted back to its starting
+    height over `retract` substeps. dt = 1e-5 s."""
+    cfg = _contact(block_origin=(4e-3, 4e-3, 1.5e-3), block_size=(24e-3, 24e-3, 4e-3),
+                   n=(48, 48, 8), grid_origin=(0.0, 0.0, 0.0), dx=0.5e-3, gn=(64, 64, 16),
+                   E=0.15e6, nu=0.45, rho=1000.0, model=NEOHOOKEAN,
+                   shape=SPHERE, sp=[radius], seed=seed)
+    cx, cy = block_center_xy(cfg)
+    cx -= 0.5 * slide[0]
+    cy -= 0.5 * slide[1]
+    z0 = top_z(cfg)
+    poses = [press_trajectory((cx, cy, z0), IDENTITY_QUAT, depth, steps_press)]
+    t = np.arange(1, steps_slide + 1, dtype=np.float64) / steps_slide
+    sl = np.zeros((steps_slide, 7))
+    sl[:, 0] = cx + slide[0] * t
+    sl[:, 1] = cy + slide[1] * t
+    sl[:, 2] = z0 - depth
+    sl[:, 3:] = IDENTITY_QUAT
+    poses.append(sl)
+    if retract > 0:
+        r = np.zeros((retract, 7))
+        u = np.arange(1, retract + 1, dtype=np.float64) / retract
+        r[:, 0] = cx + slide[0]
+        r[:, 1] = cy + slide[1]
+        r[:, 2] = z0 - depth * (1.0 - u)
+        r[:, 3:] = IDENTITY_QUAT
+        poses.append(r)
+    poses = np.concatenate(poses)
+    return dict(name="slide_18k", cfg=cfg, dt=1e-5, steps=len(poses) - 1, poses=poses,
+                render=default_render(0.25e-3, 96, 96))
+
+
 def gelsight_contact(seed: int = 0, steps: int = 2000, scale: int = 1):
     """The 1.6M-particle GelSight-sized workload: 20 x 20 x 4 mm block as a
     200 x 200 x 40 lattice (0.1 mm), grid 256 x 256 x 64 at 0.1 mm, neo-Hookean

@@ -716,3 +716,81 @@ def test_run_until_force_stops_at_the_first_crossing(oracle_lib):
     assert np.array_equal(sim.particles()[0], states[i])
     assert oracle_lib.OracleSim(cfg, poses[0]).run_until_force(poses, dt, math.inf, 0, n) == n
     assert oracle_lib.OracleSim(cfg, poses[0]).run_until_force(poses, dt, -math.inf, 0, n) == 1
+
+
+def _slide_forces(oracle_lib, model, mu, **kw):
+    wl = W.slide_contact(**kw)
+    sim = oracle_lib.OracleSim(wl["cfg"], wl["poses"][0])
+    sim.set_contact(model, mu)
+    F = []
+    for k in range(wl["steps"]):
+        assert sim.step(wl["poses"][k + 1], wl["dt"]) == 0
+        F.append(sim.force())
+    return np.array(F)
+
+
+def test_coulomb_contact_obeys_the_friction_law(oracle_lib):
+    """Coulomb contact (friction is future work in the paper, Sec. VI): a
+    nearly flat indenter (sphere of 1 m radius) pressed 0.3 mm and slid 1 mm
+    along +x. The friction force opposes the slide and never exceeds mu times
+    the normal force; once the whole contact slips it equals mu times it. At
+    mu = 0 no tangential force arises (the normals tilt by at most 1.2 %).
+    No-slip contact instead shears the gel well past mu = 0.3."""
+    kw = dict(radius=1.0, depth=0.3e-3, slide=(1e-3, 0.0), steps_press=150, steps_slide=250)
+    F = _slide_forces(oracle_lib, 1, 0.3, **kw)
+    slide = F[150:]
+    assert np.all(slide[:, 2] > 0)
+    ratio = -slide[:, 0] / slide[:, 2]
+    assert ratio.max() <= 0.3 * 1.02
+    assert 0.27 <= ratio[-40:].mean() <= 0.305, ratio[-40:].mean()
+    F0 = _slide_forces(oracle_lib, 1, 0.0, **kw)
+    assert np.abs(F0[150:, 0] / F0[150:, 2]).max() <= 2e-3
+    Fs = _slide_forces(oracle_lib, 0, 0.0, **kw)
+    assert -Fs[-1, 0] / Fs[-1, 2] > 0.4
+
+
+def test_coulomb_contact_does_not_pull(oracle_lib):
+    """Lifting the indenter off the gel: no-slip contact holds the surface
+    nodes and pulls the indenter down (negative normal force), Coulomb
+    contact lets them go (nodes moving apart keep their velocity)."""
+    kw = dict(radius=3e-3, depth=0.3e-3, slide=(0.5e-3, 0.0), steps_press=150, steps_slide=50, retract=150)
+    sticky = _slide_forces(oracle_lib, 0, 0.0, **kw)
+    coulomb = _slide_forces(oracle_lib, 1, 0.3, **kw)
+    assert sticky[-150:, 2].min() < -1e-3
+    assert coulomb[-150:, 2].min() >= -1e-12
+
+
+def test_particle_indenter(oracle_lib):
+    """The indenter as particles (Eq. 10's set I; objects enter as point
+    clouds, Sec. IV-B): the scattered indenter mass is the points' mass
+    exactly (the weights of Eq. 2 are a partition of unity; points whose
+    stencil leaves the grid are ignored); without mass there is no contact;
+    the press force grows with the mass per point and with the cloud's
+    density (a sparse cloud lets the gel in between its points)."""
+    wl = W.small_sphere_contact(seed=0, steps=1000, jitter=False)
+    cfg, poses, dt = wl["cfg"], wl["poses"], wl["dt"]
+    m = cfg["rho"] * (cfg["block_size"][0] / cfg["n"][0]) ** 3
+    S = 300
+
+    def press(pts, mass):
+        sim = oracle_lib.OracleSim(cfg, poses[0])
+        sim.set_indenter_points(pts, mass)
+        for k in range(S):
+            assert sim.step(poses[k + 1], dt) == 0
+        return sim
+
+    dense = W.sphere_points(3e-3, 20000, 1e-3, 0)
+    sim = press(dense, 10 * m)
+    # points in the grid at the last substep's start pose (identity rotation)
+    X = dense + poses[S - 1][:3]
+    base = np.floor((X - np.array(cfg["grid_origin"])) / cfg["dx"] - 0.5)
+    inside = np.all((base >= 0) & (base <= np.array(cfg["gn"]) - 3), axis=1)
+    assert 0 < inside.sum() < len(dense)
+    assert abs(sim.indenter_mass().sum() - inside.sum() * 10 * m) <= 1e-12 * inside.sum() * 10 * m
+    f_dense = sim.force()[2]
+    assert f_dense > 0
+    assert press(dense, 0.0).force()[2] == 0.0
+    assert press(dense, 100 * m).force()[2] > f_dense
+    assert press(dense, 1 * m).force()[2] < f_dense
+    sparse = W.sphere_points(3e-3, 2000, 1e-3, 0)
+    assert press(sparse, 10 * m).force()[2] < f_dense
