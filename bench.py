@@ -183,12 +183,18 @@ def streaming_leg(n=200):
             for npts in (10_000, 100_000, 1_000_000):
                 sim.set_indenter_points(W.sphere_points(wl["cfg"]["sp"][0], npts, 0.5e-3, 0), 10 * m)
                 sim.sync()
+                sim.timing_enable(("grid",))
+                sim.timing_read(reset=True)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 sim.run(poses[k:k + n], dt)
                 sim.sync()
                 res[f"points_{npts}_us_per_substep"] = (time.perf_counter() - t0) / n * 1e6
+                g = sim.timing_read(reset=True)["grid"]
+                # clear + scatter + grid update
+                res[f"grid_ms_points_{npts}"] = g[0] / max(1, g[1])
                 k += n
+            sim.timing_enable(())
             sim.set_indenter_points(np.zeros((0, 3)), 0.0)
         res["particles"] = sim.N
         sim.close()

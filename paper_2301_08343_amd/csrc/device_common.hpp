@@ -103,6 +103,7 @@ struct IndenterDev {
     T mu;                  // Coulomb friction coefficient (grid kernels instantiated with friction)
     T eps;                 // [m] step of the central differences giving the contact normal
     const double *MI;      // particle indenter: its mass per grid node (x fastest), else null
+    int blo[3], bhi[3];    // node box (inclusive) outside which MI is zero this substep
 };
 
 template <typename T> __device__ __forceinline__ T tfloor(T x);

@@ -509,7 +509,8 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
                 const double pz = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
                 // particle indenter: the node is in contact where the points
                 // scattered mass; else where the shape's signed distance is <= 0
-                const double mi = CONTACT == CONTACT_PARTICLES
+                const double mi = CONTACT == CONTACT_PARTICLES && gx >= I.blo[0] && gx <= I.bhi[0] &&
+                                          gy >= I.blo[1] && gy <= I.bhi[1] && gz >= I.blo[2] && gz <= I.bhi[2]
                                       ? I.MI[gx + (int64_t)S.g0 * (gy + (int64_t)S.g1 * gz)]
                                       : 0.0;
                 if (CONTACT == CONTACT_PARTICLES ? mi > 0.0 : indenter_phi<double>(I, px, py, pz) <= 0.0) {
@@ -572,6 +573,18 @@ template <typename T, int B, int CONTACT>
 __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
 {
     grid_block<T, B, kWG, CONTACT>(S, blockIdx.x, I, dt);
+}
+
+// Zeroes MI over the node box lo..hi (inclusive; x fastest in MI).
+__global__ void __launch_bounds__(kWG) k_clear_box(double *MI, int g0, int g1, int lo0, int lo1, int lo2, int nx,
+                                                   int ny, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i >= n) return;
+    const int x = (int)(i % nx);
+    const int64_t t = i / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+    MI[(lo0 + x) + (int64_t)g0 * ((lo1 + y) + (int64_t)g1 * (lo2 + z))] = 0.0;
 }
 
 // Particle indenter: each point (indenter frame, metres) placed at the pose

@@ -280,6 +280,7 @@ struct tacchi_sim {
     int ni = 0;
     double imass = 0.0;       // mass per point [kg]
     double *MI = nullptr;     // indenter mass per grid node
+    double plo[3], phi_[3];   // bounding box of the points, indenter frame [m]
     double dtA = 0.0;     // dt the stored affine matrices were formed with
     double dt_phase = 0.0;
     SimDev<float> sf;
@@ -485,12 +486,35 @@ tacchi_status do_grid(tacchi_sim *s, const double pose_end[7], double dt)
                                   : (s->contact_model == TACCHI_CONTACT_COULOMB ? CONTACT_COULOMB : CONTACT_STICKY);
     KernelTimer t(s, KC_GRID);
     if (contact == CONTACT_PARTICLES) {
-        // the points' mass on the grid at the substep's start pose
-        const int64_t nn = (int64_t)S.g0 * S.g1 * S.g2;
+        // the points' mass on the grid at the substep's start pose, within the
+        // node box of their stencils (the points' bounding box at that pose,
+        // one node of slack for rounding); the grid update reads MI only there
+        double R[9];
+        quat_matrix(s->pose + 3, R);
+        const int gdim[3] = {S.g0, S.g1, S.g2};
+        int64_t nbox = 1;
+        for (int a = 0; a < 3; ++a) {
+            double lo = 1e300, hi = -1e300;
+            for (int c = 0; c < 8; ++c) {
+                const double l[3] = {(c & 1) ? s->phi_[0] : s->plo[0], (c & 2) ? s->phi_[1] : s->plo[1],
+                                     (c & 4) ? s->phi_[2] : s->plo[2]};
+                const double w = s->pose[a] + R[3 * a] * l[0] + R[3 * a + 1] * l[1] + R[3 * a + 2] * l[2];
+                lo = std::min(lo, w);
+                hi = std::max(hi, w);
+            }
+            const double glo = std::floor((lo - s->cfg.grid.origin[a]) / s->d.dx - 0.5) - 1.0;
+            const double ghi = std::floor((hi - s->cfg.grid.origin[a]) / s->d.dx - 0.5) + 3.0;
+            I.blo[a] = (int)std::max(0.0, std::min(glo, (double)gdim[a]));
+            I.bhi[a] = (int)std::max(-1.0, std::min(ghi, (double)(gdim[a] - 1)));
+            nbox *= std::max(0, I.bhi[a] - I.blo[a] + 1);
+        }
         I.MI = s->MI;
-        hipLaunchKernelGGL(k_fill<double>, dim3(grid1d(nn)), dim3(kWG), 0, s->stream, s->MI, nn, 0.0);
-        hipLaunchKernelGGL(k_indenter_scatter, dim3(grid1d(s->ni)), dim3(kWG), 0, s->stream, s->ipts, s->ni, I, S.g0,
-                           S.g1, S.g2, s->imass, s->MI);
+        if (nbox > 0) {
+            hipLaunchKernelGGL(k_clear_box, dim3(grid1d(nbox)), dim3(kWG), 0, s->stream, s->MI, S.g0, S.g1, I.blo[0],
+                               I.blo[1], I.blo[2], I.bhi[0] - I.blo[0] + 1, I.bhi[1] - I.blo[1] + 1, nbox);
+            hipLaunchKernelGGL(k_indenter_scatter, dim3(grid1d(s->ni)), dim3(kWG), 0, s->stream, s->ipts, s->ni, I,
+                               S.g0, S.g1, S.g2, s->imass, s->MI);
+        }
     }
     const dim3 g(S.nblk), b(kWG);
     if (s->d.B == 4) {
@@ -1042,6 +1066,15 @@ tacchi_status tacchi_set_indenter_points(tacchi_sim *s, const double *xyz, int32
     if (!s->MI) TC_HIP(hipMalloc((void **)&s->MI, nn * sizeof(double)));
     TC_HIP(hipMalloc((void **)&s->ipts, (size_t)n * 3 * sizeof(double)));
     TC_HIP(hipMemcpy(s->ipts, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice));
+    for (int a = 0; a < 3; ++a) {
+        s->plo[a] = 1e300;
+        s->phi_[a] = -1e300;
+    }
+    for (int64_t k = 0; k < n; ++k)
+        for (int a = 0; a < 3; ++a) {
+            s->plo[a] = std::min(s->plo[a], xyz[3 * k + a]);
+            s->phi_[a] = std::max(s->phi_[a], xyz[3 * k + a]);
+        }
     s->ni = n;
     s->imass = mass;
     return TACCHI_OK;
