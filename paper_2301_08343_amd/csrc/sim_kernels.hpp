@@ -590,33 +590,108 @@ __global__ void __launch_bounds__(kWG) k_clear_box(double *MI, int g0, int g1, i
 // Particle indenter: each point (indenter frame, metres) placed at the pose
 // of the substep's start scatters w * mass to its 3x3x3 nodes (the weights
 // of Eq. 2) in the dense node array MI (x fastest, cleared before); points
-// whose nodes leave the grid are ignored. FP64 atomics.
+// whose nodes leave the grid are ignored. The points are stored in spatial
+// (Morton) order, so a workgroup's points cover a small node box: their
+// weights are summed in an LDS tile over that box (LDS FP64 atomics) and
+// flushed with one global FP64 atomic per touched node, instead of 27 global
+// atomics per point on nodes shared by ~100 points. A workgroup whose box
+// exceeds the tile, or holds more than half as many nodes as its points have
+// weights (a sparse cloud: the tile would save little), adds its points
+// directly.
+constexpr int kScatterEdge = 16;
+
+// The (z, y) node offsets of step (cc, bc) of a point's scatter, rotated by
+// the lane: neighbouring points of the spatially sorted cloud share most of
+// their nodes, and same-address atomics of one wave serialise, so each lane
+// starts at a different (z, y) row. Returns the offsets and w_z * w_y.
+__device__ __forceinline__ void rotated_pair(int cc, int bc, const double (&w)[3][3], int &c, int &bb, double &wzy)
+{
+    const int lane = threadIdx.x & 63;
+    c = cc + lane % 3;
+    c = c >= 3 ? c - 3 : c;
+    bb = bc + (lane / 3) % 3;
+    bb = bb >= 3 ? bb - 3 : bb;
+    const double wz = c == 0 ? w[2][0] : (c == 1 ? w[2][1] : w[2][2]);
+    const double wy = bb == 0 ? w[1][0] : (bb == 1 ? w[1][1] : w[1][2]);
+    wzy = wz * wy;
+}
+
 __global__ void __launch_bounds__(kWG) k_indenter_scatter(const double *pts, int n, IndenterDev<double> I, int g0,
                                                           int g1, int g2, double mass, double *MI)
 {
-    const int k = blockIdx.x * kWG + threadIdx.x;
-    if (k >= n) return;
-    const double l0 = pts[3 * k], l1 = pts[3 * k + 1], l2 = pts[3 * k + 2];
-    const double ir = 1.0 / I.dx;
-    // grid coordinates: origin + R l (R indenter frame -> world, row-major)
-    const double xg[3] = {I.tip[0] + (I.R[0] * l0 + I.R[1] * l1 + I.R[2] * l2) * ir,
-                          I.tip[1] + (I.R[3] * l0 + I.R[4] * l1 + I.R[5] * l2) * ir,
-                          I.tip[2] + (I.R[6] * l0 + I.R[7] * l1 + I.R[8] * l2) * ir};
-    const int gn[3] = {g0, g1, g2};
-    int base[3];
-    double w[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double b = floor(xg[a] - 0.5);
-        if (!(b >= 0.0 && b <= (double)(gn[a] - 3))) return;
-        base[a] = (int)b;
-        bspline3<double>(xg[a] - b, w[a]);
+    __shared__ double tile[kScatterEdge * kScatterEdge * kScatterEdge];
+    __shared__ int bmin[3], bmax[3], nvalid;
+    if (threadIdx.x < 3) {
+        bmin[threadIdx.x] = 0x7fffffff;
+        bmax[threadIdx.x] = -1;
     }
-    for (int c = 0; c < 3; ++c)
-        for (int bb = 0; bb < 3; ++bb)
-            for (int a = 0; a < 3; ++a)
-                atomicAdd(&MI[(base[0] + a) + (int64_t)g0 * ((base[1] + bb) + (int64_t)g1 * (base[2] + c))],
-                          w[0][a] * w[1][bb] * w[2][c] * mass);
+    if (threadIdx.x == 0) nvalid = 0;
+    __syncthreads();
+    const int k = blockIdx.x * kWG + threadIdx.x;
+    const int gn[3] = {g0, g1, g2};
+    int base[3] = {0, 0, 0};
+    double w[3][3];
+    bool ok = k < n;
+    if (ok) {
+        const double l0 = pts[3 * k], l1 = pts[3 * k + 1], l2 = pts[3 * k + 2];
+        const double ir = 1.0 / I.dx;
+        // grid coordinates: origin + R l (R indenter frame -> world, row-major)
+        const double xg[3] = {I.tip[0] + (I.R[0] * l0 + I.R[1] * l1 + I.R[2] * l2) * ir,
+                              I.tip[1] + (I.R[3] * l0 + I.R[4] * l1 + I.R[5] * l2) * ir,
+                              I.tip[2] + (I.R[6] * l0 + I.R[7] * l1 + I.R[8] * l2) * ir};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double b = floor(xg[a] - 0.5);
+            ok = ok && b >= 0.0 && b <= (double)(gn[a] - 3);
+            base[a] = ok ? (int)b : 0;
+            bspline3<double>(xg[a] - b, w[a]);
+        }
+    }
+    if (ok) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&bmin[a], base[a]);
+            atomicMax(&bmax[a], base[a]);
+        }
+        atomicAdd(&nvalid, 1);
+    }
+    __syncthreads();
+    if (bmax[0] < 0) return;  // no point of the workgroup in the grid
+    const int ex = bmax[0] - bmin[0] + 3, ey = bmax[1] - bmin[1] + 3, ez = bmax[2] - bmin[2] + 3;
+    if (ex <= kScatterEdge && ey <= kScatterEdge && ez <= kScatterEdge && 2 * ex * ey * ez <= 27 * nvalid) {
+        const int ne = ex * ey * ez;
+        for (int i = threadIdx.x; i < ne; i += kWG) tile[i] = 0.0;
+        __syncthreads();
+        if (ok)
+            for (int cc = 0; cc < 3; ++cc)
+                for (int bc = 0; bc < 3; ++bc) {
+                    int c, bb;
+                    double wzy;
+                    rotated_pair(cc, bc, w, c, bb, wzy);
+                    for (int a = 0; a < 3; ++a)
+                        atomicAdd(&tile[((base[2] - bmin[2] + c) * ey + (base[1] - bmin[1] + bb)) * ex +
+                                        (base[0] - bmin[0] + a)],
+                                  w[0][a] * wzy * mass);
+                }
+        __syncthreads();
+        for (int i = threadIdx.x; i < ne; i += kWG) {
+            const double v = tile[i];
+            if (v != 0.0) {
+                const int x = i % ex, t = i / ex, y = t % ey, z = t / ey;
+                atomicAdd(&MI[(bmin[0] + x) + (int64_t)g0 * ((bmin[1] + y) + (int64_t)g1 * (bmin[2] + z))], v);
+            }
+        }
+    } else if (ok) {
+        for (int cc = 0; cc < 3; ++cc)
+            for (int bc = 0; bc < 3; ++bc) {
+                int c, bb;
+                double wzy;
+                rotated_pair(cc, bc, w, c, bb, wzy);
+                for (int a = 0; a < 3; ++a)
+                    atomicAdd(&MI[(base[0] + a) + (int64_t)g0 * ((base[1] + bb) + (int64_t)g1 * (base[2] + c))],
+                              w[0][a] * wzy * mass);
+            }
+    }
 }
 
 // ---------------------------------------------------------------- G2P

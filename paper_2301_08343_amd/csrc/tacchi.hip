@@ -1065,7 +1065,6 @@ tacchi_status tacchi_set_indenter_points(tacchi_sim *s, const double *xyz, int32
     const size_t nn = (size_t)s->d.g[0] * s->d.g[1] * s->d.g[2];
     if (!s->MI) TC_HIP(hipMalloc((void **)&s->MI, nn * sizeof(double)));
     TC_HIP(hipMalloc((void **)&s->ipts, (size_t)n * 3 * sizeof(double)));
-    TC_HIP(hipMemcpy(s->ipts, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice));
     for (int a = 0; a < 3; ++a) {
         s->plo[a] = 1e300;
         s->phi_[a] = -1e300;
@@ -1075,6 +1074,29 @@ tacchi_status tacchi_set_indenter_points(tacchi_sim *s, const double *xyz, int32
             s->plo[a] = std::min(s->plo[a], xyz[3 * k + a]);
             s->phi_[a] = std::max(s->phi_[a], xyz[3 * k + a]);
         }
+    // spatial (Morton) order at the grid spacing, so that the scatter's
+    // workgroups get compact groups of points
+    auto spread = [](uint64_t v) {
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffULL;
+        v = (v | v << 16) & 0x1f0000ff0000ffULL;
+        v = (v | v << 8) & 0x100f00f00f00f00fULL;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+        v = (v | v << 2) & 0x1249249249249249ULL;
+        return v;
+    };
+    std::vector<std::pair<uint64_t, int>> order((size_t)n);
+    for (int k = 0; k < n; ++k) {
+        uint64_t c[3];
+        for (int a = 0; a < 3; ++a)
+            c[a] = (uint64_t)std::min(std::max((xyz[3 * k + a] - s->plo[a]) / s->d.dx, 0.0), 2097151.0);
+        order[k] = {spread(c[0]) | spread(c[1]) << 1 | spread(c[2]) << 2, k};
+    }
+    std::sort(order.begin(), order.end());
+    std::vector<double> sorted((size_t)n * 3);
+    for (int k = 0; k < n; ++k)
+        for (int a = 0; a < 3; ++a) sorted[3 * (size_t)k + a] = xyz[3 * (size_t)order[k].second + a];
+    TC_HIP(hipMemcpy(s->ipts, sorted.data(), sorted.size() * sizeof(double), hipMemcpyHostToDevice));
     s->ni = n;
     s->imass = mass;
     return TACCHI_OK;
