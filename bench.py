@@ -84,6 +84,7 @@ def parse():
                     help="trained surrogate; its query-stream leg runs when the file exists")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-streaming", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--queries", type=int, default=5000)
     ap.add_argument("--plain-sample", type=int, default=512)
     return ap.parse_args()
@@ -143,7 +144,8 @@ def streaming_leg(n=200):
     from paper_2301_08343_amd.sim import Sim
     out = {}
     for name, wl, prec in (("gelsight_1.6M_fp32", W.gelsight_contact(seed=0, steps=2000), "f32"),
-                           ("sphere_18k_fp64", W.small_sphere_contact(seed=0, steps=1000), "f64")):
+                           ("sphere_18k_fp64", W.small_sphere_contact(seed=0, steps=1000), "f64"),
+                           ("sphere_18k_fp32", W.small_sphere_contact(seed=0, steps=1000), "f32")):
         poses, dt = wl["poses"], wl["dt"]
         sim = Sim(wl["cfg"], poses[0], precision=prec)
         sim.run(poses[1:21], dt)
@@ -163,7 +165,7 @@ def streaming_leg(n=200):
             sim.sync()
             res[mode + "_us_per_substep"] = (time.perf_counter() - t0) / n * 1e6
             k += n
-        if prec == "f32":
+        if name.startswith("gelsight"):
             # the grid update (where the contact model acts) under no-slip and
             # Coulomb contact, mid-press, from the library's HIP events
             for model, label in ((Sim.STICKY, "sticky"), (Sim.COULOMB, "coulomb")):
@@ -202,6 +204,34 @@ def streaming_leg(n=200):
     return out
 
 
+def batch_leg(n=256, substeps=2000):
+    """The uneven batch: n contacts (particle counts log-uniform in 2e4-4e5,
+    corotated material, tilted indenters; seeds 0 .. n-1) advanced together
+    through their whole presses by graph-captured batched launches; the
+    timed region is the run alone (creation and tuning excluded)."""
+    import collections
+    import torch
+    from paper_2301_08343_amd import workloads as W
+    from paper_2301_08343_amd.batch import Batch
+    contacts = [W.batch_contact(seed, steps=substeps) for seed in range(n)]
+    t0 = time.perf_counter()
+    b = Batch(contacts, substeps)
+    b.sync()
+    setup = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(substeps)
+    b.sync()
+    el = time.perf_counter() - t0
+    total = sum(c["particles"] for c in contacts)
+    choices = collections.Counter(f"B{t}_wg{w}" for t, w, _ in b.tuning())
+    fallbacks = sum(b.contact(i).polar_fallbacks() for i in range(n))
+    b.close()
+    return {"contacts": n, "particles": total, "substeps": substeps,
+            "particle_substeps_per_s": total * substeps / el, "seconds": el, "setup_seconds": setup,
+            "polar_fp64_fallbacks": fallbacks, "tuner_choices": dict(choices)}
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle (single thread) on the same workload for as many
     substeps as fit in about `budget_s` seconds."""
@@ -219,8 +249,16 @@ def cpu_baseline(wl, budget_s):
         if time.perf_counter() - t0 > budget_s or k + 1 >= len(wl["poses"]):
             break
     el = time.perf_counter() - t0
+    # and the 18,432-particle sphere press (the FP64 parity workload), 200 substeps
+    from paper_2301_08343_amd import workloads as W
+    sw = W.small_sphere_contact(seed=0, steps=1000)
+    small = oracle.OracleSim(sw["cfg"], sw["poses"][0])
+    t1 = time.perf_counter()
+    small.run(sw["poses"], sw["dt"], 0, 200)
+    el_small = time.perf_counter() - t1
     return {"value": n * k / el, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {k} substeps of the same {n}-particle press, FP64, one thread"}
+            "sample": f"first {k} substeps of the same {n}-particle press, FP64, one thread",
+            "sphere_18k_fp64_value": int(small.N) * 200 / el_small}
 
 
 def main():
@@ -345,6 +383,7 @@ def main():
     del sim
     torch.cuda.empty_cache()
     out["streaming"] = None if args.no_streaming else streaming_leg()
+    out["batch"] = None if args.no_batch else batch_leg()
     if not args.no_surrogate and os.path.exists(args.surrogate):
         out["surrogate"] = surrogate_leg(args)
     print(json.dumps(out), flush=True)
