@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-streaming", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=0,
+                    help="only time N surrogate training steps and N forward passes (batch 256, random data)")
     ap.add_argument("--queries", type=int, default=5000)
     ap.add_argument("--plain-sample", type=int, default=512)
     return ap.parse_args()
@@ -261,12 +263,45 @@ def cpu_baseline(wl, budget_s):
             "sphere_18k_fp64_value": int(small.N) * 200 / el_small}
 
 
+def surrogate_steps(n):
+    """The surrogate's own kernels alone: n training steps (forward, backward,
+    AdamW) and n forward passes at batch 256 on random data."""
+    import torch
+    from paper_2301_08343_amd.surrogate import Net, forward_flops
+    torch.cuda.set_device(0)
+    net = Net(batch=256, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(256, 64, 64, 2, device="cuda", generator=g)
+    y = torch.randn(256, 64, 64, 3, device="cuda", generator=g)
+    for _ in range(3):
+        net.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        net.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / n
+    t0 = time.perf_counter()
+    for _ in range(n):
+        net.forward(x)
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / n
+    f = forward_flops()
+    return {"metric": "surrogate training samples/s", "value": 256 / ts, "unit": "samples/s",
+            "train_step_ms": ts * 1e3, "train_tflops": 3 * f * 256 / ts / 1e12,
+            "forward_ms": tf * 1e3, "forward_tflops": f * 256 / tf / 1e12, "batch": 256, "steps": n,
+            "peak_tflops_bf16_dense": 2500.0, "dtype": "bf16 storage, fp32 accumulation"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is not built", file=sys.stderr)
         sys.exit(2)
+    if args.surrogate_steps > 0:
+        print(json.dumps(surrogate_steps(args.surrogate_steps)), flush=True)
+        return
     import numpy as np
     import torch
     from paper_2301_08343_amd import workloads as W
