@@ -297,27 +297,149 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h,
     if (do_bias && tid < 32 && co0 + tid < cout) bpart[(int64_t)split * cout + co0 + tid] = bsum;
 }
 
-// dw[co][tap][ci] = sum over splits (fixed order) of the partials, ci < cin.
-__global__ void k_wgrad_reduce(const float *part, int splits, int cout, int taps, int cin, int cin_p, float *dw)
+// All nine taps of a 3x3 weight gradient per workgroup (32 output x 32 input
+// channels): the input rows a tap reads are the chunk's own rows shifted by
+// dh rows and dw pixels, so the chunk plus one row above and below is staged
+// once, in three copies pre-shifted by dw = -1, 0, +1 (zero where the shift
+// leaves the row, and zero for rows of another image), and every tap reads
+// its MFMA operand from a 16-byte aligned offset of one copy. The per-tap
+// kernel reads the output gradient and the input once per tap. Requires
+// chunks inside one image (h w % kWgChunk == 0) and 16 <= w <= 64, w % 16 == 0.
+constexpr int kW9Halo = kWgChunk + 2 * 64;
+
+__global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h, int w, int in_ld, int in_off,
+                                                int cin_p, const uint16_t *dout, int d_ld, int d_off, int cout,
+                                                int pix_per_split, float *part, float *bpart)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)cout * taps * cin;
-    if (idx >= total) return;
-    const int ci = (int)(idx % cin);
-    const int64_t ct = idx / cin;  // co * taps + tap
-    float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += part[((int64_t)k * cout * taps + ct) * cin_p + ci];
-    dw[idx] = s;
+    __shared__ __align__(16) uint16_t sA[32][kWgChunk + 8];     // [co][pixel]
+    __shared__ __align__(16) uint16_t sB[3][32][kW9Halo + 8];   // [dw + 1][ci][haloed pixel]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int hw = h * w, npix = n * hw;
+    const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32, split = blockIdx.z;
+    const int pbeg = split * pix_per_split, pend = min(npix, pbeg + pix_per_split);
+    const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
+    const bool do_bias = bpart != nullptr && blockIdx.y == 0;
+    const int halo = kWgChunk + 2 * w;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    const int lp = tid >> 3, lc = (tid & 7) * 4;
+    for (int p0 = pbeg; p0 < pend; p0 += kWgChunk) {
+        const int64_t ibeg = (int64_t)(p0 / hw) * hw, iend = ibeg + hw;
+        uint2 va[kWgChunk / 32], vb[kW9Halo / 32];
+#pragma unroll
+        for (int j = 0; j < kWgChunk / 32; ++j) {
+            const int p = p0 + lp + 32 * j;
+            va[j] = uint2{0u, 0u};
+            if (p < pend && co0 + lc < cout) va[j] = *(const uint2 *)(dout + (int64_t)p * d_ld + d_off + co0 + lc);
+        }
+#pragma unroll
+        for (int j = 0; j < kW9Halo / 32; ++j) {
+            const int i = lp + 32 * j;
+            const int64_t r = (int64_t)p0 - w + i;
+            vb[j] = uint2{0u, 0u};
+            if (i < halo && r >= ibeg && r < iend && ci0 + lc < cin_p)
+                vb[j] = *(const uint2 *)(in + r * in_ld + in_off + ci0 + lc);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kWgChunk / 32; ++j) {
+            const int q = lp + 32 * j;
+            sA[lc + 0][q] = (uint16_t)(va[j].x & 0xffffu);
+            sA[lc + 1][q] = (uint16_t)(va[j].x >> 16);
+            sA[lc + 2][q] = (uint16_t)(va[j].y & 0xffffu);
+            sA[lc + 3][q] = (uint16_t)(va[j].y >> 16);
+        }
+#pragma unroll
+        for (int j = 0; j < kW9Halo / 32; ++j) {
+            const int i = lp + 32 * j;
+            if (i < halo) {
+                const uint16_t v[4] = {(uint16_t)(vb[j].x & 0xffffu), (uint16_t)(vb[j].x >> 16),
+                                       (uint16_t)(vb[j].y & 0xffffu), (uint16_t)(vb[j].y >> 16)};
+                const int ww = i % w;  // p0 - w is a row start
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    sB[1][lc + k][i] = v[k];
+                    // dw = +1: entry i-1 reads this pixel; the row's last entry reads past the row
+                    if (ww >= 1) sB[2][lc + k][i - 1] = v[k];
+                    if (ww == w - 1) sB[2][lc + k][i] = 0;
+                    // dw = -1: entry i+1 reads this pixel; the row's first entry reads before the row
+                    if (ww <= w - 2) sB[0][lc + k][i + 1] = v[k];
+                    if (ww == 0) sB[0][lc + k][i] = 0;
+                }
+            }
+        }
+        __syncthreads();
+        const int r16 = lane & 15, kg = (lane >> 4) * 8;
+#pragma unroll
+        for (int j = 0; j < kWgChunk / 32; ++j) {
+            const bf16x8 a8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[wm + r16][32 * j + kg]);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dh = t / 3 - 1, dwi = t % 3;
+                const bf16x8 b8 = __builtin_bit_cast(
+                    bf16x8, *(const uint4 *)&sB[dwi][wn + r16][w * (dh + 1) + 32 * j + kg]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc[t], 0, 0, 0);
+            }
+        }
+        if (do_bias && tid < 32) {
+            for (int q = 0; q < kWgChunk; ++q) bsum += bf2f(sA[tid][q]);
+        }
+    }
+    const int ci = ci0 + wn + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int co = co0 + wm + (lane >> 4) * 4 + v;
+            if (co < cout && ci < cin_p) part[(((int64_t)split * cout + co) * 9 + t) * cin_p + ci] = acc[t][v];
+        }
+    if (do_bias && tid < 32 && co0 + tid < cout) bpart[(int64_t)split * cout + co0 + tid] = bsum;
 }
 
-// Fixed-order sum over splits of per-split partials [splits][c].
-__global__ void k_colsum_reduce(const float *part, int splits, int c, float *out)
+// dw[co][tap][ci] = sum over splits of the partials, ci < cin. 32 outputs
+// per workgroup, 8 lanes per output: lane g sums splits g, g+8, ... and the
+// eight lane sums are added in lane order, a fixed order (bit-reproducible).
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float *part, int splits, int cout, int taps, int cin,
+                                                      int cin_p, float *dw)
 {
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= c) return;
+    __shared__ float red[8][33];
+    const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int64_t idx = (int64_t)blockIdx.x * 32 + o;
+    const int64_t total = (int64_t)cout * taps * cin;
     float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * c + ch];
-    out[ch] = s;
+    if (idx < total) {
+        const int ci = (int)(idx % cin);
+        const int64_t ct = idx / cin;  // co * taps + tap
+        for (int k = g; k < splits; k += 8) s += part[((int64_t)k * cout * taps + ct) * cin_p + ci];
+    }
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && idx < total) {
+        float t = 0.0f;
+        for (int q = 0; q < 8; ++q) t += red[q][o];
+        dw[idx] = t;
+    }
+}
+
+// Sum over splits of per-split partials [splits][c], as k_wgrad_reduce
+// (32 channels per workgroup, 8 lanes each, fixed order).
+__global__ void __launch_bounds__(256) k_colsum_reduce(const float *part, int splits, int c, float *out)
+{
+    __shared__ float red[8][33];
+    const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int ch = blockIdx.x * 32 + o;
+    float s = 0.0f;
+    if (ch < c)
+        for (int k = g; k < splits; k += 8) s += part[(int64_t)k * c + ch];
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && ch < c) {
+        float t = 0.0f;
+        for (int q = 0; q < 8; ++q) t += red[q][o];
+        out[ch] = t;
+    }
 }
 
 // 1x1 head, FP32 output gradient: partial sums of dout^T in (cout x cin) and
@@ -821,8 +943,23 @@ tsg_status tsg_conv(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t
     return launch_conv_epi<1, 1>(a, epi, st);
 }
 
-static int wgrad_splits(int64_t npix, int cout, int cin_p, int taps)
+// the all-taps kernel applies where its chunks stay inside one image and
+// its shifted rows stay aligned
+static bool wgrad9_ok(int h, int w, int taps)
 {
+    return taps == 9 && w >= 16 && w <= 64 && w % 16 == 0 && ((int64_t)h * w) % kWgChunk == 0;
+}
+
+static int wgrad_splits(int64_t npix, int h, int w, int cout, int cin_p, int taps)
+{
+    if (wgrad9_ok(h, w, taps)) {
+        // ~2 workgroups per CU (the staged halo takes ~59 KB of LDS), each
+        // over at least 4 chunks
+        const int64_t tiles = (int64_t)((cout + 31) / 32) * ((cin_p + 31) / 32);
+        int64_t s = std::max<int64_t>(1, 512 / tiles);
+        s = std::min<int64_t>(s, std::max<int64_t>(1, npix / (4 * kWgChunk)));
+        return (int)s;
+    }
     const int64_t tiles = (int64_t)((cout + 31) / 32) * taps * ((cin_p + 31) / 32);
     int64_t s = std::max<int64_t>(1, 2048 / tiles);
     s = std::min<int64_t>(s, std::max<int64_t>(1, npix / 256));
@@ -832,7 +969,7 @@ static int wgrad_splits(int64_t npix, int cout, int cin_p, int taps)
 size_t tsg_wgrad_scratch_bytes(int32_t n, int32_t h, int32_t w, int32_t cin_p, int32_t cout, int32_t taps)
 {
     const int64_t npix = (int64_t)n * h * w;
-    const int s = wgrad_splits(npix, cout, cin_p, taps);
+    const int s = wgrad_splits(npix, h, w, cout, cin_p, taps);
     const size_t part = (size_t)s * cout * taps * cin_p * sizeof(float);
     const size_t bias = (size_t)s * cout * sizeof(float);
     return part + bias;
@@ -849,19 +986,25 @@ tsg_status tsg_conv_wgrad(const uint16_t *in, int32_t n, int32_t h, int32_t w, i
         return fail(-1, "tsg_conv_wgrad: scratch too small");
     hipStream_t st = (hipStream_t)stream;
     const int64_t npix = (int64_t)n * h * w;
-    const int splits = wgrad_splits(npix, cout, cin_p, taps);
+    const int splits = wgrad_splits(npix, h, w, cout, cin_p, taps);
     int pps = (int)((npix + splits - 1) / splits);
     pps = ((pps + kWgChunk - 1) / kWgChunk) * kWgChunk;
     float *bpart = db ? scratch + (size_t)splits * cout * taps * cin_p : nullptr;
-    const dim3 grid((cout + 31) / 32, taps * ((cin_p + 31) / 32), splits);
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld, d_off, cout,
-                       taps, pps, scratch, bpart);
+    if (wgrad9_ok(h, w, taps)) {
+        const dim3 grid((cout + 31) / 32, (cin_p + 31) / 32, splits);
+        hipLaunchKernelGGL(k_wgrad9, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld, d_off,
+                           cout, pps, scratch, bpart);
+    } else {
+        const dim3 grid((cout + 31) / 32, taps * ((cin_p + 31) / 32), splits);
+        hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld, d_off,
+                           cout, taps, pps, scratch, bpart);
+    }
     TSG_LAUNCHED();
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks_for((int64_t)cout * taps * cin)), dim3(256), 0, st, scratch, splits,
-                       cout, taps, cin, cin_p, dw);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(((int64_t)cout * taps * cin + 31) / 32)), dim3(256), 0, st,
+                       scratch, splits, cout, taps, cin, cin_p, dw);
     TSG_LAUNCHED();
     if (db) {
-        hipLaunchKernelGGL(k_colsum_reduce, dim3(blocks_for(cout, 64)), dim3(64), 0, st, bpart, splits, cout, db);
+        hipLaunchKernelGGL(k_colsum_reduce, dim3((cout + 31) / 32), dim3(256), 0, st, bpart, splits, cout, db);
         TSG_LAUNCHED();
     }
     return 0;

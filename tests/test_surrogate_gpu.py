@@ -151,6 +151,11 @@ def test_conv_input_gradient(T, case, fuse_gelu):
     (2, 16, 16, 64, 64, 64, 0, 32, 64, 32, 9),
     (1, 8, 8, 40, 40, 48, 8, 24, 24, 0, 9),
     (3, 33, 31, 32, 32, 32, 0, 64, 64, 0, 9),
+    # the all-taps kernel (h w a multiple of 128, 16 <= w <= 64): widths 32 and 64,
+    # partial channel blocks, strided and offset layouts, several images
+    (2, 32, 32, 32, 32, 32, 0, 32, 32, 0, 9),
+    (1, 64, 64, 40, 48, 48, 0, 24, 24, 0, 9),
+    (3, 16, 16, 20, 24, 48, 24, 36, 40, 4, 9),
 ])
 def test_conv_weight_gradient(T, case):
     n, h, w, cin, cin_p, ld, off, cout, gld, goff, taps = case
