@@ -287,10 +287,33 @@ def surrogate_steps(n):
     torch.cuda.synchronize()
     tf = (time.perf_counter() - t0) / n
     f = forward_flops()
+    # per forward convolution: HIP events on the launching stream around each
+    # layer of one extra forward pass (median of 5 passes)
+    runs = []
+    for _ in range(5):
+        net.layer_timer = []
+        net.forward(x)
+        torch.cuda.synchronize()
+        runs.append(net.layer_timer)
+    net.layer_timer = None
+    peak_tf, peak_gbs = 2500.0, HBM_PEAK_GBS
+    layers = []
+    for k, (name, _, nb, r, cin_p, co, taps, z, _, _) in enumerate(runs[0]):
+        ms = sorted(run[k][8].elapsed_time(run[k][9]) for run in runs)[2]
+        ci = next(c for nm, c, _, _ in net.specs if nm == name)
+        flops = 2.0 * nb * r * r * co * taps * ci
+        # input read once, output (and the stored pre-activation) written once, weights once
+        nbytes = 2.0 * nb * r * r * (cin_p + co * (2 if z else 1)) + 2.0 * co * taps * cin_p
+        ai = flops / nbytes
+        bound = "mfma" if ai > peak_tf * 1e12 / (peak_gbs * 1e9) else "hbm"
+        tfs, gbs = flops / (ms * 1e-3) / 1e12, nbytes / (ms * 1e-3) / 1e9
+        layers.append({"layer": name, "pixels": r * r, "cin": ci, "cout": co, "us": ms * 1e3, "tflops": tfs,
+                       "GBps": gbs, "flop_per_byte": ai, "bound": bound,
+                       "frac": tfs / peak_tf if bound == "mfma" else gbs / peak_gbs})
     return {"metric": "surrogate training samples/s", "value": 256 / ts, "unit": "samples/s",
             "train_step_ms": ts * 1e3, "train_tflops": 3 * f * 256 / ts / 1e12,
             "forward_ms": tf * 1e3, "forward_tflops": f * 256 / tf / 1e12, "batch": 256, "steps": n,
-            "peak_tflops_bf16_dense": 2500.0, "dtype": "bf16 storage, fp32 accumulation"}
+            "peak_tflops_bf16_dense": peak_tf, "dtype": "bf16 storage, fp32 accumulation", "layers": layers}
 
 
 def main():

@@ -83,6 +83,8 @@ class Net:
         self.L = len(enc)
         self.dev = torch.device(device)
         self.specs = layer_specs(self.enc, mid)
+        # a list to collect HIP events around each convolution launch (timing only), else None
+        self.layer_timer = None
         self.N = native
         native.tsg()
         # flat FP32 master parameters, gradients and moments
@@ -209,10 +211,19 @@ class Net:
         wp = self.wt[name] if transposed else self.wf[name]
         bias = None if transposed else _ptr(self.param(name)[1])
         cout = cout if cout is not None else (self.cin_p[name] if transposed else co)
+        timer = getattr(self, "layer_timer", None)
+        if timer is not None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record()
         native.tsg_call("tsg_conv", _ptr(src), n, r, r, src_ld, src_off, cin_p, _ptr(wp), bias, cout, t, epi,
                         _ptr(out) if out is not None else None, out_ld, out_off,
                         _ptr(z) if z is not None else None, z_ld, z_off,
                         _ptr(self.out) if epi == F32 else None, self._stream())
+        if timer is not None:
+            e1 = torch.cuda.Event(enable_timing=True)
+            e1.record()
+            # (layer, transposed, n, r, input channels as stored, output channels, taps, GELU z stored, events)
+            timer.append((name, transposed, n, r, cin_p, cout, t, z is not None, e0, e1))
 
     def _wgrad(self, name, n, r, src, src_ld, src_off, cin, cin_p, g, g_ld, g_off):
         _, _, co, t = next(s for s in self.specs if s[0] == name)
