@@ -13,7 +13,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
+# The planted-mistake tests point this at a build of a mutated copy of
+# oracle.c, to show that the pins catch the mistake.
+LIB_PATH = os.environ.get("TACCHI_ORACLE_LIB") or _DEFAULT_LIB
 SOURCES = [os.path.join(_HERE, "oracle.c")]
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall", "-Wextra",
           "-fPIC", "-shared"]
@@ -21,6 +24,8 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall", "-W
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (strict IEEE FP64: no contraction, no fast-math)."""
+    if LIB_PATH != _DEFAULT_LIB:
+        return LIB_PATH  # a mutated build, used as given
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, *SOURCES, "-o", tmp, "-lm"])

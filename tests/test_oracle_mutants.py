@@ -1,0 +1,115 @@
+"""Planted mistakes in the oracle: each one must fail a pin.
+
+Every case below copies oracle.c, plants one plausible mistake (a dropped
+term, a wrong sign, constant or index, a transposed operand, an off-by-one
+boundary), builds the copy with gcc and runs the pin tests named for it
+against that build in a child process; the case passes when a pin fails.
+This is what makes the pins a check of the oracle rather than of
+themselves. CPU only; nothing here touches the HIP library.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE_C = os.path.join(ROOT, "oracle", "oracle.c")
+
+# (name, text in oracle.c, replacement, pins expected to catch it (pytest -k))
+MUTANTS = [
+    ("bspline_centre_coefficient",
+     "if (a < 0.5) return 0.75 - a * a;", "if (a < 0.5) return 0.75 - 0.5 * a * a;", "bspline_moments"),
+    ("bspline_outer_square_dropped",
+     "return 0.5 * (1.5 - a) * (1.5 - a);", "return 0.5 * (1.5 - a);", "bspline_moments"),
+    ("stencil_base_off_by_half",
+     "double b = floor(xi - 0.5);", "double b = floor(xi);", "p2g_mass_and_linear_momentum"),
+    ("lattice_not_cell_centred",
+     "(idx[a] + 0.5) * s->h[a];", "idx[a] * s->h[a];", "symmetric_press"),
+    ("apic_affine_term_without_mass",
+     "s->m * vp[r] + s->m * Cd", "s->m * vp[r] + Cd", "angular_momentum"),
+    ("stress_term_sign",
+     "double me = -dt * Dinv * wt", "double me = dt * Dinv * wt", "energy_gradient"),
+    ("p2g_stress_scale_1_over_dx2",
+     "Dinv = 4.0 / (dx * dx);\n    memset(s->M", "Dinv = 1.0 / (dx * dx);\n    memset(s->M", "energy_gradient"),
+    ("g2p_velocity_gradient_scale_dropped",
+     "Cn[k] = Dinv * B[k];", "Cn[k] = B[k];", "affine_field_reproduction"),
+    ("g2p_velocity_gradient_transposed",
+     "B[r * 3 + cc] += wt * Vq[r] * d[cc];", "B[cc * 3 + r] += wt * Vq[r] * d[cc];", "affine_field_reproduction"),
+    ("deformation_update_order",
+     "mat_mul(G, Fp, Fn);", "mat_mul(Fp, G, Fn);", "deformation_gradient_follows"),
+    ("neo_hookean_volume_term",
+     "(r == c ? lambda * lnJ : 0.0)", "(r == c ? lambda * (J - 1.0) : 0.0)", "textbook_energy"),
+    ("corotated_missing_Ft",
+     "mat_mul(D, Ft, DFt);", "memcpy(DFt, D, sizeof D);", "textbook_energy"),
+    ("lame_lambda_denominator",
+     "(1.0 - 2.0 * nu)", "(1.0 - nu)", "lame_parameters"),
+    ("polar_reflection_not_removed",
+     "if (mat_det(F) < 0.0) sig[kmin] = -sig[kmin];", "", "polar_decomposition"),
+    ("gravity_dropped",
+     "/ s->M[q] + dt * s->cfg.gravity[r];", "/ s->M[q];", "free_fall"),
+    ("advection_with_old_velocity",
+     "vp[r] = vn[r];\n            xp[r] = xp[r] + dt * vn[r];",
+     "xp[r] = xp[r] + dt * vp[r];\n            vp[r] = vn[r];", "free_fall"),
+    ("rigid_velocity_cross_sign",
+     "om[1] * r[2] - om[2] * r[1];", "om[2] * r[1] - om[1] * r[2];", "rigid_motion_of_the_pose"),
+    ("quaternion_matrix_sign",
+     "R[1] = 2 * (x * y - w * z);", "R[1] = 2 * (x * y + w * z);", "rotated_sphere"),
+    ("contact_force_sign",
+     "s->force[r] += s->M[q] * (V[r] - after[r]) / dt;", "s->force[r] += s->M[q] * (after[r] - V[r]) / dt;",
+     "run_until_force"),
+    ("floor_off_by_one",
+     "if (c <= s->cfg.floor_node)", "if (c < s->cfg.floor_node)", "walls_and_floor"),
+    ("wall_keeps_outward_velocity",
+     "if (idx[r] < wall && V[r] < 0.0)", "if (idx[r] < wall && V[r] > 0.0)", "walls_and_floor"),
+    ("bonded_layers_off_by_one",
+     "p / layer_size < s->cfg.n_fixed_layers", "p / layer_size <= s->cfg.n_fixed_layers", "free_fall"),
+    ("coulomb_friction_sign",
+     "1.0 + s->friction * un / tn", "1.0 - s->friction * un / tn", "friction_law"),
+    ("particle_indenter_blend_mass",
+     "/ (s->M[q] + s->MI[q]);", "/ s->M[q];", "particle_indenter"),
+    ("heightmap_transposed",
+     "H[(int64_t)j * n0 + i] = s->x[p * 3 + 2];", "H[(int64_t)i * n1 + j] = s->x[p * 3 + 2];", "heightmap_rows"),
+    ("render_normal_sign",
+     "double N[3] = {gx / nrm, gy / nrm, -1.0 / nrm};", "double N[3] = {-gx / nrm, -gy / nrm, -1.0 / nrm};",
+     "render_plane"),
+    ("render_central_difference_step",
+     "/ (2.0 * r);\n            double gy", "/ r;\n            double gy", "render_plane"),
+]
+
+
+def _run_mutant(tmpdir: str, name: str, old: str, new: str, select: str):
+    src = open(ORACLE_C).read()
+    assert src.count(old) == 1, f"{name}: the text to mutate must occur exactly once in oracle.c"
+    d = os.path.join(tmpdir, name)
+    os.makedirs(d, exist_ok=True)
+    c_path, so_path = os.path.join(d, "oracle.c"), os.path.join(d, "liboracle.so")
+    with open(c_path, "w") as f:
+        f.write(src.replace(old, new))
+    # the copy includes oracle.h from the oracle's own folder
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
+                           "-I", os.path.dirname(ORACLE_C), c_path, "-o", so_path, "-lm"])
+    env = dict(os.environ, TACCHI_ORACLE_LIB=so_path, PYTHONDONTWRITEBYTECODE="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        "-x", "-q", "-m", "not gpu", "-k", select, "-p", "no:cacheprovider"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode, r.stdout[-600:]
+
+
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    workers = min(8, os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda m: _run_mutant(str(tmp_path), *m), MUTANTS))
+    survivors = [(name, out) for name, rc, out in results if rc != 1]
+    # rc 1: tests ran and one failed; 0 would mean the mistake went unnoticed,
+    # anything else that the selection or the build is broken
+    assert not survivors, "planted mistakes not caught by the pins:\n" + "\n".join(
+        f"{n}:\n{o}" for n, o in survivors)
+
+
+@pytest.mark.parametrize("name,old,new,select", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutation_text_is_unique(name, old, new, select):
+    assert open(ORACLE_C).read().count(old) == 1

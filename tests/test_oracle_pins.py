@@ -183,6 +183,73 @@ def test_affine_field_reproduction(oracle_lib):
     np.testing.assert_allclose(F1, np.broadcast_to(np.eye(3) + dt * G, F1.shape), rtol=0, atol=1e-14)
 
 
+def test_deformation_gradient_follows_the_affine_field(oracle_lib):
+    """Eq. 9 for a stress-free material (E = 0) under an affine velocity field
+    v = G x + b, which the transfers carry exactly: the kinematics of the field,
+    dF/dt = G F, make one substep map any F to (I + dt G) F, with the field's
+    gradient on the left."""
+    cfg = small_cfg(pad=5, E=0.0)
+    sim = oracle_lib.OracleSim(cfg, FAR_POSE)
+    x, _, _, F = W.random_particle_state(23, cfg, f_scale=0.2)
+    assert np.abs(F - np.eye(3)).max() > 0.05
+    rng = W.SplitMix64(78)
+    G = np.array([[rng.uniform(-50, 50) for _ in range(3)] for _ in range(3)])
+    b = np.array([rng.uniform(-0.1, 0.1) for _ in range(3)])
+    sim.set_particles(x, x @ G.T + b, np.broadcast_to(G, (len(x), 3, 3)).copy(), F)
+    dt = 1e-5
+    assert sim.p2g(dt) == 0 and sim.grid_update(FAR_POSE, dt) == 0 and sim.g2p(dt) == 0
+    _, _, _, F1 = sim.particles()
+    np.testing.assert_allclose(F1, (np.eye(3) + dt * G) @ F, rtol=0, atol=1e-12)
+    assert np.abs(F1 - F @ (np.eye(3) + dt * G)).max() > 1e-6  # the order is visible at this size
+
+
+def test_walls_and_floor_hold_the_grid_velocity(oracle_lib):
+    """R8 on a uniform velocity field (P/M = v exactly, no stress): nodes
+    within wall_nodes of a grid face lose the velocity component that points
+    out of the grid, and keep the others; nodes at or below floor_node are held
+    at rest; every other node keeps v."""
+    cfg = small_cfg(n=(6, 5, 4), pad=4, E=0.0)
+    cfg["wall_nodes"], cfg["floor_node"] = 5, 5
+    sim = oracle_lib.OracleSim(cfg, FAR_POSE)
+    x, _, C, F = sim.particles()
+    u = np.array([-0.3, 0.2, -0.1])
+    sim.set_particles(x, np.broadcast_to(u, x.shape).copy(), C, F)
+    dt = 1e-6
+    assert sim.p2g(dt) == 0 and sim.grid_update(FAR_POSE, dt) == 0
+    M, _, V = sim.grid()
+    _, idx = node_positions(cfg)
+    g, wall = np.array(cfg["gn"]), cfg["wall_nodes"]
+    live = M > 0
+    expect = np.broadcast_to(u, V.shape).copy()
+    low, high = idx < wall, idx > g - 1 - wall
+    expect[low & (expect < 0)] = 0.0
+    expect[high & (expect > 0)] = 0.0
+    expect[idx[:, 2] <= cfg["floor_node"]] = 0.0
+    # the field reaches both the low x wall and the high y wall, and the floor
+    assert (live & low[:, 0]).any() and (live & high[:, 1]).any() and (live & (idx[:, 2] <= 5)).any()
+    assert (live & ~low.any(axis=1) & ~high.any(axis=1) & (idx[:, 2] > 5)).any()
+    np.testing.assert_allclose(V[live], expect[live], rtol=0, atol=1e-12)
+    assert np.abs(V[~live]).max() == 0.0
+
+
+def test_heightmap_rows_follow_the_lattice_y_axis(oracle_lib):
+    """The depth map is [n_y][n_x]: a top surface tilted differently along
+    world x and world y shows each slope along its own axis of the map."""
+    cfg = small_cfg(n=(6, 5, 4))
+    sim = oracle_lib.OracleSim(cfg, FAR_POSE)
+    x, v, C, F = sim.particles()
+    x = x.copy()
+    ax, ay = 3e-3, -7e-3
+    x[:, 2] += ax * x[:, 0] + ay * x[:, 1]
+    sim.set_particles(x, v, C, F)
+    H = sim.heightmap()
+    n0, n1 = cfg["n"][0], cfg["n"][1]
+    assert H.shape == (n1, n0)
+    h = cfg["block_size"][0] / n0
+    np.testing.assert_allclose(np.diff(H, axis=1), ax * h, rtol=1e-9)
+    np.testing.assert_allclose(np.diff(H, axis=0), ay * h, rtol=1e-9)
+
+
 # ------------------------------------------------------------------ P8 exact rational step
 
 def _bspline_q(r):
@@ -446,6 +513,58 @@ def test_indenter_velocity_rigid_motion(oracle_lib):
     v = oracle_lib.indenter_velocity(p0, p2, 1e-3, X)
     omega = np.array([0, 0, ang / 1e-3])
     np.testing.assert_allclose(v, np.cross(omega, X - p0[:3]), atol=1e-15)
+
+
+def test_indenter_velocity_is_the_rigid_motion_of_the_pose(oracle_lib):
+    """Against the posed rigid motion itself (scipy's rotations): the point
+    that sits at X at the start pose moves to pos1 + R1 R0^T (X - pos0) at the
+    end pose, so its displacement over dt matches the returned velocity up to
+    the second-order term of the small rotation."""
+    from scipy.spatial.transform import Rotation
+
+    def wxyz(r):
+        q = r.as_quat()
+        return np.array([q[3], q[0], q[1], q[2]])
+
+    R0 = Rotation.from_rotvec(np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8]) * 0.4)
+    dR = Rotation.from_rotvec(np.array([-0.6, 0.2, 0.45]) * 1e-4)
+    R1 = dR * R0
+    pos0, pos1 = np.array([1e-3, 2e-3, 3e-3]), np.array([1.2e-3, 1.9e-3, 2.95e-3])
+    dt = 1e-3
+    for X in (np.array([4e-3, -1e-3, 5e-3]), np.array([-2e-3, 3.5e-3, 0.5e-3])):
+        v = oracle_lib.indenter_velocity(np.concatenate([pos0, wxyz(R0)]), np.concatenate([pos1, wxyz(R1)]), dt, X)
+        X1 = pos1 + R1.apply(R0.inv().apply(X - pos0))
+        np.testing.assert_allclose(v, (X1 - X) / dt, rtol=0, atol=1e-7)
+
+
+def test_gap_of_a_rotated_sphere_is_the_lower_cap_of_its_moved_centre(oracle_lib):
+    """A sphere (tip at the pose, centre R above the tip in its own frame)
+    under a general rotation about its tip: its centre moves to
+    pos + Rot (0, 0, R) (scipy's rotation) and the lowest point on each
+    vertical line is that sphere's lower cap."""
+    from scipy.spatial.transform import Rotation
+    R = 2e-3
+    rot = Rotation.from_rotvec(np.array([0.3, -0.5, 0.8]) / np.linalg.norm([0.3, -0.5, 0.8]) * math.radians(25))
+    q = rot.as_quat()
+    pose = np.array([5e-3, 4e-3, 1e-3, q[3], q[0], q[1], q[2]])
+    c = pose[:3] + rot.apply([0.0, 0.0, R])
+    rng = W.SplitMix64(5)
+    for _ in range(40):
+        rho, ang = 0.9 * R * math.sqrt(rng.uniform(0, 1)), rng.uniform(0, 2 * math.pi)
+        x, y = c[0] + rho * math.cos(ang), c[1] + rho * math.sin(ang)
+        z = oracle_lib.lowest_point(W.SPHERE, [R], 0, pose, x, y, c[2] - 2 * R, c[2] + 2 * R)
+        assert abs(z - (c[2] - math.sqrt(R * R - rho * rho))) <= 1e-12
+
+
+def test_lame_parameters_give_back_E_and_nu(oracle_lib):
+    """mu and lambda from (E, nu) satisfy the inverse relations of isotropic
+    elasticity, E = mu (3 lambda + 2 mu) / (lambda + mu) and
+    nu = lambda / (2 (lambda + mu)), and K = lambda + 2 mu / 3 = E / (3 (1 - 2 nu))."""
+    for E, nu in ((0.15e6, 0.45), (1e5, 0.3), (2e9, 0.1)):
+        mu, lam = oracle_lib.lame(E, nu)
+        assert abs(mu * (3 * lam + 2 * mu) / (lam + mu) - E) <= 1e-13 * E
+        assert abs(lam / (2 * (lam + mu)) - nu) <= 1e-14
+        assert abs(lam + 2 * mu / 3 - E / (3 * (1 - 2 * nu))) <= 1e-13 * E
 
 
 # ------------------------------------------------------------------ P11-P13 whole-run physics
