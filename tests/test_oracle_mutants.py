@@ -1,9 +1,10 @@
 """Planted mistakes in the oracle: each one must fail a pin.
 
-Every case below copies oracle.c, plants one plausible mistake (a dropped
-term, a wrong sign, constant or index, a transposed operand, an off-by-one
-boundary), builds the copy with gcc and runs the pin tests named for it
-against that build in a child process; the case passes when a pin fails.
+Every case below copies oracle.c (or the network's reference,
+oracle/surrogate.py), plants one plausible mistake (a dropped term, a wrong
+sign, constant or index, a transposed operand, an off-by-one boundary),
+builds or loads the copy and runs the pin tests named for it against that
+copy in a child process; the case passes when a pin fails.
 This is what makes the pins a check of the oracle rather than of
 themselves. CPU only; nothing here touches the HIP library.
 """
@@ -18,6 +19,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE_C = os.path.join(ROOT, "oracle", "oracle.c")
+SURROGATE_PY = os.path.join(ROOT, "oracle", "surrogate.py")
 
 # (name, text in oracle.c, replacement, pins expected to catch it (pytest -k))
 MUTANTS = [
@@ -113,3 +115,78 @@ def test_every_planted_mistake_fails_a_pin(tmp_path):
 @pytest.mark.parametrize("name,old,new,select", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_mutation_text_is_unique(name, old, new, select):
     assert open(ORACLE_C).read().count(old) == 1
+
+
+# the network's reference: (name, text in surrogate.py, replacement, pins (pytest -k))
+SURROGATE_MUTANTS = [
+    ("tap_offsets_transposed", "(t // 3 - 1, t % 3 - 1)", "(t % 3 - 1, t // 3 - 1)", "conv_matches"),
+    ("conv_shift_sign", "_shifted(x, dh, dw) @ w[:, t, :].T", "_shifted(x, -dh, -dw) @ w[:, t, :].T", "conv_matches"),
+    ("dx_shift_sign", "dx += _shifted(gout @ w[:, t, :], -dh, -dw_)", "dx += _shifted(gout @ w[:, t, :], dh, dw_)",
+     "conv_backward"),
+    ("bias_grad_mean", "gout.sum(axis=(0, 1, 2))", "gout.mean(axis=(0, 1, 2))", "conv_backward"),
+    ("gelu_grad_density_term", " + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)", "", "gelu_closed"),
+    ("gelu_scale", "return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))", "return 0.5 * z * (1.0 + erf(z / 2.0))",
+     "gelu_closed"),
+    ("avgpool_backward_factor", "/ 4.0", "/ 2.0", "adjoint"),
+    ("upsample_backward_mean", "g.reshape(n, H // 2, 2, W // 2, 2, c).sum(axis=(2, 4))",
+     "g.reshape(n, H // 2, 2, W // 2, 2, c).mean(axis=(2, 4))", "adjoint"),
+    ("mse_gradient_factor", "2.0 * e / e.size", "e / e.size", "central_differences"),
+    ("adamw_no_bias_correction", "mh = m / (1.0 - b1 ** step)", "mh = m", "adamw"),
+    ("adamw_decay_dropped", "+ wd * p)", ")", "adamw"),
+    ("adamw_eps_inside_sqrt", "(np.sqrt(vh) + eps)", "np.sqrt(vh + eps)", "adamw"),
+    ("nearest_last_index_on_ties", "idx = np.argmin(d2, axis=1)",
+     "idx = d2.shape[1] - 1 - np.argmin(d2[:, ::-1], axis=1)", "ties"),
+    ("skip_concat_order", "np.concatenate([up, skips[l]], axis=-1)", "np.concatenate([skips[l], up], axis=-1)",
+     "match_torch_autograd"),
+    ("backward_split_swapped", "g_up, g_skip[l] = g[..., :c], g[..., c:]", "g_skip[l], g_up = g[..., :c], g[..., c:]",
+     "central_differences"),
+    ("pool_before_skip", "        skips.append(h)\n        h = S(avgpool2(h))",
+     "        h = S(avgpool2(h))\n        skips.append(upsample2(h))", "match_torch_autograd"),
+    ("he_init_std", "math.sqrt(2.0 / (ci * t))", "math.sqrt(1.0 / (ci * t))", "he_normal"),
+    ("bf16_round_half_up", "(u + 0x7FFF + ((u >> 16) & 1))", "(u + 0x8000)", "bf16_rounding"),
+    ("decoder_input_channels", '(f"dec{l}a", 2 * c, c, 9)', '(f"dec{l}a", c, c, 9)', "parameter_count"),
+    ("contact_residual_side", "contact_residual * np.minimum(x[..., 0], 0.0)",
+     "contact_residual * np.maximum(x[..., 0], 0.0)", "match_torch_autograd"),
+]
+
+# loads the mutated copy as oracle.surrogate before pytest imports the pins
+_SURROGATE_DRIVER = """
+import importlib.util, sys
+sys.path.insert(0, sys.argv[1])
+import oracle
+spec = importlib.util.spec_from_file_location("oracle.surrogate", sys.argv[2])
+mod = importlib.util.module_from_spec(spec)
+sys.modules["oracle.surrogate"] = mod
+spec.loader.exec_module(mod)
+oracle.surrogate = mod
+import pytest
+sys.exit(pytest.main(sys.argv[3:]))
+"""
+
+
+def _run_surrogate_mutant(tmpdir: str, name: str, old: str, new: str, select: str):
+    src = open(SURROGATE_PY).read()
+    assert src.count(old) == 1, f"{name}: the text to mutate must occur exactly once in surrogate.py"
+    path = os.path.join(tmpdir, f"surrogate_{name}.py")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    r = subprocess.run([sys.executable, "-c", _SURROGATE_DRIVER, ROOT, path,
+                        os.path.join(ROOT, "tests", "test_surrogate_oracle.py"), "-x", "-q", "-m", "not gpu",
+                        "-k", select, "-p", "no:cacheprovider"],
+                       cwd=ROOT, env=dict(os.environ, PYTHONDONTWRITEBYTECODE="1"),
+                       capture_output=True, text=True, timeout=600)
+    return name, r.returncode, r.stdout[-600:]
+
+
+def test_every_planted_mistake_in_the_network_reference_fails_a_pin(tmp_path):
+    workers = min(6, os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda m: _run_surrogate_mutant(str(tmp_path), *m), SURROGATE_MUTANTS))
+    survivors = [(name, out) for name, rc, out in results if rc != 1]
+    assert not survivors, "planted mistakes not caught by the pins:\n" + "\n".join(
+        f"{n}:\n{o}" for n, o in survivors)
+
+
+@pytest.mark.parametrize("name,old,new,select", SURROGATE_MUTANTS, ids=[m[0] for m in SURROGATE_MUTANTS])
+def test_network_mutation_text_is_unique(name, old, new, select):
+    assert open(SURROGATE_PY).read().count(old) == 1

@@ -188,3 +188,24 @@ def test_nearest_neighbour_brute_force():
         dd = [float(((q[i] - t[j]) ** 2).sum()) for j in range(len(t))]
         assert idx[i] == int(np.argmin(dd)) and abs(d2[i] - min(dd)) <= 1e-12
     assert idx[10] == 3 and idx[11] == 17 and d2[10] == 0.0
+
+
+def test_nearest_takes_the_lowest_index_on_ties():
+    """Equal distances (exact in binary) resolve to the lowest reference
+    index, whichever side of the query the tied rows lie on."""
+    t = np.array([[2.0, 0.0], [1.0, 0.0], [-1.0, 0.0], [1.0, 0.0], [0.0, 1.5]])
+    q = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, 0.25]])
+    d2, idx = R.nearest(q, t)
+    assert list(idx) == [1, 1, 1] and list(d2) == [1.0, 0.0, 0.3125]
+
+
+def test_initial_weights_follow_he_normal():
+    """He et al. (2015): zero-mean normal weights of variance 2 / fan-in
+    (fan-in = taps x input channels), zero biases."""
+    P = R.init_params(np.random.default_rng(11))
+    for name, ci, co, taps in R.layer_specs():
+        w, b = P[name]
+        assert w.shape == (co, taps, ci) and not b.any()
+        if w.size >= 100_000:
+            std = math.sqrt(2.0 / (ci * taps))
+            assert abs(w.std() / std - 1.0) < 0.01 and abs(w.mean()) < 0.01 * std
