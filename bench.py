@@ -7,9 +7,10 @@ depth map and the 480 x 640 Phong image. The metric is particle-substeps/s
 over the timed frames. Inputs are synthetic and resident on the GPU before
 the timed region starts.
 
-Prints ONE JSON line. With --gpus above 1 it exits: this build runs on one
-GPU (the contacts and the block are independent per GPU; see the sharding
-notes of the design document).
+Prints ONE JSON line. With --gpus above 1 it exits: the library runs on one
+GPU (independent contacts would shard one process per GPU; one large block
+would split into slabs of grid blocks that exchange their tile halos each
+substep).
 """
 from __future__ import annotations
 
