@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E nameplate, GB/s
 
-# Algorithmic bytes (FP32) per unit (the kernel table of the design notes):
+# Algorithmic bytes (FP32) per unit: what each kernel must read and write once
 #   P2G: bin entry 4 + u 12 + v 12 + A 36 read per particle; one (B+3)^3 tile of
 #        mass + momentum (16 B per node) stored per grid block holding particles
 #   G2P: bin entry 4 + u 12 + H 36 read, u 12 + v 12 + H 36 + A 36 + next bin entry 4
