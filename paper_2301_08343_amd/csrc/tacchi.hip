@@ -133,6 +133,7 @@ tacchi_status derive(const tacchi_config *c, Derived *d)
     for (int a = 0; a < 3; ++a) {
         if (c->block.n[a] < 2) return fail(TACCHI_E_ARG, "lattice needs >= 2 particles per axis");
         if (c->grid.n[a] < 7) return fail(TACCHI_E_ARG, "grid needs >= 7 nodes per axis");
+        if (c->grid.n[a] > (1 << 16)) return fail(TACCHI_E_ARG, "grid needs <= 65536 nodes per axis");
         if (!(c->block.size[a] > 0)) return fail(TACCHI_E_ARG, "block size must be > 0");
         N *= c->block.n[a];
         nodes *= c->grid.n[a];
@@ -158,12 +159,16 @@ tacchi_status derive(const tacchi_config *c, Derived *d)
     d->N = N;
     d->dx = dx;
     d->B = c->tile == 0 ? 8 : c->tile;
-    d->nblk = 1;
+    int64_t nblk = 1;
     for (int a = 0; a < 3; ++a) {
         d->nb[a] = (d->g[a] + d->B - 1) / d->B;
-        d->nblk *= d->nb[a];
+        nblk *= d->nb[a];
     }
-    d->nodes = (int64_t)d->nblk * d->B * d->B * d->B;
+    // node indices (and four values per node) stay within 32-bit arithmetic
+    if (nblk * d->B * d->B * d->B >= (int64_t)1 << 29)
+        return fail(TACCHI_E_ARG, "too many grid nodes (limit 2^29 after rounding up to whole blocks)");
+    d->nblk = (int)nblk;
+    d->nodes = nblk * d->B * d->B * d->B;
     d->V0 = d->h[0] * d->h[1] * d->h[2];
     d->m = c->mat.rho * d->V0;
     d->mu = c->mat.E / (2 * (1 + c->mat.nu));

@@ -59,6 +59,8 @@ def test_workspace_sizes():
     (lambda c: c.update(dx=0.4e-3, gn=(80, 80, 20)), "lattice spacing"),
     (lambda c: c.update(shape=9), "shape"),
     (lambda c: c.update(sp=(0.0,) * 8), "radius"),
+    (lambda c: c.update(gn=(64, 64, 70000)), "65536"),
+    (lambda c: c.update(gn=(1024, 1024, 1024)), "too many grid nodes"),
 ])
 def test_config_validation(mutate, msg):
     wl = W.small_sphere_contact()
