@@ -66,7 +66,10 @@ enum { TACCHI_NO_INDENTER = -1, TACCHI_SPHERE = 0, TACCHI_CYLINDER = 1, TACCHI_C
 /* Elastomer block sampled by a cell-centred particle lattice: particle
  * (i, j, k) rests at origin + ((i, j, k) + 1/2) * size / n. */
 typedef struct { double origin[3], size[3]; int32_t n[3]; } tacchi_block;
-/* Background grid: node (a, b, c) at origin + (a, b, c) * dx, n nodes per axis. */
+/* Background grid: node (a, b, c) at origin + (a, b, c) * dx, n nodes per axis
+ * (7 to 65536 per axis, at most 2^29 nodes once rounded up to whole blocks;
+ * dx >= the lattice spacing; at least 3 nodes of margin around the block,
+ * whose bottom face lies on a node plane). */
 typedef struct { double origin[3]; double dx; int32_t n[3]; } tacchi_grid;
 /* Hyperelastic material: E [Pa], nu, rho [kg/m^3], model TACCHI_NEOHOOKEAN or
  * TACCHI_COROTATED. */
