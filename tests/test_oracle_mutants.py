@@ -20,6 +20,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE_C = os.path.join(ROOT, "oracle", "oracle.c")
 SURROGATE_PY = os.path.join(ROOT, "oracle", "surrogate.py")
+ORACLE_PY = os.path.join(ROOT, "oracle", "__init__.py")
 
 # (name, text in oracle.c, replacement, pins expected to catch it (pytest -k))
 MUTANTS = [
@@ -190,3 +191,62 @@ def test_every_planted_mistake_in_the_network_reference_fails_a_pin(tmp_path):
 @pytest.mark.parametrize("name,old,new,select", SURROGATE_MUTANTS, ids=[m[0] for m in SURROGATE_MUTANTS])
 def test_network_mutation_text_is_unique(name, old, new, select):
     assert open(SURROGATE_PY).read().count(old) == 1
+
+
+# the oracle's Python side (depth-map resampling, markers, gap field):
+# (name, text in oracle/__init__.py, replacement, pins (pytest -k))
+PACKAGE_MUTANTS = [
+    ("marker_rim_offset", "si = min(max((px - o[0]) / h[0] - 0.5, 0.0), n0 - 1.0)",
+     "si = min(max((px - o[0]) / h[0], 0.0), n0 - 1.0)", "markers_reproduce"),
+    ("marker_bilinear_corner", "out.append((1 - tx) * (1 - ty) * u[j0, i0] + tx * (1 - ty) * u[j0, i0 + 1]",
+     "out.append((1 - tx) * (1 - ty) * u[j0, i0] + tx * (1 - ty) * u[j0 + 1, i0]", "markers_reproduce"),
+    ("displacement_mean_divisor", "out[r, c] /= sub * sub", "out[r, c] /= sub", "surface_displacement"),
+    ("displacement_subpoint_offset", "si = min(max((c + (qx + 0.5) / sub) * n0 / res - 0.5, 0.0), n0 - 1.0)",
+     "si = min(max((c + qx / sub) * n0 / res - 0.5, 0.0), n0 - 1.0)", "surface_displacement"),
+    ("gap_subpoints_ignored", "x = ox + (c + (qx + 0.5) / sub) * wx / res",
+     "x = ox + (c + 0.5) * wx / res", "upright_sphere"),
+    ("gap_upper_clamp_dropped", "acc += min(max(z - ztop, lo), hi)", "acc += max(z - ztop, lo)",
+     "upright_sphere"),
+]
+
+# loads the mutated copy as the oracle package (its C library as built)
+_PACKAGE_DRIVER = """
+import importlib.util, os, sys
+sys.path.insert(0, sys.argv[1])
+spec = importlib.util.spec_from_file_location("oracle", sys.argv[2],
+                                              submodule_search_locations=[os.path.join(sys.argv[1], "oracle")])
+mod = importlib.util.module_from_spec(spec)
+sys.modules["oracle"] = mod
+spec.loader.exec_module(mod)
+import pytest
+sys.exit(pytest.main(sys.argv[3:]))
+"""
+
+
+def _run_package_mutant(tmpdir: str, name: str, old: str, new: str, select: str):
+    src = open(ORACLE_PY).read()
+    assert src.count(old) == 1, f"{name}: the text to mutate must occur exactly once in oracle/__init__.py"
+    path = os.path.join(tmpdir, f"oracle_{name}.py")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    import oracle
+    lib = oracle.build(force=False)
+    r = subprocess.run([sys.executable, "-c", _PACKAGE_DRIVER, ROOT, path,
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-x", "-q", "-m", "not gpu",
+                        "-k", select, "-p", "no:cacheprovider"],
+                       cwd=ROOT, env=dict(os.environ, PYTHONDONTWRITEBYTECODE="1", TACCHI_ORACLE_LIB=lib),
+                       capture_output=True, text=True, timeout=600)
+    return name, r.returncode, r.stdout[-600:]
+
+
+def test_every_planted_mistake_in_the_oracle_package_fails_a_pin(tmp_path):
+    with cf.ThreadPoolExecutor(min(6, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(lambda m: _run_package_mutant(str(tmp_path), *m), PACKAGE_MUTANTS))
+    survivors = [(name, out) for name, rc, out in results if rc != 1]
+    assert not survivors, "planted mistakes not caught by the pins:\n" + "\n".join(
+        f"{n}:\n{o}" for n, o in survivors)
+
+
+@pytest.mark.parametrize("name,old,new,select", PACKAGE_MUTANTS, ids=[m[0] for m in PACKAGE_MUTANTS])
+def test_package_mutation_text_is_unique(name, old, new, select):
+    assert open(ORACLE_PY).read().count(old) == 1
