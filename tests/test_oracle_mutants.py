@@ -81,6 +81,21 @@ MUTANTS = [
      "render_plane"),
     ("render_central_difference_step",
      "/ (2.0 * r);\n            double gy", "/ r;\n            double gy", "render_plane"),
+    ("contact_normal_sign",
+     "g[k] = (phi_world(s, s->pose, a) - phi_world(s, s->pose, b)) / (2.0 * eps);",
+     "g[k] = (phi_world(s, s->pose, b) - phi_world(s, s->pose, a)) / (2.0 * eps);", "does_not_pull"),
+    ("coulomb_never_separates", "if (un >= 0.0) {", "if (un >= 1e300) {", "does_not_pull"),
+    ("indenter_scatter_weight",
+     "+= w[0][a] * w[1][b] * w[2][c] * s->imass;", "+= w[0][a] * w[1][b] * s->imass;", "placed_by_the_pose"),
+    ("indenter_points_rotation_transposed",
+     "X[r] = s->pose[r] + R[r * 3 + 0] * l[0] + R[r * 3 + 1] * l[1] + R[r * 3 + 2] * l[2];",
+     "X[r] = s->pose[r] + R[0 * 3 + r] * l[0] + R[1 * 3 + r] * l[1] + R[2 * 3 + r] * l[2];", "placed_by_the_pose"),
+    ("contact_at_end_pose",
+     "} else if (s->cfg.shape >= 0 && phi_world(s, s->pose, X) <= 0.0) {",
+     "} else if (s->cfg.shape >= 0 && phi_world(s, pose_end, X) <= 0.0) {", "start_pose"),
+    ("empty_node_keeps_velocity",
+     "                    V[0] = V[1] = V[2] = 0.0;\n                    continue;",
+     "                    continue;", "empty_nodes"),
 ]
 
 

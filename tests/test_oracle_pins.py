@@ -250,6 +250,77 @@ def test_heightmap_rows_follow_the_lattice_y_axis(oracle_lib):
     np.testing.assert_allclose(np.diff(H, axis=0), ay * h, rtol=1e-9)
 
 
+def test_empty_nodes_have_zero_velocity(oracle_lib):
+    """Eq. 6 applies only where a node has mass; a node that had mass in one
+    grid update and has none in the next carries no stale velocity."""
+    cfg = small_cfg(n=(6, 5, 4), pad=5, E=0.0)
+    sim = oracle_lib.OracleSim(cfg, FAR_POSE)
+    x, _, C, F = sim.particles()
+    sim.set_particles(x, np.broadcast_to([0.2, -0.1, 0.3], x.shape).copy(), C, F)
+    dt = 1e-6
+    assert sim.p2g(dt) == 0 and sim.grid_update(FAR_POSE, dt) == 0
+    M0, _, V0 = sim.grid()
+    assert np.abs(V0[M0 > 0]).min() > 0
+    sim.set_particles(x + np.array([2e-3, 0.0, 0.0]), np.broadcast_to([0.2, -0.1, 0.3], x.shape).copy(), C, F)
+    assert sim.p2g(dt) == 0 and sim.grid_update(FAR_POSE, dt) == 0
+    M1, _, V1 = sim.grid()
+    vacated = (M0 > 0) & (M1 == 0)
+    assert vacated.sum() > 10
+    assert np.abs(V1[M1 == 0]).max() == 0.0
+
+
+def test_contact_is_decided_at_the_substep_start_pose(oracle_lib):
+    """R7: a node takes the indenter's velocity when it lies inside the solid
+    at the pose of the substep's start; with a pose step large enough to move
+    the surface past whole nodes, nodes inside only at the end keep the
+    gel's velocity."""
+    R = 3e-3
+    cfg = small_cfg(n=(10, 10, 4), pad=6, E=0.0, shape=W.SPHERE, sp=(R,))
+    top = W.top_z(cfg)
+    cx = cfg["block_origin"][0] + 0.5 * cfg["block_size"][0]
+    cy = cfg["block_origin"][1] + 0.5 * cfg["block_size"][1]
+    p0 = np.array([cx, cy, top - 1.5e-3, 1, 0, 0, 0])
+    p1 = p0 - np.array([0, 0, 1.0e-3, 0, 0, 0, 0])
+    sim = oracle_lib.OracleSim(cfg, p0)
+    x, _, C, F = sim.particles()
+    u = np.array([0.0, 0.0, 0.05])
+    sim.set_particles(x, np.broadcast_to(u, x.shape).copy(), C, F)
+    dt = 1e-3
+    assert sim.p2g(dt) == 0 and sim.grid_update(p1, dt) == 0
+    M, _, V = sim.grid()
+    X, _ = node_positions(cfg)
+    c0, c1 = p0[:3] + [0, 0, R], p1[:3] + [0, 0, R]
+    in0 = (np.linalg.norm(X - c0, axis=1) <= R) & (M > 0)
+    only1 = (np.linalg.norm(X - c1, axis=1) < R - 1e-9) & ~(np.linalg.norm(X - c0, axis=1) <= R) & (M > 0)
+    assert in0.sum() > 5 and only1.sum() > 5
+    vind = (p1[:3] - p0[:3]) / dt
+    np.testing.assert_allclose(V[in0], np.broadcast_to(vind, V[in0].shape), atol=1e-12)
+    np.testing.assert_allclose(V[only1], np.broadcast_to(u, V[only1].shape), atol=1e-12)
+
+
+def test_indenter_points_are_placed_by_the_pose(oracle_lib):
+    """A rotated point cloud scatters its mass around the posed points: the
+    quadratic B-spline weights have zero first moment, so the scattered mass's
+    centroid is the mass-weighted mean of the world points pos + Rot p
+    (scipy's rotation) and its total is the points' mass."""
+    from scipy.spatial.transform import Rotation
+    cfg = small_cfg(n=(10, 10, 4), pad=6, E=0.0)
+    rot = Rotation.from_rotvec(np.array([0.4, -0.7, 0.5]) * 0.9)
+    q = rot.as_quat()
+    top = W.top_z(cfg)
+    pose = np.array([cfg["block_origin"][0] + 5e-3, cfg["block_origin"][1] + 5e-3, top + 1e-3,
+                     q[3], q[0], q[1], q[2]])
+    pts = np.array([[1.2e-3, -0.4e-3, 0.7e-3], [-0.9e-3, 0.8e-3, 1.5e-3], [0.3e-3, 1.1e-3, -0.6e-3]])
+    sim = oracle_lib.OracleSim(cfg, pose)
+    sim.set_indenter_points(pts, 2e-9)
+    assert sim.p2g(1e-6) == 0 and sim.grid_update(pose, 1e-6) == 0
+    MI = sim.indenter_mass()
+    X, _ = node_positions(cfg)
+    world = pose[:3] + rot.apply(pts)
+    assert abs(MI.sum() - 3 * 2e-9) <= 1e-12 * 6e-9
+    np.testing.assert_allclose((MI[:, None] * X).sum(axis=0) / MI.sum(), world.mean(axis=0), rtol=0, atol=1e-15)
+
+
 # ------------------------------------------------------------------ P8 exact rational step
 
 def _bspline_q(r):
