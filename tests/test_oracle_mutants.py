@@ -222,6 +222,8 @@ PACKAGE_MUTANTS = [
      "x = ox + (c + 0.5) * wx / res", "upright_sphere"),
     ("gap_upper_clamp_dropped", "acc += min(max(z - ztop, lo), hi)", "acc += max(z - ztop, lo)",
      "upright_sphere"),
+    ("force_limit_strict", "if self.force()[2] >= fz_limit:", "if self.force()[2] > fz_limit:",
+     "run_until_force"),
 ]
 
 # loads the mutated copy as the oracle package (its C library as built)

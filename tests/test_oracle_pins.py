@@ -904,6 +904,8 @@ def test_run_until_force_stops_at_the_first_crossing(oracle_lib):
     sim = oracle_lib.OracleSim(cfg, poses[0])
     assert sim.run_until_force(poses, dt, limit, 0, n) == i + 1
     assert np.array_equal(sim.particles()[0], states[i])
+    # reaching the limit exactly counts as reaching it
+    assert oracle_lib.OracleSim(cfg, poses[0]).run_until_force(poses, dt, f[i], 0, n) == i + 1
     assert oracle_lib.OracleSim(cfg, poses[0]).run_until_force(poses, dt, math.inf, 0, n) == n
     assert oracle_lib.OracleSim(cfg, poses[0]).run_until_force(poses, dt, -math.inf, 0, n) == 1
 
