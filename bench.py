@@ -27,14 +27,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E nameplate, GB/s
 
-# Algorithmic bytes (FP32) per unit: what each kernel must read and write once
-#   P2G: bin entry 4 + u 12 + v 12 + A 36 read per particle; one (B+3)^3 tile of
-#        mass + momentum (16 B per node) stored per grid block holding particles
-#   G2P: bin entry 4 + u 12 + H 36 read, u 12 + v 12 + H 36 + A 36 + next bin entry 4
-#        written per particle; one (B+3)^3 tile of velocities (12 B per node) read per
-#        grid block holding particles
-BYTES_PER_PARTICLE = {"p2g": 64, "g2p": 152}
-BYTES_PER_TILE_NODE = {"p2g": 16, "g2p": 12}
+# Algorithmic bytes (FP32) of one substep, per particle and per active grid
+# node (a node inside some particle's 3x3x3 stencil): what each kernel must
+# read and write once, whatever its tiling
+#   P2G:  bin entry 4 + u 12 + v 12 + A 36 read per particle; mass + momentum
+#         16 written per active node
+#   grid: mass + momentum 16 read, velocity 12 written and the next
+#         accumulation buffer 16 cleared per active node
+#   G2P:  bin entry 4 + u 12 + H 36 read, u 12 + v 12 + H 36 + A 36 written per
+#         particle; velocity 12 read per active node
+BYTES_PER_PARTICLE = {"p2g": 64, "grid": 0, "g2p": 148}
+BYTES_PER_ACTIVE_NODE = {"p2g": 16, "grid": 44, "g2p": 12}
+TIMED_KERNELS = ("p2g", "grid", "g2p")
+
+
+def design_bytes(kernel, particles, active_blocks, B):
+    """What this design moves besides the algorithmic bytes: P2G stores each
+    live block's whole (B+3)^3 tile of mass and momentum (16 B per node) and
+    the grid update gathers them back; G2P also writes the next substep's bin
+    entry (4 B) and stages a (B+3)^3 tile of 16-byte velocities per live
+    block. Reported beside the algorithmic figure, never as the roofline."""
+    tile = (B + 3) ** 3 * active_blocks
+    if kernel == "p2g":
+        return 64 * particles + 16 * tile
+    if kernel == "grid":
+        return 16 * tile + 16 * B ** 3 * active_blocks
+    return 152 * particles + 16 * tile
 
 # Counter-measured HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE,
 # scaled by what they read for a plain device copy) live in the committed
@@ -88,8 +106,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=0,
                     help="only time N surrogate training steps and N forward passes (batch 256, random data)")
-    ap.add_argument("--queries", type=int, default=5000)
+    ap.add_argument("--queries", type=int, default=10000)
     ap.add_argument("--plain-sample", type=int, default=512)
+    ap.add_argument("--no-families", action="store_true")
+    ap.add_argument("--cpu-worker", type=int, default=-1, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -114,7 +134,9 @@ def surrogate_leg(args):
     torch.cuda.synchronize()
     inf_s = (time.perf_counter() - t0) / reps
     ftr = SP.train_features(meta["train_samples"], meta["h_m"])
-    rep = SP.serve_benchmark(net, ftr, meta["threshold"], meta["h_m"], args.queries, args.plain_sample, log=log)
+    prior = meta.get("heldout", {}).get("height_rmse_um_by_group")
+    rep = SP.serve_benchmark(net, ftr, meta["threshold"], meta["h_m"], args.queries, args.plain_sample,
+                             prior_rmse_um=prior, log=log)
     r, p = rep["router"], rep["plain_mpm"]
     return {"metric": "tactile frames/s, surrogate + MPM fallback vs plain batched MPM",
             "frames_per_s": r["frames_per_s"], "plain_mpm_frames_per_s": p["frames_per_s"],
@@ -127,10 +149,15 @@ def surrogate_leg(args):
             "queries": r["queries"], "mpm_fallbacks": r["mpm_fallbacks"], "ood": r["ood"],
             "audited": r["audited"], "breaker_tripped_families": r["breaker_tripped"],
             "served_by_surrogate": r["served_by_surrogate"],
-            "audited_height_rmse_um_served_families": r["audited_height_rmse_um_open_classes"],
+            "served_sample": rep["served_sample"],
+            "served_within_limit": rep["served_vs_mpm_height_rmse_um"] <= 5.0,
+            "breaker_tripped_at_start": r["breaker_tripped_at_start"],
+            "breaker_rerouted_in_batch": r["breaker_rerouted_in_batch"],
+            "per_family": r["per_class"],
             "inference_frames_per_s": 512 / inf_s,
             "inference_tflops": 512 * forward_flops(meta["res"]) / inf_s / 1e12,
             "plain_mpm_sample": p["queries"], "data_h_m": meta["h_m"], "train_samples": meta["train_samples"],
+            "heldout_height_rmse_um_by_family": prior,
             "dtype": "bf16 storage, fp32 accumulation"}
 
 
@@ -235,9 +262,63 @@ def batch_leg(n=256, substeps=2000):
             "polar_fp64_fallbacks": fallbacks, "tuner_choices": dict(choices)}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_worker(seed, budget_s):
+    """One oracle process on one uneven-batch contact (corotated, tilted
+    indenter) for about budget_s seconds; prints its rate as JSON."""
+    import oracle
+    from paper_2301_08343_amd import workloads as W
+    wl = W.batch_contact(seed, steps=2000)
+    sim = oracle.OracleSim(wl["cfg"], wl["poses"][0])
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < budget_s and k + 1 < len(wl["poses"]):
+        st = sim.step(wl["poses"][k + 1], wl["dt"])
+        if st != 0:
+            raise RuntimeError(f"oracle failed with status {st}")
+        k += 1
+    el = time.perf_counter() - t0
+    print(json.dumps({"seed": seed, "particles": int(sim.N), "substeps": k, "seconds": el}), flush=True)
+
+
+def cpu_all_cores(budget_s):
+    """The oracle on every host core at once: one process per core, each on
+    its own contact of the uneven batch (independent contacts, the way the
+    CPU would serve a batch); the aggregate of their rates."""
+    import subprocess
+    nproc = os.cpu_count() or 1
+    procs = min(16, nproc)  # the host share one GPU's job may use
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    runs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(seed),
+                              "--cpu-seconds", str(budget_s)], stdout=subprocess.PIPE, text=True, env=env)
+            for seed in range(procs)]
+    rates, parts = [], []
+    for r in runs:
+        out, _ = r.communicate()
+        if r.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with status {r.returncode}")
+        d = json.loads(out.strip().splitlines()[-1])
+        rates.append(d["particles"] * d["substeps"] / d["seconds"])
+        parts.append(d["particles"])
+    return {"value": sum(rates), "unit": "particle-substeps/s", "processes": procs, "nproc": nproc,
+            "sample": f"{procs} uneven-batch contacts (seeds 0-{procs - 1}, {min(parts)}-{max(parts)} particles, "
+                      f"corotated), one oracle process each, ~{budget_s:.0f} s"}
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle (single thread) on the same workload for as many
-    substeps as fit in about `budget_s` seconds."""
+    substeps as fit in about `budget_s` seconds; then the same oracle on all
+    host cores at once (independent contacts)."""
     import oracle
     oracle.build(force=False)
     sim = oracle.OracleSim(wl["cfg"], wl["poses"][0])
@@ -252,6 +333,7 @@ def cpu_baseline(wl, budget_s):
         if time.perf_counter() - t0 > budget_s or k + 1 >= len(wl["poses"]):
             break
     el = time.perf_counter() - t0
+    del sim
     # and the 18,432-particle sphere press (the FP64 parity workload), 200 substeps
     from paper_2301_08343_amd import workloads as W
     sw = W.small_sphere_contact(seed=0, steps=1000)
@@ -261,7 +343,49 @@ def cpu_baseline(wl, budget_s):
     el_small = time.perf_counter() - t1
     return {"value": n * k / el, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
             "sample": f"first {k} substeps of the same {n}-particle press, FP64, one thread",
-            "sphere_18k_fp64_value": int(small.N) * 200 / el_small}
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "sphere_18k_fp64_value": int(small.N) * 200 / el_small,
+            "all_cores": cpu_all_cores(budget_s)}
+
+
+def family_presses(tile, substeps=50, frames=40):
+    """The whole 2000-substep GelSight press of each other indenter family
+    (seeds 1-4: flat punch, cone, edge, textured plate), frames of 50
+    substeps with the depth map and the image, one timed run each."""
+    import torch
+    from paper_2301_08343_amd import workloads as W
+    from paper_2301_08343_amd.sim import Sim
+    out = {}
+    for seed in (1, 2, 3, 4):
+        wl = W.gelsight_contact(seed=seed, steps=substeps * frames)
+        sim = Sim(wl["cfg"], wl["poses"][0], precision="f32", tile=tile)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(frames):
+            sim.run(wl["poses"][f * substeps + 1:(f + 1) * substeps + 1], wl["dt"])
+            sim.heightmap()
+            sim.render(wl["render"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[W.SHAPE_NAMES[wl["cfg"]["shape"]]] = {
+            "particle_substeps_per_s": sim.N * substeps * frames / el, "ms_per_step": el * 1e3 / frames,
+            "depth_m": wl["depth"], "polar_fp64_fallbacks": sim.polar_fallbacks()}
+        sim.close()
+    return out
+
+
+def active_nodes(x, cfg):
+    """Grid nodes inside some particle's 3 x 3 x 3 stencil (x: [N][3] m)."""
+    import numpy as np
+    g0, g1, g2 = cfg["gn"]
+    base = np.floor((x - np.array(cfg["grid_origin"])) / cfg["dx"] - 0.5).astype(np.int64)
+    mark = np.zeros(g0 * g1 * g2, dtype=bool)
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                mark[((base[:, 2] + c) * g1 + base[:, 1] + b) * g0 + base[:, 0] + a] = True
+    return int(mark.sum())
 
 
 def surrogate_steps(n):
@@ -319,6 +443,9 @@ def surrogate_steps(n):
 
 def main():
     args = parse()
+    if args.cpu_worker >= 0:
+        cpu_worker(args.cpu_worker, args.cpu_seconds)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is not built", file=sys.stderr)
@@ -360,7 +487,7 @@ def main():
     sim = Sim(cfg, poses[0], precision="f32", tile=args.tile)
     N = sim.N
     sim.sync()
-    sim.timing_enable(("p2g", "g2p"))
+    sim.timing_enable(TIMED_KERNELS)
     sim.timing_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -371,22 +498,24 @@ def main():
     timing = sim.timing_read(reset=True)
     sim.timing_enable(())
     sim.sync()
-    # grid blocks holding particles in the final state (outside the timed region)
+    # active grid nodes and blocks of the final state (outside the timed region)
     x, _, _, _ = sim.read_particles()
-    xi = (x.double().cpu().numpy().T - np.array(cfg["grid_origin"])) / cfg["dx"]
-    base = np.floor(xi).astype(np.int64) // args.tile
-    active = len(np.unique(base[:, 0] + 4096 * (base[:, 1] + 4096 * base[:, 2])))
-    tile_nodes = (args.tile + 3) ** 3
+    xs = x.double().cpu().numpy().T
+    nodes = active_nodes(xs, cfg)
+    cell = np.floor((xs - np.array(cfg["grid_origin"])) / cfg["dx"]).astype(np.int64) // args.tile
+    active = len(np.unique(cell[:, 0] + 4096 * (cell[:, 1] + 4096 * cell[:, 2])))
     assert bool(torch.isfinite(img).all())
 
     value = N * S * args.steps / el
-    k_ms = {k: timing[k][0] / max(1, timing[k][1]) for k in ("p2g", "g2p")}
+    k_ms = {k: timing[k][0] / max(1, timing[k][1]) for k in TIMED_KERNELS}
     dom = max(k_ms, key=lambda k: timing[k][0])
     per_kernel = {}
-    for k in ("p2g", "g2p"):
-        b = BYTES_PER_PARTICLE[k] * N + BYTES_PER_TILE_NODE[k] * tile_nodes * active
+    for k in TIMED_KERNELS:
+        b = BYTES_PER_PARTICLE[k] * N + BYTES_PER_ACTIVE_NODE[k] * nodes
         per_kernel[k] = {"algorithmic_bytes_per_launch": b, "avg_launch_ms": k_ms[k],
-                         "achieved": b / (k_ms[k] * 1e-3) / 1e9}
+                         "achieved": b / (k_ms[k] * 1e-3) / 1e9, "launches": timing[k][1],
+                         "traffic": committed_traffic(k),
+                         "design_bytes_per_launch": design_bytes(k, N, active, args.tile)}
     algo_bytes = per_kernel[dom]["algorithmic_bytes_per_launch"]
     achieved = per_kernel[dom]["achieved"]
     # a plain device copy of 1 GiB (read + write) as the measured bandwidth
@@ -430,7 +559,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(dom),
                      "avg_launch_ms": k_ms[dom], "algorithmic_bytes_per_launch": algo_bytes,
-                     "active_blocks": active, "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
+                     "bytes_per_particle": BYTES_PER_PARTICLE, "bytes_per_active_node": BYTES_PER_ACTIVE_NODE,
+                     "particles": N, "active_nodes": nodes, "active_blocks": active,
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
+                     "substep_GBps": sum(per_kernel[k]["algorithmic_bytes_per_launch"] for k in TIMED_KERNELS)
+                     * value / N / 1e9,
                      "kernels": per_kernel},
         "kernel_ms": {k: v[0] / max(1, v[1]) for k, v in timing.items() if v[1]},
     }
@@ -441,6 +574,7 @@ def main():
         out["cpu_baseline"] = None
     del sim
     torch.cuda.empty_cache()
+    out["families"] = None if args.no_families else family_presses(args.tile, S)
     out["streaming"] = None if args.no_streaming else streaming_leg()
     out["batch"] = None if args.no_batch else batch_leg()
     if not args.no_surrogate and os.path.exists(args.surrogate):

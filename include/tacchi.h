@@ -160,10 +160,17 @@ tacchi_status tacchi_set_contact(tacchi_sim *sim, int32_t model, double mu);
  * for it), and a grid node carrying indenter mass M_I takes the velocity
  * (M V + M_I v_indenter)/(M + M_I) in place of the shape's contact; the
  * contact force is still the gel's momentum change. n = 0 returns to the
- * shape's contact (tacchi_set_contact). The handle allocates its own device
- * buffers for the points and an FP64 mass per grid node (freed by
- * tacchi_destroy). Must be called between substeps. Synchronises. */
-tacchi_status tacchi_set_indenter_points(tacchi_sim *sim, const double *xyz, int32_t n, double mass);
+ * shape's contact (tacchi_set_contact); dev_ws may then be NULL.
+ * The points and an FP64 indenter mass per grid node live in dev_ws, device
+ * memory owned by the caller: 256-byte aligned, at least
+ * tacchi_points_workspace_bytes(sim, n) bytes, kept alive (and not used
+ * otherwise) until the next tacchi_set_indenter_points or tacchi_destroy.
+ * Errors: E_ARG (NULL, n outside [0, 2^24], bad mass or coordinate),
+ * E_WORKSPACE (workspace missing, misaligned or too small), E_STATE (inside a
+ * substep). Must be called between substeps. Synchronises. */
+size_t tacchi_points_workspace_bytes(const tacchi_sim *sim, int32_t n);
+tacchi_status tacchi_set_indenter_points(tacchi_sim *sim, const double *xyz, int32_t n, double mass,
+                                         void *dev_ws, size_t ws_bytes);
 
 /* The scripted press with a terminal condition on the contact force
  * (Sec. III-C: the simulation ends when a terminal condition is met): runs
@@ -222,7 +229,9 @@ tacchi_status tacchi_render(tacchi_sim *sim, const tacchi_render_params *rp, flo
  * bilinearly between the top-layer particles' displacements (particle i at
  * (i + 1/2) h; clamped at the border). 1 <= res <= 4096, 1 <= sub <= 16.
  * With out_on_device != 0 the call is asynchronous on the simulation's
- * stream; otherwise it synchronises and reports the device error word. */
+ * stream; otherwise the kernel writes into the handle's pinned host staging
+ * buffer (no device memory is allocated), and the call synchronises and
+ * reports the device error word. */
 tacchi_status tacchi_surface_displacement(tacchi_sim *sim, int32_t res, int32_t sub, float *out,
                                           int32_t out_on_device);
 
@@ -234,8 +243,10 @@ tacchi_status tacchi_surface_displacement(tacchi_sim *sim, int32_t res, int32_t 
  * precision, n x 3): bilinear between the four surrounding top-layer
  * particles (particle i at (i + 1/2) h), a point on the half-cell rim outside
  * the outermost particle centres taking the edge value. 1 <= n <= 2^24.
- * With out_on_device != 0 out is device memory; the call synchronises either
- * way and reports the device error word. */
+ * With out_on_device != 0 out is device memory. The marker coordinates (and
+ * a host output) pass through the handle's pinned host staging buffer, which
+ * the kernel reads and writes directly: no device memory is allocated. The
+ * call synchronises either way and reports the device error word. */
 tacchi_status tacchi_markers(tacchi_sim *sim, const double *xy, int32_t n, void *out, int32_t out_on_device);
 
 /* Gap field of an indenter over the undeformed top face, the geometric input
@@ -249,10 +260,15 @@ tacchi_status tacchi_markers(tacchi_sim *sim, const double *xy, int32_t n, void 
  * indenter up to z_top + hi: hi). With hi = 0 this is the penetration of the
  * indenter into the undeformed face. z_ind is found by sampling the inside
  * test at 512 heights from z_top + lo to z_top + hi and bisecting the first
- * crossing 40 times. lo < hi, hi - lo <= 1 m. Synchronises. Errors: E_ARG,
- * E_DEVICE. */
+ * crossing 40 times. lo < hi, hi - lo <= 1 m. The n query descriptors are
+ * copied into dev_ws, device memory owned by the caller (256-byte aligned,
+ * at least tacchi_indenter_gap_workspace_bytes(n) bytes). Runs on
+ * hip_stream and synchronises it. Errors: E_ARG, E_WORKSPACE (workspace
+ * missing, misaligned or too small), E_DEVICE. */
+size_t tacchi_indenter_gap_workspace_bytes(int32_t n);
 tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n,
-                                  int32_t res, int32_t sub, double lo, double hi, float *out, void *hip_stream);
+                                  int32_t res, int32_t sub, double lo, double hi, float *out,
+                                  void *dev_ws, size_t ws_bytes, void *hip_stream);
 
 /* Particle state in SoA layout (see the conventions); any pointer may be
  * NULL to skip that array. Synchronises. */

@@ -757,28 +757,26 @@ template <typename T>
 tacchi_status markers_t(tacchi_sim *s, const std::vector<double> &q, int n, void *out, int on_device)
 {
     SimDev<T> &S = sdev<T>(s);
-    std::vector<T> qt(q.begin(), q.end());
-    const size_t qbytes = qt.size() * sizeof(T), obytes = (size_t)n * 3 * sizeof(T);
-    char *buf = nullptr;
+    // the marker coordinates (and a host output) live in the handle's pinned
+    // host staging buffer, which the kernel reads and writes directly: no
+    // device memory is allocated
+    const size_t qbytes = q.size() * sizeof(T), obytes = (size_t)n * 3 * sizeof(T);
     const size_t off = (qbytes + 255) & ~(size_t)255;
-    TC_HIP(hipMallocAsync((void **)&buf, off + (on_device ? 0 : obytes), s->stream));
-    T *dq = (T *)buf, *dout = on_device ? (T *)out : (T *)(buf + off);
-    hipError_t e = hipMemcpyAsync(dq, qt.data(), qbytes, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) {
-        if (s->d.B == 4)
-            hipLaunchKernelGGL((k_markers<T, 4>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, dq, n, T(s->d.dx),
-                               dout);
-        else
-            hipLaunchKernelGGL((k_markers<T, 8>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, dq, n, T(s->d.dx),
-                               dout);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, dout, obytes, hipMemcpyDeviceToHost, s->stream);
-    const hipError_t ef = hipFreeAsync(buf, s->stream);
+    void *stage = nullptr;
+    TC_HIP(hipStreamSynchronize(s->stream));  // the staging buffer may still feed an earlier call
+    tacchi_status st = staging(s, off + (on_device ? 0 : obytes), &stage);
+    if (st) return st;
+    T *dq = (T *)stage, *dout = on_device ? (T *)out : (T *)((char *)stage + off);
+    for (size_t k = 0; k < q.size(); ++k) dq[k] = T(q[k]);
+    if (s->d.B == 4)
+        hipLaunchKernelGGL((k_markers<T, 4>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, dq, n, T(s->d.dx), dout);
+    else
+        hipLaunchKernelGGL((k_markers<T, 8>), dim3(grid1d(n)), dim3(kWG), 0, s->stream, S, dq, n, T(s->d.dx), dout);
+    hipError_t e = hipGetLastError();
     const hipError_t es = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess || ef != hipSuccess || es != hipSuccess)
-        return fail(TACCHI_E_DEVICE, std::string("tacchi_markers: ") +
-                                         hipGetErrorString(e != hipSuccess ? e : (ef != hipSuccess ? ef : es)));
+    if (e != hipSuccess || es != hipSuccess)
+        return fail(TACCHI_E_DEVICE, std::string("tacchi_markers: ") + hipGetErrorString(e != hipSuccess ? e : es));
+    if (!on_device) std::memcpy(out, dout, obytes);
     return read_error_word(s);
 }
 
@@ -1052,7 +1050,16 @@ tacchi_status tacchi_run(tacchi_sim *s, const tacchi_pose *poses, int32_t n, dou
     return TACCHI_OK;
 }
 
-tacchi_status tacchi_set_indenter_points(tacchi_sim *s, const double *xyz, int32_t n, double mass)
+
+size_t tacchi_points_workspace_bytes(const tacchi_sim *s, int32_t n)
+{
+    if (!s || n < 1) return 0;
+    const size_t nn = (size_t)s->d.g[0] * s->d.g[1] * s->d.g[2];
+    return align256(nn * sizeof(double)) + align256((size_t)n * 3 * sizeof(double));
+}
+
+tacchi_status tacchi_set_indenter_points(tacchi_sim *s, const double *xyz, int32_t n, double mass, void *dev_ws,
+                                         size_t ws_bytes)
 {
     if (!s || (n > 0 && !xyz)) return fail(TACCHI_E_ARG, "NULL argument");
     if (n < 0 || n > (1 << 24)) return fail(TACCHI_E_ARG, "point count must be in [0, 2^24]");
@@ -1062,14 +1069,17 @@ tacchi_status tacchi_set_indenter_points(tacchi_sim *s, const double *xyz, int32
         if (!std::isfinite(xyz[k])) return fail(TACCHI_E_ARG, "non-finite point coordinate");
     tacchi_status st = set_device(s);
     if (st) return st;
+    if (n > 0 && (!dev_ws || ((uintptr_t)dev_ws & 255) || ws_bytes < tacchi_points_workspace_bytes(s, n)))
+        return fail(TACCHI_E_WORKSPACE, "indenter points need a 256-byte aligned device workspace of "
+                                        "tacchi_points_workspace_bytes(sim, n) bytes");
     TC_HIP(hipStreamSynchronize(s->stream));
-    if (s->ipts) TC_HIP(hipFree(s->ipts));
     s->ipts = nullptr;
+    s->MI = nullptr;
     s->ni = 0;
     if (n == 0) return TACCHI_OK;
     const size_t nn = (size_t)s->d.g[0] * s->d.g[1] * s->d.g[2];
-    if (!s->MI) TC_HIP(hipMalloc((void **)&s->MI, nn * sizeof(double)));
-    TC_HIP(hipMalloc((void **)&s->ipts, (size_t)n * 3 * sizeof(double)));
+    s->MI = (double *)dev_ws;
+    s->ipts = (double *)((char *)dev_ws + align256(nn * sizeof(double)));
     for (int a = 0; a < 3; ++a) {
         s->plo[a] = 1e300;
         s->phi_[a] = -1e300;
@@ -1222,17 +1232,19 @@ tacchi_status tacchi_surface_displacement(tacchi_sim *s, int32_t res, int32_t su
     if (on_device)
         return s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, sub, out)
                                               : surface_disp_t<float>(s, res, sub, out);
+    // a host output is written by the kernel into the handle's pinned host
+    // staging buffer and copied out: no device memory is allocated
     const size_t bytes = (size_t)res * res * 3 * sizeof(float);
-    float *dst = nullptr;
-    TC_HIP(hipMallocAsync((void **)&dst, bytes, s->stream));
-    st = s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, sub, dst)
-                                        : surface_disp_t<float>(s, res, sub, dst);
-    hipError_t e = st ? hipSuccess : hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, s->stream);
-    const hipError_t ef = hipFreeAsync(dst, s->stream);
+    TC_HIP(hipStreamSynchronize(s->stream));  // the staging buffer may still feed an earlier call
+    void *stage = nullptr;
+    st = staging(s, bytes, &stage);
+    if (st) return st;
+    st = s->cfg.precision == TACCHI_F64 ? surface_disp_t<double>(s, res, sub, (float *)stage)
+                                        : surface_disp_t<float>(s, res, sub, (float *)stage);
     const hipError_t es = hipStreamSynchronize(s->stream);
     if (st) return st;
-    if (e != hipSuccess || ef != hipSuccess || es != hipSuccess)
-        return fail(TACCHI_E_DEVICE, "tacchi_surface_displacement: copy failed");
+    if (es != hipSuccess) return fail(TACCHI_E_DEVICE, "tacchi_surface_displacement: kernel failed");
+    std::memcpy(out, stage, bytes);
     return read_error_word(s);
 }
 
@@ -1260,12 +1272,21 @@ tacchi_status tacchi_markers(tacchi_sim *s, const double *xy, int32_t n, void *o
                                           : markers_t<float>(s, q, n, out, on_device);
 }
 
+size_t tacchi_indenter_gap_workspace_bytes(int32_t n)
+{
+    return n < 1 ? 0 : (size_t)n * sizeof(GapDev);
+}
+
 tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res,
-                                  int32_t sub, double lo, double hi, float *out, void *hip_stream)
+                                  int32_t sub, double lo, double hi, float *out, void *dev_ws, size_t ws_bytes,
+                                  void *hip_stream)
 {
     if (!cfgs || !poses || !out || n < 1 || res < 1 || res > 4096 || sub < 1 || sub > 16 || !(hi > lo) ||
         !std::isfinite(lo) || !std::isfinite(hi) || hi - lo > 1.0)
         return fail(TACCHI_E_ARG, "tacchi_indenter_gap: bad arguments");
+    if (!dev_ws || ((uintptr_t)dev_ws & 255) || ws_bytes < tacchi_indenter_gap_workspace_bytes(n))
+        return fail(TACCHI_E_WORKSPACE, "tacchi_indenter_gap: workspace missing, misaligned or smaller than "
+                                        "tacchi_indenter_gap_workspace_bytes(n)");
     std::vector<GapDev> q((size_t)n);
     for (int k = 0; k < n; ++k) {
         const tacchi_config &c = cfgs[k];
@@ -1285,19 +1306,17 @@ tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *
         q[k].ztop = c.block.origin[2] + c.block.size[2];
     }
     hipStream_t st = (hipStream_t)hip_stream;
-    GapDev *dq = nullptr;
-    TC_HIP(hipMallocAsync((void **)&dq, q.size() * sizeof(GapDev), st));
+    GapDev *dq = (GapDev *)dev_ws;
     hipError_t e = hipMemcpyAsync(dq, q.data(), q.size() * sizeof(GapDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_indenter_gap, dim3(grid1d((int64_t)n * res * res)), dim3(kWG), 0, st, dq, n, res, sub,
                            lo, hi, out);
         e = hipGetLastError();
     }
-    const hipError_t ef = hipFreeAsync(dq, st);
+    // q is pageable host memory read by the copy: wait before it goes
     const hipError_t es = hipStreamSynchronize(st);
-    if (e != hipSuccess || ef != hipSuccess || es != hipSuccess)
-        return fail(TACCHI_E_DEVICE, std::string("tacchi_indenter_gap: ") +
-                                         hipGetErrorString(e != hipSuccess ? e : (ef != hipSuccess ? ef : es)));
+    if (e != hipSuccess || es != hipSuccess)
+        return fail(TACCHI_E_DEVICE, std::string("tacchi_indenter_gap: ") + hipGetErrorString(e != hipSuccess ? e : es));
     return TACCHI_OK;
 }
 
@@ -1414,11 +1433,6 @@ void tacchi_destroy(tacchi_sim *s)
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
-    if (s->ipts || s->MI) {
-        (void)hipStreamSynchronize(s->stream);
-        if (s->ipts) (void)hipFree(s->ipts);
-        if (s->MI) (void)hipFree(s->MI);
-    }
     delete s;
 }
 

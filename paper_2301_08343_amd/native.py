@@ -29,6 +29,7 @@ EXPORTS = (
     "tacchi_batch_tuning", "tacchi_batch_substeps_done", "tacchi_batch_sync", "tacchi_batch_destroy",
     "tacchi_surface_displacement", "tacchi_indenter_gap", "tacchi_batch_surface_displacement", "tacchi_markers",
     "tacchi_run_until_force", "tacchi_set_contact", "tacchi_set_indenter_points",
+    "tacchi_points_workspace_bytes", "tacchi_indenter_gap_workspace_bytes",
 )
 NUM_KERNEL_CLASSES = 6
 KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
@@ -150,7 +151,11 @@ def lib():
         L.tacchi_surface_displacement.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32]
         L.tacchi_set_indenter_points.restype = ctypes.c_int32
         L.tacchi_set_indenter_points.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
-                                                 ctypes.c_double]
+                                                 ctypes.c_double, _vp, ctypes.c_size_t]
+        L.tacchi_points_workspace_bytes.restype = ctypes.c_size_t
+        L.tacchi_points_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
+        L.tacchi_indenter_gap_workspace_bytes.restype = ctypes.c_size_t
+        L.tacchi_indenter_gap_workspace_bytes.argtypes = [ctypes.c_int32]
         L.tacchi_set_contact.restype = ctypes.c_int32
         L.tacchi_set_contact.argtypes = [_vp, ctypes.c_int32, ctypes.c_double]
         L.tacchi_run_until_force.restype = ctypes.c_int32
@@ -160,7 +165,8 @@ def lib():
         L.tacchi_markers.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _vp, ctypes.c_int32]
         L.tacchi_indenter_gap.restype = ctypes.c_int32
         L.tacchi_indenter_gap.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(Pose), ctypes.c_int32,
-                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp, _vp]
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp,
+                                          _vp, ctypes.c_size_t, _vp]
         L.tacchi_batch_surface_displacement.restype = ctypes.c_int32
         L.tacchi_batch_surface_displacement.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32]
         L.tacchi_last_error.restype = ctypes.c_char_p

@@ -11,7 +11,13 @@ Each query is a contact (indenter, pose, depth). Per batch of queries:
   3. a seeded 2% audit sends further queries to the MPM, where the surrogate's
      height error is measured against the MPM's answer;
   4. a circuit breaker routes every later query to the MPM once the RMSE of
-     the most recent audits exceeds the limit (5 um by default);
+     the most recent audits exceeds the limit (5 um by default). A breaker
+     starts tripped when the held-out error measured for its queries is
+     already above the limit, and audits are applied in stream order: when
+     one trips the breaker, every later query of the batch that the
+     surrogate was going to answer under that breaker is solved by the MPM
+     as well, so no surrogate answer leaves after the breaker has seen the
+     error;
   5. the MPM answers every query sent to it; the rest keep the surrogate's.
 Latency of a query = its batch's start -> its answer ready (all queries are
 queued at time zero and batches run back to back).
@@ -62,10 +68,15 @@ def audit_draws(n, rate, seed):
 class Router:
     """Surrogate answers with OOD and audit fallbacks to the MPM. The circuit
     breaker is kept per indenter family when per_class is set (the query names
-    its indenter), else one breaker covers every query."""
+    its indenter), else one breaker covers every query. prior_rmse_um maps a
+    breaker key to the surrogate's held-out height RMSE for its queries;
+    breakers whose prior exceeds the limit start tripped."""
+
+    # route codes
+    SURROGATE, OOD, AUDIT, BREAKER, BREAKER_IN_BATCH = 0, 1, 2, 3, 4
 
     def __init__(self, net: Net, train_features, threshold, audit_rate=0.02, audit_seed=7, rmse_limit_um=5.0,
-                 window=20, per_class=True):
+                 window=20, per_class=True, prior_rmse_um=None):
         self.net = net
         self.train_features = train_features.contiguous()
         self.threshold = float(threshold)
@@ -74,11 +85,16 @@ class Router:
         self.rmse_limit_um = rmse_limit_um
         self.window = window
         self.per_class = per_class
+        self.prior_rmse_um = {int(k): float(v) for k, v in (prior_rmse_um or {}).items()}
 
     @staticmethod
     def calibrate(train_features, heldout_features, q=0.995):
         d, _ = nn_distance(heldout_features.contiguous(), train_features.contiguous())
         return float(torch.quantile(d.cpu(), q))
+
+    def _over_limit(self, sq):
+        recent = sq[-self.window:]
+        return math.sqrt(sum(recent) / len(recent)) > self.rmse_limit_um
 
     def serve(self, contacts, batch=512, log=None):
         """Answer every contact; returns (answers [n][res][res][3] in Y_UNIT, report dict)."""
@@ -87,9 +103,10 @@ class Router:
         key = np.array([c["cfg"]["shape"] if self.per_class else 0 for c in contacts])
         answers = torch.empty(n, D.RES, D.RES, 3, dtype=torch.float32, device="cuda")
         lat = np.zeros(n)
-        route = np.zeros(n, dtype=np.int8)  # 0 surrogate, 1 ood, 2 audit, 3 breaker
+        route = np.zeros(n, dtype=np.int8)
         audits_sq = {}
-        tripped = set()
+        tripped = {k for k, e in self.prior_rmse_um.items() if e > self.rmse_limit_um} if self.per_class else set()
+        tripped_at_start = sorted(tripped)
         n_mpm = 0
         torch.cuda.synchronize()
         t_all = time.perf_counter()
@@ -97,6 +114,7 @@ class Router:
             cs = contacts[k0:k0 + batch]
             m = len(cs)
             kb = key[k0:k0 + m]
+            rb = route[k0:k0 + m]  # view
             t0 = time.perf_counter()
             brk = np.array([k in tripped for k in kb], dtype=bool)
             x = D.inputs(cs)
@@ -108,56 +126,71 @@ class Router:
                 ood = (d > self.threshold).cpu().numpy() & ~brk
                 aud = audit[k0:k0 + m] & ~brk & ~ood
                 send |= ood | aud
-                route[k0:k0 + m][ood] = 1
-                route[k0:k0 + m][aud] = 2
+                rb[ood] = self.OOD
+                rb[aud] = self.AUDIT
                 answers[k0:k0 + m] = pred
-            route[k0:k0 + m][brk] = 3
+            rb[brk] = self.BREAKER
             torch.cuda.synchronize()
             lat[k0:k0 + m] = time.perf_counter() - t0
             idx = np.nonzero(send)[0]
+            late = []
             if len(idx):
                 ym = D.solve([cs[i] for i in idx])
                 n_mpm += len(idx)
                 it = torch.tensor(idx, device="cuda")
-                aud_idx = [j for j, i in enumerate(idx) if route[k0 + i] == 2]
+                aud_idx = [j for j, i in enumerate(idx) if rb[i] == self.AUDIT]
                 if aud_idx:
                     ai = torch.tensor(aud_idx, device="cuda")
                     e = per_sample_rmse(pred.index_select(0, it.index_select(0, ai)), ym.index_select(0, ai), 2)
+                    # audits in stream order: a breaker that trips re-routes the
+                    # later surrogate answers of its key in this batch
                     for j, v in zip(aud_idx, (e * D.Y_UNIT * 1e6).cpu().tolist()):
-                        audits_sq.setdefault(int(kb[idx[j]]), []).append(v * v)
+                        kk = int(kb[idx[j]])
+                        sq = audits_sq.setdefault(kk, [])
+                        sq.append(v * v)
+                        if kk not in tripped and self._over_limit(sq):
+                            tripped.add(kk)
+                            late += [i for i in range(idx[j] + 1, m) if kb[i] == kk and rb[i] == self.SURROGATE]
                 answers.index_copy_(0, it + k0, ym)
                 torch.cuda.synchronize()
                 lat[k0 + idx] = time.perf_counter() - t0
-            for k, sq in audits_sq.items():
-                recent = sq[-self.window:]
-                if k not in tripped and math.sqrt(sum(recent) / len(recent)) > self.rmse_limit_um:
-                    tripped.add(k)
+            if late:
+                late = np.array(sorted(late))
+                yl = D.solve([cs[i] for i in late])
+                n_mpm += len(late)
+                answers.index_copy_(0, torch.tensor(late, device="cuda") + k0, yl)
+                rb[late] = self.BREAKER_IN_BATCH
+                torch.cuda.synchronize()
+                lat[k0 + late] = time.perf_counter() - t0
             if log:
                 log(f"router: {k0 + m}/{n} answered, {n_mpm} by MPM, tripped={sorted(tripped)}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_all
         all_sq = [v for sq in audits_sq.values() for v in sq]
         audited = math.sqrt(sum(all_sq) / len(all_sq)) if all_sq else float("nan")
-        # audits of the classes the breaker left open: the error of what was served
-        open_sq = [v for k, sq in audits_sq.items() if k not in tripped for v in sq]
         rep = {
             "queries": n, "wall_s": wall, "frames_per_s": n / wall,
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mpm_fallbacks": int(n_mpm), "ood": int((route == 1).sum()), "audited": int((route == 2).sum()),
-            "breaker_routed": int((route == 3).sum()), "breaker_tripped": sorted(int(k) for k in tripped),
-            "served_by_surrogate": int((route == 0).sum()),
+            "mpm_fallbacks": int(n_mpm), "ood": int((route == self.OOD).sum()),
+            "audited": int((route == self.AUDIT).sum()),
+            "breaker_routed": int((route == self.BREAKER).sum()),
+            "breaker_rerouted_in_batch": int((route == self.BREAKER_IN_BATCH).sum()),
+            "breaker_tripped_at_start": [int(k) for k in tripped_at_start],
+            "breaker_tripped": sorted(int(k) for k in tripped),
+            "served_by_surrogate": int((route == self.SURROGATE).sum()),
             "audited_height_rmse_um": audited,
-            "audited_height_rmse_um_open_classes": math.sqrt(sum(open_sq) / len(open_sq)) if open_sq else None,
+            "prior_rmse_um": {str(k): v for k, v in sorted(self.prior_rmse_um.items())},
             "per_class": {str(int(k)): {"queries": int((key == k).sum()),
-                                        "surrogate": int(((key == k) & (route == 0)).sum()),
+                                        "surrogate": int(((key == k) & (route == self.SURROGATE)).sum()),
                                         "audits": len(audits_sq.get(int(k), [])),
                                         "audited_rmse_um": (math.sqrt(sum(audits_sq[int(k)]) / len(audits_sq[int(k)]))
                                                             if audits_sq.get(int(k)) else None),
-                                        "tripped": int(k) in tripped}
+                                        "tripped": int(k) in tripped,
+                                        "tripped_at_start": int(k) in tripped_at_start}
                           for k in np.unique(key)},
         }
-        return answers, rep
+        return answers, rep, route
 
 
 def plain_mpm(contacts, batch=512, log=None):

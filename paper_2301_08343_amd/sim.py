@@ -80,8 +80,16 @@ class Sim:
         """Represent the indenter by points [n][3] (indenter frame, metres) of
         `mass` kg each; an empty array returns to the shape's contact."""
         pts = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        n = pts.shape[0]
+        nbytes = int(N.lib().tacchi_points_workspace_bytes(self._h, n)) if n > 0 else 0
+        ws, ptr = None, 0
+        if nbytes:
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
         N.check(N.lib().tacchi_set_indenter_points(self._h, pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                                   pts.shape[0], float(mass)))
+                                                   n, float(mass), ctypes.c_void_p(ptr), nbytes))
+        # the points and per-node indenter mass live here until the next call
+        self._points_ws = ws
 
     def run_until_force(self, poses, dt: float, fz_limit: float) -> int:
         """Substeps to poses[0], poses[1], ... until the z contact force on the
@@ -206,6 +214,10 @@ def indenter_gap(cfgs, poses, res: int, lo: float = -2e-3, hi: float = 2e-3, dev
         carr[k] = N.make_config(cfgs[k], poses[k], N.F32, 0)
         parr[k] = N.make_pose(poses[k])
     out = torch.empty(n, res, res, dtype=torch.float32, device=device)
+    nbytes = int(N.lib().tacchi_indenter_gap_workspace_bytes(n))
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
     N.check(N.lib().tacchi_indenter_gap(carr, parr, n, res, sub, lo, hi, ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(ptr), nbytes,
                                         ctypes.c_void_p(torch.cuda.current_stream(out.device).cuda_stream)))
     return out

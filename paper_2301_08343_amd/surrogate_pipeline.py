@@ -17,6 +17,7 @@ import os
 import sys
 import time
 
+import numpy as np
 import torch
 
 from . import dataset as D
@@ -91,20 +92,41 @@ def train_features(n, h, chunk=2048):
     return torch.cat(out)
 
 
-def serve_benchmark(net, ftr, thr, h, queries, plain_sample, log=log):
-    """The query stream through the router, and plain batched MPM on its first
-    `plain_sample` queries (whose answers also measure the served error)."""
+def served_sample(n, k, seed=11):
+    """About k query indices spread over a stream of n: query i is in the
+    sample when the i-th SplitMix64 output of `seed` is below (k / n) 2^64."""
+    from .workloads import SplitMix64
+    rng = SplitMix64(seed)
+    lim = int(min(1.0, k / n) * 2.0 ** 64)
+    return [i for i in range(n) if rng.next_u64() < lim]
+
+
+def serve_benchmark(net, ftr, thr, h, queries, plain_sample, prior_rmse_um=None, log=log):
+    """The query stream through the router, and plain batched MPM on a seeded
+    sample of about `plain_sample` queries spread over the whole stream: its
+    rate is the plain MPM's frames/s, and its answers measure the error of
+    the answers the router served for those queries (per family too)."""
     rep = {}
     qs = D.contacts_for(range(QUERY_SEED0, QUERY_SEED0 + queries), h, full=False)
-    r = RT.Router(net, ftr, thr)
-    ans, rrep = r.serve(qs, log=log)
+    r = RT.Router(net, ftr, thr, prior_rmse_um=prior_rmse_um)
+    ans, rrep, route = r.serve(qs, log=log)
     rep["router"] = rrep
     log(f"router: {json.dumps(rrep)}")
-    k = min(plain_sample, queries)
-    ymp, prep = RT.plain_mpm(qs[:k], log=log)
-    rep["plain_mpm"] = dict(prep, note=f"first {k} queries; frames/s extrapolates to the stream")
-    served = TR.per_sample_rmse(ans[:k], ymp, 2) * D.Y_UNIT * 1e6
+    pick = served_sample(queries, plain_sample)
+    ymp, prep = RT.plain_mpm([qs[i] for i in pick], log=log)
+    rep["plain_mpm"] = dict(prep, note=f"{len(pick)} queries sampled over the stream; frames/s is per query")
+    served = (TR.per_sample_rmse(ans[torch.tensor(pick, device=ans.device)], ymp, 2) * D.Y_UNIT * 1e6).cpu()
+    fam = torch.tensor([qs[i]["cfg"]["shape"] for i in pick])
+    by_route = torch.tensor(route[pick].astype(np.int64))
     rep["served_vs_mpm_height_rmse_um"] = float((served ** 2).mean().sqrt())
+    rep["served_sample"] = {
+        "queries": len(pick), "first_index": pick[0], "last_index": pick[-1], "seed": 11,
+        "height_rmse_um_by_family": {str(int(k)): float((served[fam == k] ** 2).mean().sqrt())
+                                     for k in torch.unique(fam)},
+        "surrogate_answers": int((by_route == RT.Router.SURROGATE).sum()),
+        "height_rmse_um_of_surrogate_answers": (
+            float((served[by_route == RT.Router.SURROGATE] ** 2).mean().sqrt())
+            if bool((by_route == RT.Router.SURROGATE).any()) else None)}
     rep["speedup_frames_per_s"] = rrep["frames_per_s"] / prep["frames_per_s"]
     log(f"plain MPM: {json.dumps(prep)}; served answers vs MPM: "
         f"{rep['served_vs_mpm_height_rmse_um']:.2f} um; speedup {rep['speedup_frames_per_s']:.1f}x")
@@ -221,7 +243,8 @@ def main(argv=None):
         serve_net = Net(batch=512, seed=0, contact_residual=net.contact_residual)
         serve_net.flat.copy_(net.flat)
         serve_net.repack()
-        rep.update(serve_benchmark(serve_net, ftr, thr, a.h, a.queries, a.plain_sample))
+        rep.update(serve_benchmark(serve_net, ftr, thr, a.h, a.queries, a.plain_sample,
+                                   prior_rmse_um=rep["heldout"].get("height_rmse_um_by_group")))
 
     with open(os.path.join(a.out, "report.json"), "w") as f:
         json.dump(rep, f, indent=1)

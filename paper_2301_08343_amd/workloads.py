@@ -280,13 +280,18 @@ def gelsight_contact_at(seed: int, h: float = 0.2e-3, full: bool = True):
                 poses=poses, end_pose=end, depth=depth, particles=nxy * nxy * nz, seed=seed, h=h)
 
 
-def batch_contact(seed: int, steps: int = 2000):
+def batch_contact(seed: int, steps: int = 2000, max_lateral: int = 0):
     """One contact of the uneven batch: particle count log-uniform in
     [2e4, 4e5]; block side L ~ U[10, 20] mm, thickness T ~ U[3, 5] mm,
     spacing h = (L^2 T / N)^(1/3) (redrawn until h is in [0.1, 0.3] mm);
     E ~ U[0.1, 0.3] MPa, nu ~ U[0.40, 0.48]; fixed-corotated material;
     indenter family and depth as in the GelSight workload plus a tilt of up to
-    5 degrees about a random horizontal axis; dt = 0.45 dx / c_p."""
+    5 degrees about a random horizontal axis; dt = 0.45 dx / c_p.
+
+    max_lateral > 0 keeps every draw (h, thickness, material, indenter, tilt,
+    depth, time step) but cuts the block to at most that many particles per
+    lateral axis, with the grid margin and xy jitter sized to the cut block:
+    the same contact at a size a single-core solver finishes quickly."""
     rng = SplitMix64(0xBA7C + seed)
     while True:
         N = math.exp(rng.uniform(math.log(2e4), math.log(4e5)))
@@ -296,6 +301,8 @@ def batch_contact(seed: int, steps: int = 2000):
         if 0.1e-3 <= h <= 0.3e-3:
             break
     nxy = max(8, int(round(L / h)))
+    if max_lateral > 0:
+        nxy = min(nxy, max_lateral)
     nz = max(4, int(round(T / h)))
     dx = h
     margin = max(6, int(math.ceil(0.12 * nxy)))

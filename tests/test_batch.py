@@ -105,6 +105,36 @@ def test_small_batch_matches_oracle(oracle_lib, gpu):
         assert np.abs(to_np(batch.contact(i).heightmap()) - orc.heightmap()).max() <= 0.1e-6
 
 
+def test_drawn_batch_matches_oracle(oracle_lib, gpu):
+    """Contacts drawn by the uneven batch's generator (seeds covering the five
+    indenter families: lattice spacing, thickness, E, nu, corotated law, tilt,
+    depth and time step as drawn), cut to 32 x 32 particles laterally, pressed
+    to their drawn depth in 400 substeps in one batch, FP32 with the FP64
+    polar gate, against the FP64 oracle: positions within 1e-5 of the cut
+    block's width and depth maps within 0.1 um."""
+    Batch, _ = gpu
+    S = 400
+    seeds = [0, 1, 2, 3, 6]  # textured plate, edge, sphere, cylinder, cone
+    contacts = [W.batch_contact(s, steps=S, max_lateral=32) for s in seeds]
+    assert sorted(c["cfg"]["shape"] for c in contacts) == [0, 1, 2, 3, 4]
+    batch = Batch(contacts, S)
+    batch.run(S)
+    batch.sync()
+    for i, c in enumerate(contacts):
+        print(f"drawn contact {c['name']}: n = {c['cfg']['n']}, h = {c['cfg']['dx'] * 1e3:.3f} mm", flush=True)
+        orc = oracle_lib.OracleSim(c["cfg"], c["poses"][0])
+        orc.run(c["poses"], c["dt"], 0, S)
+        xo = orc.particles()[0]
+        Ho = orc.heightmap()
+        xb = to_np(batch.contact(i).read_particles()[0]).T
+        Hb = to_np(batch.contact(i).heightmap())
+        err, err_h = np.abs(xb - xo).max(), np.abs(Hb - Ho).max()
+        print(f"  max |dx| = {err:.3e} m, max |dH| = {err_h:.3e} m, indent {W.top_z(c['cfg']) - Ho.min():.3e} m")
+        assert W.top_z(c["cfg"]) - Ho.min() > 0.1e-3  # the contact engaged
+        assert err <= 1e-5 * c["cfg"]["block_size"][0]
+        assert err_h <= 0.1e-6
+
+
 def test_tuner_writes_and_reuses_its_cache(gpu, tmp_path):
     Batch, _ = gpu
     S = 30

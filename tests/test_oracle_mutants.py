@@ -85,6 +85,9 @@ MUTANTS = [
      "g[k] = (phi_world(s, s->pose, a) - phi_world(s, s->pose, b)) / (2.0 * eps);",
      "g[k] = (phi_world(s, s->pose, b) - phi_world(s, s->pose, a)) / (2.0 * eps);", "does_not_pull"),
     ("coulomb_never_separates", "if (un >= 0.0) {", "if (un >= 1e300) {", "does_not_pull"),
+    ("noise_cubic_fade",
+     "double u = fx * fx * fx * (fx * (fx * 6.0 - 15.0) + 10.0);", "double u = fx * fx * (3.0 - 2.0 * fx);",
+     "gradient_noise"),
     ("indenter_scatter_weight",
      "+= w[0][a] * w[1][b] * w[2][c] * s->imass;", "+= w[0][a] * w[1][b] * s->imass;", "placed_by_the_pose"),
     ("indenter_points_rotation_transposed",

@@ -573,6 +573,43 @@ def test_indenter_shapes(oracle_lib):
     assert oracle_lib.noise2(9, 0.5, 0.5) != oracle_lib.noise2(10, 0.5, 0.5)
 
 
+def test_noise_is_gradient_noise_with_a_curvature_free_fade(oracle_lib):
+    """The textured plate's gradient noise (Perlin 2002): at a lattice point
+    the fade's slope vanishes, so the noise's gradient there is that corner's
+    own gradient vector, one of (+-1, 0), (0, +-1), (+-1, +-1); the quintic
+    fade also has zero curvature at 0 and 1, so the noise's second derivative
+    is continuous across lattice lines (with the cubic 3t^2 - 2t^3 fade it
+    jumps by O(1))."""
+    n = oracle_lib.noise2
+    h = 1e-6
+    allowed = {(1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1)}
+    seen = set()
+    for ix in range(-4, 5):
+        for iy in range(-4, 5):
+            gx = (n(9, ix + h, iy) - n(9, ix - h, iy)) / (2 * h)
+            gy = (n(9, ix, iy + h) - n(9, ix, iy - h)) / (2 * h)
+            g = (int(round(gx)), int(round(gy)))
+            assert g in allowed and abs(gx - g[0]) < 1e-5 and abs(gy - g[1]) < 1e-5, (ix, iy, gx, gy)
+            seen.add(g)
+    assert len(seen) >= 6  # the hash spreads the corners over the gradient set
+
+    def d2x(x, y, e):
+        return (n(9, x + e, y) - 2.0 * n(9, x, y) + n(9, x - e, y)) / (e * e)
+
+    def d2y(x, y, e):
+        return (n(9, x, y + e) - 2.0 * n(9, x, y) + n(9, x, y - e)) / (e * e)
+
+    # one-sided second differences 2e either side of a lattice line differ by
+    # about 4e times the noise's third derivative (~10^2): 3e-3 at e = 1e-5
+    e = 1e-5
+    jumps = []
+    for k in range(-4, 5):
+        for off in (-2.63, -1.37, 0.37, 1.81):
+            jumps.append(abs(d2x(k + 2 * e, off, e) - d2x(k - 2 * e, off, e)))
+            jumps.append(abs(d2y(off, k + 2 * e, e) - d2y(off, k - 2 * e, e)))
+    assert max(jumps) < 0.02, max(jumps)
+
+
 def test_indenter_velocity_rigid_motion(oracle_lib):
     p0 = np.array([1e-3, 2e-3, 3e-3, 1, 0, 0, 0])
     p1 = np.array([1.5e-3, 2e-3, 2.9e-3, 1, 0, 0, 0])

@@ -4,6 +4,7 @@ router's report is consistent, and the circuit breaker hands everything to
 the MPM when its limit cannot be met."""
 import json
 
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -26,7 +27,10 @@ def test_pipeline_small(gpu, tmp_path):
     assert rep["train"]["loss_curve"][-1] < rep["train"]["loss_curve"][0]
     r = rep["router"]
     assert r["queries"] == 300
-    assert r["mpm_fallbacks"] == r["ood"] + r["audited"] + r["breaker_routed"]
+    assert r["mpm_fallbacks"] == r["ood"] + r["audited"] + r["breaker_routed"] + r["breaker_rerouted_in_batch"]
+    assert r["served_by_surrogate"] + r["mpm_fallbacks"] == 300
+    # the served answers' error is measured on a sample spread over the stream
+    assert rep["served_sample"]["queries"] >= 32 and rep["served_sample"]["last_index"] >= 200
     assert r["audited"] >= 1  # 2% of 300 draws
     assert (tmp_path / "surrogate.safetensors").exists()
 
@@ -42,15 +46,43 @@ def test_breaker_routes_everything_to_mpm(gpu, tmp_path):
     ftr = RT.features(D.inputs(train))
     qs = D.contacts_for(range(1000, 1096), 0.5e-3)
     r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.5, rmse_limit_um=1e-6, per_class=False)
-    ans, rep = r.serve(qs, batch=32)
+    ans, rep, route = r.serve(qs, batch=32)
     assert rep["breaker_tripped"] == [0]
     assert rep["breaker_routed"] == 64  # batches 2 and 3
-    ym = D.solve(qs[32:])
-    assert torch.allclose(ans[32:], ym, rtol=0, atol=1e-4)  # 10 nm: the answers are the MPM's
-    # one breaker per indenter family: a family trips once it has an audit
+    # audits act in stream order: after the first audit of batch 1 no
+    # surrogate answer is served
+    first = int(np.nonzero(route == RT.Router.AUDIT)[0][0])
+    assert first < 32
+    assert not np.any(route[first + 1:] == RT.Router.SURROGATE)
+    assert rep["breaker_rerouted_in_batch"] == int(np.sum(route[first + 1:32] == RT.Router.BREAKER_IN_BATCH))
+    ym = D.solve(qs[first + 1:])
+    assert torch.allclose(ans[first + 1:], ym, rtol=0, atol=1e-4)  # 10 nm: the answers are the MPM's
+    # one breaker per indenter family: a family trips at its first audit
     r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.5, rmse_limit_um=1e-6, per_class=True)
-    _, rep = r.serve(qs, batch=32)
+    _, rep, route = r.serve(qs, batch=32)
     for k, pc in rep["per_class"].items():
         assert pc["tripped"] == (pc["audits"] > 0)
     assert rep["breaker_routed"] > 0
     assert sum(pc["queries"] for pc in rep["per_class"].values()) == 96
+
+
+def test_breaker_starts_tripped_from_the_heldout_error(gpu):
+    """A family whose held-out error is above the limit never gets a surrogate
+    answer; the others start open."""
+    from paper_2301_08343_amd import dataset as D
+    from paper_2301_08343_amd import router as RT
+    from paper_2301_08343_amd.surrogate import Net
+    net = Net(batch=64, seed=1)
+    ftr = RT.features(D.inputs(D.contacts_for(range(64), 0.5e-3)))
+    qs = D.contacts_for(range(2000, 2064), 0.5e-3)
+    fam = np.array([c["cfg"]["shape"] for c in qs])
+    prior = {0: 1.0, 1: 7.5, 2: 2.0, 3: 6.0, 4: 1.0}
+    r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.0, rmse_limit_um=5.0, per_class=True, prior_rmse_um=prior)
+    ans, rep, route = r.serve(qs, batch=32)
+    assert rep["breaker_tripped_at_start"] == [1, 3]
+    bad = np.isin(fam, [1, 3])
+    assert np.all(route[bad] == RT.Router.BREAKER)
+    assert np.all(route[~bad] == RT.Router.SURROGATE)
+    idx = np.nonzero(bad)[0]
+    ym = D.solve([qs[i] for i in idx])
+    assert torch.allclose(ans[torch.tensor(idx, device="cuda")], ym, rtol=0, atol=1e-4)
