@@ -64,6 +64,7 @@ struct SimDev {
     int g0, g1, g2;        // grid nodes per axis
     int nb0, nb1, nb2;     // grid blocks per axis
     int nblk;
+    int xcd_chunk;         // blocks per XCD chunk of the per-block kernels (xcd_block)
     int ts0, ts1, ts2;     // lattice index i lies in tile (i + ts) / B
     int nt0, nt1, nt2;     // tiles per axis
     FastDiv div_nt0, div_nt1, div_n0, div_n1;
@@ -102,6 +103,7 @@ struct IndenterDev {
     T dx;                  // [m] converts grid units to metres for the shape
     T mu;                  // Coulomb friction coefficient (grid kernels instantiated with friction)
     T eps;                 // [m] step of the central differences giving the contact normal
+    T zmin;                // [m] below this indenter-frame height a point is outside the solid
     const double *MI;      // particle indenter: its mass per grid node (x fastest), else null
     int blo[3], bhi[3];    // node box (inclusive) outside which MI is zero this substep
 };
@@ -114,6 +116,24 @@ template <typename T>
 __device__ __forceinline__ bool finite3(T a, T b, T c)
 {
     return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+// Grid block of workgroup i in the per-block kernels. Workgroups are handed to
+// the eight XCDs round robin (workgroup i to XCD i mod 8), and each XCD has its
+// own L2. Here XCD x takes whole chunks of C consecutive blocks (chunks x,
+// x + 8, x + 16, ...): three rows of blocks, so the tile and velocity halos
+// that neighbouring blocks share along x and y are fetched into one L2. With
+// three rows a round of 8 chunks (24 rows) does not tile a z layer of the
+// GelSight grid (32 rows), so the XCDs rotate over the rows from layer to
+// layer and none is left with the empty border rows only (chunks that tile
+// the layer were measured 10-15 % slower than this). Blocks past the last
+// whole round of 8 chunks keep their index. A bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int i, int n, int C)
+{
+    const int R = 8 * C;
+    if (C <= 1 || i >= (n / R) * R) return i;
+    const int x = i & 7, j = i >> 3;
+    return ((j / C) * 8 + x) * C + (j % C);
 }
 
 template <int B>
