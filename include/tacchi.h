@@ -270,6 +270,24 @@ tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *
                                   int32_t res, int32_t sub, double lo, double hi, float *out,
                                   void *dev_ws, size_t ws_bytes, void *hip_stream);
 
+/* tacchi_indenter_gap for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same gap field, computed by the same kernel from the same
+ * arguments, with the n query descriptors kept in a fixed device array of the
+ * library instead of a caller workspace. Nothing is allocated: the array comes
+ * with the library's code object, one copy per GPU, held until the process
+ * ends; its address on a GPU is looked up on the first call there (with that
+ * GPU current). n <= tacchi_indenter_gap_noalloc_max() (2048), else E_ARG.
+ * hip_stream must belong to the current GPU. Every call on a GPU uses that
+ * GPU's one array, so calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller; the call synchronises
+ * hip_stream before it returns. Errors as tacchi_indenter_gap (no
+ * E_WORKSPACE). */
+int32_t tacchi_indenter_gap_noalloc_max(void);
+tacchi_status tacchi_indenter_gap_noalloc(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n,
+                                          int32_t res, int32_t sub, double lo, double hi, float *out,
+                                          void *hip_stream);
+
 /* Particle state in SoA layout (see the conventions); any pointer may be
  * NULL to skip that array. Synchronises. */
 tacchi_status tacchi_read_particles(tacchi_sim *sim, void *x, void *v, void *C, void *F,

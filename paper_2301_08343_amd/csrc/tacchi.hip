@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1295,17 +1296,18 @@ size_t tacchi_indenter_gap_workspace_bytes(int32_t n)
     return n < 1 ? 0 : (size_t)n * sizeof(GapDev);
 }
 
-tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res,
-                                  int32_t sub, double lo, double hi, float *out, void *dev_ws, size_t ws_bytes,
-                                  void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Validated query descriptors of a gap-field call.
+tacchi_status gap_queries(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res, int32_t sub,
+                          double lo, double hi, const float *out, const char *who, std::vector<GapDev> &q)
 {
     if (!cfgs || !poses || !out || n < 1 || res < 1 || res > 4096 || sub < 1 || sub > 16 || !(hi > lo) ||
         !std::isfinite(lo) || !std::isfinite(hi) || hi - lo > 1.0)
-        return fail(TACCHI_E_ARG, "tacchi_indenter_gap: bad arguments");
-    if (!dev_ws || ((uintptr_t)dev_ws & 255) || ws_bytes < tacchi_indenter_gap_workspace_bytes(n))
-        return fail(TACCHI_E_WORKSPACE, "tacchi_indenter_gap: workspace missing, misaligned or smaller than "
-                                        "tacchi_indenter_gap_workspace_bytes(n)");
-    std::vector<GapDev> q((size_t)n);
+        return fail(TACCHI_E_ARG, std::string(who) + ": bad arguments");
+    q.resize((size_t)n);
     for (int k = 0; k < n; ++k) {
         const tacchi_config &c = cfgs[k];
         if (c.ind.shape < TACCHI_SPHERE || c.ind.shape > TACCHI_TEXTURED_PLATE)
@@ -1323,19 +1325,92 @@ tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *
         q[k].wy = c.block.size[1];
         q[k].ztop = c.block.origin[2] + c.block.size[2];
     }
-    hipStream_t st = (hipStream_t)hip_stream;
-    GapDev *dq = (GapDev *)dev_ws;
+    return TACCHI_OK;
+}
+
+// Copies the descriptors to dq (device memory) and runs the gap kernel on st;
+// synchronises (q is pageable host memory read by the copy).
+tacchi_status gap_run(const std::vector<GapDev> &q, GapDev *dq, int32_t res, int32_t sub, double lo, double hi,
+                      float *out, hipStream_t st, const char *who)
+{
+    const int n = (int)q.size();
     hipError_t e = hipMemcpyAsync(dq, q.data(), q.size() * sizeof(GapDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_indenter_gap, dim3(grid1d((int64_t)n * res * res)), dim3(kWG), 0, st, dq, n, res, sub,
                            lo, hi, out);
         e = hipGetLastError();
     }
-    // q is pageable host memory read by the copy: wait before it goes
     const hipError_t es = hipStreamSynchronize(st);
     if (e != hipSuccess || es != hipSuccess)
-        return fail(TACCHI_E_DEVICE, std::string("tacchi_indenter_gap: ") + hipGetErrorString(e != hipSuccess ? e : es));
+        return fail(TACCHI_E_DEVICE, std::string(who) + ": " + hipGetErrorString(e != hipSuccess ? e : es));
     return TACCHI_OK;
+}
+
+// Query descriptors of tacchi_indenter_gap_noalloc: a fixed array in device
+// memory that comes with the library's code object, one copy on each GPU the
+// library runs on, held until the process ends. Host code never uses its name
+// as an address (that is a host-side stand-in): the device address of each
+// GPU's copy is looked up once, with that GPU current, and kept.
+constexpr int kGapNoAllocMax = 2048;
+static __device__ __align__(256) unsigned char scratch[kGapNoAllocMax * sizeof(GapDev)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+tacchi_status gap_scratch(void **out)
+{
+    int dev = -1;
+    TC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TACCHI_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TACCHI_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TACCHI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tacchi_status tacchi_indenter_gap(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n, int32_t res,
+                                  int32_t sub, double lo, double hi, float *out, void *dev_ws, size_t ws_bytes,
+                                  void *hip_stream)
+{
+    std::vector<GapDev> q;
+    tacchi_status st = gap_queries(cfgs, poses, n, res, sub, lo, hi, out, "tacchi_indenter_gap", q);
+    if (st) return st;
+    if (!dev_ws || ((uintptr_t)dev_ws & 255) || ws_bytes < tacchi_indenter_gap_workspace_bytes(n))
+        return fail(TACCHI_E_WORKSPACE, "tacchi_indenter_gap: workspace missing, misaligned or smaller than "
+                                        "tacchi_indenter_gap_workspace_bytes(n)");
+    return gap_run(q, (GapDev *)dev_ws, res, sub, lo, hi, out, (hipStream_t)hip_stream, "tacchi_indenter_gap");
+}
+
+int32_t tacchi_indenter_gap_noalloc_max(void)
+{
+    return kGapNoAllocMax;
+}
+
+tacchi_status tacchi_indenter_gap_noalloc(const tacchi_config *cfgs, const tacchi_pose *poses, int32_t n,
+                                          int32_t res, int32_t sub, double lo, double hi, float *out,
+                                          void *hip_stream)
+{
+    if (n > kGapNoAllocMax)
+        return fail(TACCHI_E_ARG, "tacchi_indenter_gap_noalloc: more queries than "
+                                  "tacchi_indenter_gap_noalloc_max() (" + std::to_string(kGapNoAllocMax) + ")");
+    std::vector<GapDev> q;
+    tacchi_status st = gap_queries(cfgs, poses, n, res, sub, lo, hi, out, "tacchi_indenter_gap_noalloc", q);
+    if (st) return st;
+    void *dq = nullptr;
+    st = gap_scratch(&dq);
+    if (st) return st;
+    return gap_run(q, (GapDev *)dq, res, sub, lo, hi, out, (hipStream_t)hip_stream, "tacchi_indenter_gap_noalloc");
 }
 
 tacchi_status tacchi_render(tacchi_sim *s, const tacchi_render_params *rp, float *rgb, int32_t h, int32_t w,

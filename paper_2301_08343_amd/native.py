@@ -30,6 +30,7 @@ EXPORTS = (
     "tacchi_surface_displacement", "tacchi_indenter_gap", "tacchi_batch_surface_displacement", "tacchi_markers",
     "tacchi_run_until_force", "tacchi_set_contact", "tacchi_set_indenter_points",
     "tacchi_points_workspace_bytes", "tacchi_indenter_gap_workspace_bytes",
+    "tacchi_indenter_gap_noalloc", "tacchi_indenter_gap_noalloc_max",
 )
 NUM_KERNEL_CLASSES = 6
 KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
@@ -156,6 +157,12 @@ def lib():
         L.tacchi_points_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
         L.tacchi_indenter_gap_workspace_bytes.restype = ctypes.c_size_t
         L.tacchi_indenter_gap_workspace_bytes.argtypes = [ctypes.c_int32]
+        L.tacchi_indenter_gap_noalloc_max.restype = ctypes.c_int32
+        L.tacchi_indenter_gap_noalloc_max.argtypes = []
+        L.tacchi_indenter_gap_noalloc.restype = ctypes.c_int32
+        L.tacchi_indenter_gap_noalloc.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(Pose), ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                                  _vp, _vp]
         L.tacchi_set_contact.restype = ctypes.c_int32
         L.tacchi_set_contact.argtypes = [_vp, ctypes.c_int32, ctypes.c_double]
         L.tacchi_run_until_force.restype = ctypes.c_int32
