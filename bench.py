@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -237,29 +238,44 @@ def streaming_leg(n=200):
 def batch_leg(n=256, substeps=2000):
     """The uneven batch: n contacts (particle counts log-uniform in 2e4-4e5,
     corotated material, tilted indenters; seeds 0 .. n-1) advanced together
-    through their whole presses by graph-captured batched launches; the
-    timed region is the run alone (creation and tuning excluded)."""
+    through their whole presses by graph-captured batched launches. Creation
+    runs the tuner (a fresh cache: every (material, size class) is timed over
+    all its settings) and is reported apart; the timed region is the run."""
     import collections
+    import tempfile
     import torch
     from paper_2301_08343_amd import workloads as W
     from paper_2301_08343_amd.batch import Batch
     contacts = [W.batch_contact(seed, steps=substeps) for seed in range(n)]
-    t0 = time.perf_counter()
-    b = Batch(contacts, substeps)
-    b.sync()
-    setup = time.perf_counter() - t0
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "tune.json")
+        t0 = time.perf_counter()
+        b = Batch(contacts, substeps, tune_cache=cache, tune=True)
+        b.sync()
+        setup = time.perf_counter() - t0
+        with open(cache) as fh:
+            table = json.load(fh)["entries"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.run(substeps)
     b.sync()
     el = time.perf_counter() - t0
     total = sum(c["particles"] for c in contacts)
-    choices = collections.Counter(f"B{t}_wg{w}" for t, w, _ in b.tuning())
+    tuning = b.tuning()
+    us_tuned, us_default = b.tuning_check()
+    choices = collections.Counter(f"B{t}_wg{w}_ipw{q}" for t, w, q, _ in tuning)
     fallbacks = sum(b.contact(i).polar_fallbacks() for i in range(n))
     b.close()
+    classes = collections.Counter(int(math.floor(math.log2(W.lattice_count(c["cfg"])))) for c in contacts)
+    tuner = [{"model": e["model"], "log2n": e["log2n"], "contacts": classes.get(e["log2n"], 0),
+              "chosen": f"B{e['tile']}_wg{e['wg']}_ipw{e['ipw']}", "us_per_substep": e["us_per_substep"],
+              "candidates_us": {f"B{c[0]}_wg{c[1]}_ipw{c[2]}": c[3] for c in e["candidates"]}}
+             for e in sorted(table, key=lambda e: (e["model"], e["log2n"]))]
     return {"contacts": n, "particles": total, "substeps": substeps,
-            "particle_substeps_per_s": total * substeps / el, "seconds": el, "setup_seconds": setup,
-            "polar_fp64_fallbacks": fallbacks, "tuner_choices": dict(choices)}
+            "particle_substeps_per_s": total * substeps / el, "seconds": el, "setup_seconds_with_tuning": setup,
+            "polar_fp64_fallbacks": fallbacks, "tuner_choices": dict(choices), "tuner_table": tuner,
+            "tuner_batch_check_us_per_substep": {"tuned": us_tuned, "default_everywhere": us_default,
+                                                 "kept": "tuned" if us_tuned <= us_default else "default"}}
 
 
 def cpu_model():

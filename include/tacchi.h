@@ -342,11 +342,18 @@ void tacchi_destroy(tacchi_sim *sim);
  * a HIP graph and replayed. Contacts must be FP32 (precision TACCHI_F32).
  * Indenter trajectories are given up front: traj[i][k] is contact i's pose
  * after k substeps (k = 0..substeps); past the last entry the final pose is
- * held. A per-particle-count tuner picks each contact's grid block edge B in
- * {4, 8} and workgroup size in {128, 256} by timing a few substeps of one
- * contact per log2(N) class; choices are cached in the JSON file
- * `tune_cache` (read if present, extended when `tune` != 0; NULL disables the
- * file). Without a cached or tuned choice a contact uses B = 8, 256 threads.
+ * held. A tuner picks, per (material model, log2(N) class), the grid block
+ * edge B in {4, 8}, the workgroup size in {64, 128, 256} (grid update and G2P;
+ * P2G at B = 8 keeps 512 threads) and the work items (grid blocks) per
+ * workgroup in {1, 2}, by timing 20 substeps of each setting on up to 8 of
+ * the class's contacts launched together, after advancing them
+ * 200 substeps into their own presses; the per-class choices are then kept
+ * only if the whole batch runs at least as fast with them as with the default
+ * everywhere (tacchi_batch_tuning_check). Choices and the time of every
+ * candidate are cached in the JSON file `tune_cache` (keyed by GPU
+ * architecture, precision, material model and class; read if present,
+ * extended when `tune` != 0; NULL disables the file). Without a cached or
+ * tuned choice a contact uses B = 8, 256 threads, one block per workgroup.
  * The batch owns one single-contact handle per contact for read-out.
  * ------------------------------------------------------------------------- */
 typedef struct tacchi_batch tacchi_batch;   /* opaque, host memory owned by the library */
@@ -374,11 +381,18 @@ tacchi_status tacchi_batch_run(tacchi_batch *batch, int32_t substeps);
  * the batch: do not step, write or destroy it. NULL if i is out of range. */
 tacchi_sim *tacchi_batch_contact(tacchi_batch *batch, int32_t i);
 
-/* Per-contact tuning choice: grid block edge, workgroup size and the measured
- * microseconds per substep of the tuning run (0 if the choice was a default);
- * any pointer may be NULL, arrays hold n entries. */
-tacchi_status tacchi_batch_tuning(const tacchi_batch *batch, int32_t *tile, int32_t *wg,
+/* Per-contact tuning choice: grid block edge, workgroup size, grid blocks per
+ * workgroup and the measured microseconds per substep of the tuning run (0 if
+ * the choice was a default); any pointer may be NULL, arrays hold n entries. */
+tacchi_status tacchi_batch_tuning(const tacchi_batch *batch, int32_t *tile, int32_t *wg, int32_t *ipw,
                                   double *us_per_substep);
+
+/* The tuner's whole-batch check (batch created with tune != 0): microseconds
+ * per substep of the whole batch with the per-class choices and with the
+ * default setting for every contact, each timed over 20 substeps after
+ * advancing 200 into the presses; the batch keeps the choices only when they
+ * are not slower. Both 0 when the batch was not tuned. */
+tacchi_status tacchi_batch_tuning_check(const tacchi_batch *batch, double *us_tuned, double *us_default);
 
 /* Substeps advanced so far. */
 int64_t tacchi_batch_substeps_done(const tacchi_batch *batch);

@@ -57,11 +57,20 @@ class Batch:
         return self._views[i]
 
     def tuning(self):
+        """Per contact (tile B, workgroup size, grid blocks per workgroup, tuned us per substep)."""
         t = (ctypes.c_int32 * self.n)()
         w = (ctypes.c_int32 * self.n)()
+        q = (ctypes.c_int32 * self.n)()
         us = (ctypes.c_double * self.n)()
-        N.check(N.lib().tacchi_batch_tuning(self._h, t, w, us))
-        return [(t[i], w[i], us[i]) for i in range(self.n)]
+        N.check(N.lib().tacchi_batch_tuning(self._h, t, w, q, us))
+        return [(t[i], w[i], q[i], us[i]) for i in range(self.n)]
+
+    def tuning_check(self):
+        """(whole-batch us per substep with the tuned choices, with the default
+        everywhere); zeros when the batch was not tuned."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        N.check(N.lib().tacchi_batch_tuning_check(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def substeps_done(self) -> int:
         return int(N.lib().tacchi_batch_substeps_done(self._h))

@@ -5,8 +5,8 @@
 // range of the batch workspace, so state read-out (depth map, image,
 // particles) goes through the ordinary calls. Substeps are advanced by the
 // batched kernels of batch_kernels.hpp: contacts that share a tuning choice
-// (grid block edge B, workgroup size, material model) form a group, and each
-// phase of a substep is one launch per group. Runs of an even number of
+// (grid block edge B, workgroup size, work items per workgroup, material
+// model) form a group, and each phase of a substep is one launch per group. Runs of an even number of
 // substeps are captured once as a HIP graph and replayed.
 #include <fstream>
 #include <map>
@@ -20,7 +20,7 @@ struct tacchi_batch {
     hipStream_t stream = nullptr;
     std::vector<tacchi_config> cfgs;
     std::vector<tacchi_sim *> sims;
-    std::vector<int> tile, wg, log2n;
+    std::vector<int> tile, wg, ipw, log2n;
     std::vector<double> dt;
     std::vector<double> traj;  // [n][nsteps+1][7]
     std::vector<size_t> ws_off, ws_len;
@@ -31,7 +31,7 @@ struct tacchi_batch {
     int *step = nullptr;
     BatchItem *items = nullptr;
     struct Group {
-        int B, WG, model;
+        int B, WG, ipw, model;
         BatchItem *items;
         int count;
     };
@@ -42,6 +42,7 @@ struct tacchi_batch {
     hipGraph_t graph_def[2] = {nullptr, nullptr};
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::vector<double> tune_us;  // measured us/substep of the chosen setting per contact (0 = not tuned)
+    double tune_batch_us[2] = {0.0, 0.0};  // whole batch per substep: tuned choices, all default (0: not timed)
 };
 
 namespace {
@@ -115,12 +116,30 @@ std::string device_arch(int device)
 }
 
 // Tuning cache: a JSON object {"entries": [{"arch": ..., "precision": "f32",
-// "log2n": L, "tile": B, "wg": W, "us_per_substep": t}, ...]}.
-struct TuneEntry {
-    std::string arch;
-    int log2n, tile, wg;
+// "model": M, "log2n": L, "tile": B, "wg": W, "ipw": P, "us_per_substep": t,
+// "candidates": [[B, W, P, t], ...]}, ...]}, one entry per (arch, precision,
+// material model, log2 of the particle count); "candidates" lists every
+// setting the sweep timed.
+struct TuneCandidate {
+    int tile, wg, ipw;
     double us;
 };
+
+struct TuneEntry {
+    std::string arch;
+    int model, log2n, tile, wg, ipw;
+    double us;
+    std::vector<TuneCandidate> cands;
+};
+
+constexpr int kTuneTiles[] = {4, 8};
+constexpr int kTuneWGs[] = {64, 128, 256};
+constexpr int kTuneIPWs[] = {1, 2};
+
+bool tune_setting_known(int tile, int wg, int ipw)
+{
+    return (tile == 4 || tile == 8) && (wg == 64 || wg == 128 || wg == 256) && (ipw == 1 || ipw == 2);
+}
 
 std::vector<TuneEntry> read_tune_cache(const char *path)
 {
@@ -131,7 +150,6 @@ std::vector<TuneEntry> read_tune_cache(const char *path)
     std::stringstream ss;
     ss << f.rdbuf();
     const std::string s = ss.str();
-    size_t pos = 0;
     auto field = [](const std::string &e, const char *key) -> std::string {
         const std::string k = std::string("\"") + key + "\"";
         size_t p = e.find(k);
@@ -144,19 +162,23 @@ std::vector<TuneEntry> read_tune_cache(const char *path)
         while (q < e.size() && e[q] != ',' && e[q] != '}' && e[q] != '"') ++q;
         return e.substr(p, q - p);
     };
+    // entries are the objects holding "log2n"; their candidate lists hold no braces
+    size_t pos = 0;
     while ((pos = s.find('{', pos + 1)) != std::string::npos) {
         const size_t end = s.find('}', pos);
         if (end == std::string::npos) break;
         const std::string e = s.substr(pos, end - pos + 1);
         if (e.find("\"log2n\"") == std::string::npos) continue;
+        if (field(e, "precision") != "f32" || field(e, "model").empty()) continue;
         TuneEntry t;
         t.arch = field(e, "arch");
-        if (field(e, "precision") != "f32") continue;
+        t.model = std::atoi(field(e, "model").c_str());
         t.log2n = std::atoi(field(e, "log2n").c_str());
         t.tile = std::atoi(field(e, "tile").c_str());
         t.wg = std::atoi(field(e, "wg").c_str());
+        t.ipw = std::atoi(field(e, "ipw").c_str());
         t.us = std::atof(field(e, "us_per_substep").c_str());
-        if ((t.tile == 4 || t.tile == 8) && (t.wg == 128 || t.wg == 256)) out.push_back(t);
+        if (tune_setting_known(t.tile, t.wg, t.ipw)) out.push_back(t);
     }
     return out;
 }
@@ -170,54 +192,84 @@ bool write_tune_cache(const char *path, const std::vector<TuneEntry> &entries)
         const TuneEntry &t = entries[i];
         char buf[256];
         std::snprintf(buf, sizeof buf,
-                      "    {\"arch\": \"%s\", \"precision\": \"f32\", \"log2n\": %d, \"tile\": %d, \"wg\": %d, "
-                      "\"us_per_substep\": %.3f}%s\n",
-                      t.arch.c_str(), t.log2n, t.tile, t.wg, t.us, i + 1 < entries.size() ? "," : "");
+                      "    {\"arch\": \"%s\", \"precision\": \"f32\", \"model\": %d, \"log2n\": %d, \"tile\": %d, "
+                      "\"wg\": %d, \"ipw\": %d, \"us_per_substep\": %.3f, \"candidates\": [",
+                      t.arch.c_str(), t.model, t.log2n, t.tile, t.wg, t.ipw, t.us);
         f << buf;
+        for (size_t k = 0; k < t.cands.size(); ++k) {
+            std::snprintf(buf, sizeof buf, "%s[%d, %d, %d, %.3f]", k ? ", " : "", t.cands[k].tile, t.cands[k].wg,
+                          t.cands[k].ipw, t.cands[k].us);
+            f << buf;
+        }
+        f << (i + 1 < entries.size() ? "]},\n" : "]}\n");
     }
     f << "  ]\n}\n";
     return (bool)f;
 }
 
-template <int B, int MODEL, int WG>
-void launch_group_phase(tacchi_batch *bt, const tacchi_batch::Group &g, int phase, int parity, int bump)
+template <int B, int MODEL, int WG, int IPW>
+void launch_group_phase(tacchi_batch *bt, const tacchi_batch::Group &g, int phase, int parity, int bump, bool sort)
 {
-    const dim3 grid(g.count), blk(WG);
+    const dim3 grid((g.count + IPW - 1) / IPW), blk(WG);
     // P2G at B = 8 always runs kP2GWG-thread workgroups, as in the
     // single-contact path: its LDS tile allows few workgroups per CU, so the
     // resident waves come from the workgroup size (the tuned size applies to
     // the grid update and G2P)
     constexpr int P2G_WG = B == 8 ? kP2GWG : WG;
     if (phase == 0)
-        hipLaunchKernelGGL((k_p2g_batch<B, MODEL, P2G_WG>), grid, dim3(P2G_WG), 0, bt->stream, g.items,
+        hipLaunchKernelGGL((k_p2g_batch<B, MODEL, P2G_WG, IPW>), grid, dim3(P2G_WG), 0, bt->stream, g.items, g.count,
                            bt->descs[parity], bt->consts, bt->step, bump);
     else if (phase == 1)
-        hipLaunchKernelGGL((k_grid_batch<B, WG>), grid, blk, 0, bt->stream, g.items, bt->descs[parity], bt->consts,
-                           bt->itab, bt->nsteps, bt->step);
+        hipLaunchKernelGGL((k_grid_batch<B, WG, IPW>), grid, blk, 0, bt->stream, g.items, g.count, bt->descs[parity],
+                           bt->consts, bt->itab, bt->nsteps, bt->step);
+    else if (sort)
+        hipLaunchKernelGGL((k_g2p_batch<B, MODEL, WG, IPW, true>), grid, blk, 0, bt->stream, g.items, g.count,
+                           bt->descs[parity], bt->consts);
     else
-        hipLaunchKernelGGL((k_g2p_batch<B, MODEL, WG>), grid, blk, 0, bt->stream, g.items, bt->descs[parity],
-                           bt->consts);
+        hipLaunchKernelGGL((k_g2p_batch<B, MODEL, WG, IPW, false>), grid, blk, 0, bt->stream, g.items, g.count,
+                           bt->descs[parity], bt->consts);
 }
 
-void launch_group(tacchi_batch *bt, const tacchi_batch::Group &g, int phase, int parity, int bump)
+template <int B, int MODEL, int WG>
+void launch_group_w(tacchi_batch *bt, const tacchi_batch::Group &g, int phase, int parity, int bump, bool sort)
 {
-    const int key = (g.B == 4 ? 0 : 4) + (g.model ? 2 : 0) + (g.WG == 128 ? 0 : 1);
-    switch (key) {
-    case 0: launch_group_phase<4, 0, 128>(bt, g, phase, parity, bump); break;
-    case 1: launch_group_phase<4, 0, 256>(bt, g, phase, parity, bump); break;
-    case 2: launch_group_phase<4, 1, 128>(bt, g, phase, parity, bump); break;
-    case 3: launch_group_phase<4, 1, 256>(bt, g, phase, parity, bump); break;
-    case 4: launch_group_phase<8, 0, 128>(bt, g, phase, parity, bump); break;
-    case 5: launch_group_phase<8, 0, 256>(bt, g, phase, parity, bump); break;
-    case 6: launch_group_phase<8, 1, 128>(bt, g, phase, parity, bump); break;
-    default: launch_group_phase<8, 1, 256>(bt, g, phase, parity, bump); break;
-    }
+    if (g.ipw == 2)
+        launch_group_phase<B, MODEL, WG, 2>(bt, g, phase, parity, bump, sort);
+    else
+        launch_group_phase<B, MODEL, WG, 1>(bt, g, phase, parity, bump, sort);
 }
 
-tacchi_status batch_substep(tacchi_batch *bt, int parity)
+template <int B, int MODEL>
+void launch_group_bm(tacchi_batch *bt, const tacchi_batch::Group &g, int phase, int parity, int bump, bool sort)
 {
+    if (g.WG == 64)
+        launch_group_w<B, MODEL, 64>(bt, g, phase, parity, bump, sort);
+    else if (g.WG == 128)
+        launch_group_w<B, MODEL, 128>(bt, g, phase, parity, bump, sort);
+    else
+        launch_group_w<B, MODEL, 256>(bt, g, phase, parity, bump, sort);
+}
+
+void launch_group(tacchi_batch *bt, const tacchi_batch::Group &g, int phase, int parity, int bump,
+                  bool sort = false)
+{
+    if (g.B == 4)
+        g.model ? launch_group_bm<4, 1>(bt, g, phase, parity, bump, sort)
+                : launch_group_bm<4, 0>(bt, g, phase, parity, bump, sort);
+    else
+        g.model ? launch_group_bm<8, 1>(bt, g, phase, parity, bump, sort)
+                : launch_group_bm<8, 0>(bt, g, phase, parity, bump, sort);
+}
+
+// One substep of every group; `index` counts the batch's substeps (inside a
+// captured run: the substep's place in the run), and every kSortEvery-th
+// substep's G2P sorts the bin lists.
+tacchi_status batch_substep(tacchi_batch *bt, int parity, int64_t index)
+{
+    const bool sort = index % kSortEvery == kSortEvery - 1;
     for (int phase = 0; phase < 3; ++phase)
-        for (size_t gi = 0; gi < bt->groups.size(); ++gi) launch_group(bt, bt->groups[gi], phase, parity, gi == 0);
+        for (size_t gi = 0; gi < bt->groups.size(); ++gi)
+            launch_group(bt, bt->groups[gi], phase, parity, gi == 0, sort);
     TC_LAUNCHED();
     return TACCHI_OK;
 }
@@ -253,7 +305,7 @@ tacchi_status batch_build_groups(tacchi_batch *bt)
 {
     std::map<int, std::vector<int>> by_key;
     for (int i = 0; i < bt->n; ++i) {
-        const int key = bt->tile[i] * 1000 + bt->wg[i] * 10 + bt->cfgs[i].mat.model;
+        const int key = bt->tile[i] * 100000 + bt->wg[i] * 100 + bt->ipw[i] * 10 + bt->cfgs[i].mat.model;
         by_key[key].push_back(i);
     }
     std::vector<BatchItem> all;
@@ -264,7 +316,8 @@ tacchi_status batch_build_groups(tacchi_batch *bt)
         for (int i : kv.second)
             for (int b = 0; b < bt->sims[i]->d.nblk; ++b) all.push_back({i, b});
         const int i0 = kv.second[0];
-        bt->groups.push_back({bt->tile[i0], bt->wg[i0], bt->cfgs[i0].mat.model, nullptr, (int)(all.size() - start)});
+        bt->groups.push_back({bt->tile[i0], bt->wg[i0], bt->ipw[i0], bt->cfgs[i0].mat.model, nullptr,
+                              (int)(all.size() - start)});
         ranges.push_back({start, all.size() - start});
     }
     for (size_t g = 0; g < bt->groups.size(); ++g) bt->groups[g].items = bt->items + ranges[g].first;
@@ -281,27 +334,40 @@ tacchi_status batch_reset_step(tacchi_batch *bt)
     return TACCHI_OK;
 }
 
-// Times `reps` substeps of contact i alone with the given setting (after two
-// warmup substeps) and returns microseconds per substep. The contact is
-// re-created from its initial state before and after.
-tacchi_status batch_time_setting(tacchi_batch *bt, int i, int tile, int wgs, double *us)
+// Times kTuneReps substeps of the contacts `ids` (up to kTuneContacts of one
+// class, launched together as in the batch, so the time is their throughput
+// rather than one contact's latency) with the given setting and returns
+// microseconds per substep. The contacts start from their initial state and
+// are first advanced kTuneAdvance substeps along their own trajectories with
+// the default setting (so the timed substeps see indented, moving contacts),
+// then two warm-up substeps with the setting; they are re-created from their
+// initial state afterwards.
+constexpr int kTuneAdvance = 200, kTuneWarm = 2, kTuneReps = 20, kTuneContacts = 8;
+
+tacchi_status batch_time_setting(tacchi_batch *bt, const std::vector<int> &ids, int tile, int wgs, int ipw,
+                                 double *us)
 {
-    tacchi_status st = batch_make_contact(bt, i, tile);
-    if (st) return st;
     std::vector<BatchItem> its;
-    for (int b = 0; b < bt->sims[i]->d.nblk; ++b) its.push_back({i, b});
+    for (int i : ids) {
+        tacchi_status st = batch_make_contact(bt, i, tile);
+        if (st) return st;
+        for (int b = 0; b < bt->sims[i]->d.nblk; ++b) its.push_back({i, b});
+    }
     TC_HIP(hipMemcpyAsync(bt->items, its.data(), its.size() * sizeof(BatchItem), hipMemcpyHostToDevice, bt->stream));
-    st = batch_reset_step(bt);
+    tacchi_status st = batch_reset_step(bt);
     if (st) return st;
-    tacchi_batch::Group g{tile, wgs, bt->cfgs[i].mat.model, bt->items, (int)its.size()};
+    const int model = bt->cfgs[ids[0]].mat.model;
+    const tacchi_batch::Group base{tile, 256, 1, model, bt->items, (int)its.size()};
+    const tacchi_batch::Group g{tile, wgs, ipw, model, bt->items, (int)its.size()};
+    const int adv = std::min(kTuneAdvance, std::max(0, bt->nsteps - kTuneWarm - kTuneReps));
     hipEvent_t e0, e1;
     TC_HIP(hipEventCreate(&e0));
     TC_HIP(hipEventCreate(&e1));
-    const int warm = 2, reps = std::min(10, std::max(1, bt->nsteps - warm));
     int parity = 0;
-    for (int k = 0; k < warm + reps; ++k) {
-        if (k == warm) (void)hipEventRecord(e0, bt->stream);
-        for (int phase = 0; phase < 3; ++phase) launch_group(bt, g, phase, parity, 1);
+    for (int k = 0; k < adv + kTuneWarm + kTuneReps; ++k) {
+        if (k == adv + kTuneWarm) (void)hipEventRecord(e0, bt->stream);
+        const bool sort = k % kSortEvery == kSortEvery - 1;
+        for (int phase = 0; phase < 3; ++phase) launch_group(bt, k < adv ? base : g, phase, parity, 1, sort);
         parity ^= 1;
     }
     (void)hipEventRecord(e1, bt->stream);
@@ -311,8 +377,54 @@ tacchi_status batch_time_setting(tacchi_batch *bt, int i, int tile, int wgs, dou
     TC_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *us = 1e3 * ms / reps;
-    return batch_make_contact(bt, i, tile);
+    *us = 1e3 * ms / kTuneReps;
+    for (int i : ids) {
+        st = read_error_word(bt->sims[i]);
+        if (st) return st;
+        st = batch_make_contact(bt, i, tile);
+        if (st) return st;
+    }
+    return TACCHI_OK;
+}
+
+// Microseconds per substep of the whole batch with its current choices (all
+// contacts created with their tiles, groups built), over kTuneReps substeps
+// after kTuneAdvance + kTuneWarm; leaves the batch at its initial state.
+tacchi_status batch_time_all(tacchi_batch *bt, double *us)
+{
+    for (int i = 0; i < bt->n; ++i) {
+        tacchi_status st = batch_make_contact(bt, i, bt->tile[i]);
+        if (st) return st;
+    }
+    tacchi_status st = batch_build_groups(bt);
+    if (st) return st;
+    st = batch_reset_step(bt);
+    if (st) return st;
+    const int adv = std::min(kTuneAdvance, std::max(0, bt->nsteps - kTuneWarm - kTuneReps));
+    hipEvent_t e0, e1;
+    TC_HIP(hipEventCreate(&e0));
+    TC_HIP(hipEventCreate(&e1));
+    int parity = 0;
+    for (int k = 0; k < adv + kTuneWarm + kTuneReps; ++k) {
+        if (k == adv + kTuneWarm) (void)hipEventRecord(e0, bt->stream);
+        st = batch_substep(bt, parity, k);
+        if (st) return st;
+        parity ^= 1;
+    }
+    (void)hipEventRecord(e1, bt->stream);
+    TC_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    TC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *us = 1e3 * ms / kTuneReps;
+    for (int i = 0; i < bt->n; ++i) {
+        st = read_error_word(bt->sims[i]);
+        if (st) return st;
+        st = batch_make_contact(bt, i, bt->tile[i]);
+        if (st) return st;
+    }
+    return TACCHI_OK;
 }
 
 void batch_free(tacchi_batch *bt)
@@ -362,6 +474,7 @@ tacchi_status tacchi_batch_create(const tacchi_config *cfgs, int32_t n, const ta
     bt->sims.assign(n, nullptr);
     bt->tile.assign(n, 8);
     bt->wg.assign(n, 256);
+    bt->ipw.assign(n, 1);
     bt->tune_us.assign(n, 0.0);
     bt->dt.assign(dt, dt + n);
     bt->ws_off = L.off;
@@ -405,24 +518,37 @@ tacchi_status tacchi_batch_create(const tacchi_config *cfgs, int32_t n, const ta
         hipMemcpyAsync(bt->itab, itab.data(), itab.size() * sizeof(IndenterDev<double>), hipMemcpyHostToDevice,
                        bt->stream) != hipSuccess)
         return bail(fail(TACCHI_E_DEVICE, "upload of the batch tables failed"));
-    // tuning: cached choices, else timed sweeps per particle-count class
+    // tuning: cached choices, else timed sweeps per (material model,
+    // particle-count class) on the class's first contact
     const std::string arch = device_arch(bt->device);
     std::vector<TuneEntry> cache = read_tune_cache(tune_cache);
-    std::map<int, TuneEntry> chosen;
+    std::map<std::pair<int, int>, TuneEntry> chosen;
     for (const TuneEntry &t : cache)
-        if (t.arch == arch) chosen[t.log2n] = t;
+        if (t.arch == arch) chosen[{t.model, t.log2n}] = t;
     bool wrote = false;
+    std::map<std::pair<int, int>, std::vector<int>> members;
     for (int i = 0; i < n; ++i) {
-        const int cls = bt->log2n[i];
+        std::vector<int> &m = members[{cfgs[i].mat.model, bt->log2n[i]}];
+        if ((int)m.size() < kTuneContacts) m.push_back(i);
+    }
+    for (int i = 0; i < n; ++i) {
+        const std::pair<int, int> cls{cfgs[i].mat.model, bt->log2n[i]};
         if (!chosen.count(cls) && tune) {
-            TuneEntry best{arch, cls, 8, 256, 1e30};
-            for (int t : {4, 8})
-                for (int w : {128, 256}) {
-                    double us = 0.0;
-                    st = batch_time_setting(bt, i, t, w, &us);
-                    if (st) return bail(st);
-                    if (us < best.us) best = {arch, cls, t, w, us};
-                }
+            TuneEntry best{arch, cls.first, cls.second, 8, 256, 1, 1e30, {}};
+            for (int t : kTuneTiles)
+                for (int w : kTuneWGs)
+                    for (int q : kTuneIPWs) {
+                        double us = 0.0;
+                        st = batch_time_setting(bt, members[cls], t, w, q, &us);
+                        if (st) return bail(st);
+                        best.cands.push_back({t, w, q, us});
+                        if (us < best.us) {
+                            best.tile = t;
+                            best.wg = w;
+                            best.ipw = q;
+                            best.us = us;
+                        }
+                    }
             chosen[cls] = best;
             cache.push_back(best);
             wrote = true;
@@ -430,7 +556,32 @@ tacchi_status tacchi_batch_create(const tacchi_config *cfgs, int32_t n, const ta
         if (chosen.count(cls)) {
             bt->tile[i] = chosen[cls].tile;
             bt->wg[i] = chosen[cls].wg;
+            bt->ipw[i] = chosen[cls].ipw;
             bt->tune_us[i] = chosen[cls].us;
+        }
+    }
+    // the classes share each phase's launches, so the tuned choices are kept
+    // only if the whole batch runs faster with them than with the default
+    // setting for every contact (different choices make more, smaller
+    // launches per phase)
+    if (tune) {
+        double us_tuned = 0.0, us_default = 0.0;
+        st = batch_time_all(bt, &us_tuned);
+        if (st) return bail(st);
+        const std::vector<int> tile_t = bt->tile, wg_t = bt->wg, ipw_t = bt->ipw;
+        bt->tile.assign(n, 8);
+        bt->wg.assign(n, 256);
+        bt->ipw.assign(n, 1);
+        st = batch_time_all(bt, &us_default);
+        if (st) return bail(st);
+        bt->tune_batch_us[0] = us_tuned;
+        bt->tune_batch_us[1] = us_default;
+        if (us_tuned <= us_default) {
+            bt->tile = tile_t;
+            bt->wg = wg_t;
+            bt->ipw = ipw_t;
+        } else {
+            bt->tune_us.assign(n, 0.0);
         }
     }
     if (wrote && tune_cache && *tune_cache && !write_tune_cache(tune_cache, cache))
@@ -463,7 +614,7 @@ tacchi_status tacchi_batch_run(tacchi_batch *bt, int32_t substeps)
                 int q = p;
                 tacchi_status st = TACCHI_OK;
                 for (int k = 0; k < bt->graph_len && st == TACCHI_OK; ++k) {
-                    st = batch_substep(bt, q);
+                    st = batch_substep(bt, q, k);
                     q ^= 1;
                 }
                 hipGraph_t g = nullptr;
@@ -477,7 +628,7 @@ tacchi_status tacchi_batch_run(tacchi_batch *bt, int32_t substeps)
             left -= bt->graph_len;
             bt->done += bt->graph_len;
         } else {
-            tacchi_status st = batch_substep(bt, bt->parity);
+            tacchi_status st = batch_substep(bt, bt->parity, bt->done);
             if (st) return st;
             bt->parity ^= 1;
             left -= 1;
@@ -507,14 +658,24 @@ tacchi_sim *tacchi_batch_contact(tacchi_batch *bt, int32_t i)
     return bt->sims[i];
 }
 
-tacchi_status tacchi_batch_tuning(const tacchi_batch *bt, int32_t *tile, int32_t *wg, double *us_per_substep)
+tacchi_status tacchi_batch_tuning(const tacchi_batch *bt, int32_t *tile, int32_t *wg, int32_t *ipw,
+                                  double *us_per_substep)
 {
     if (!bt) return fail(TACCHI_E_ARG, "batch is NULL");
     for (int i = 0; i < bt->n; ++i) {
         if (tile) tile[i] = bt->tile[i];
         if (wg) wg[i] = bt->wg[i];
+        if (ipw) ipw[i] = bt->ipw[i];
         if (us_per_substep) us_per_substep[i] = bt->tune_us[i];
     }
+    return TACCHI_OK;
+}
+
+tacchi_status tacchi_batch_tuning_check(const tacchi_batch *bt, double *us_tuned, double *us_default)
+{
+    if (!bt || !us_tuned || !us_default) return fail(TACCHI_E_ARG, "NULL argument");
+    *us_tuned = bt->tune_batch_us[0];
+    *us_default = bt->tune_batch_us[1];
     return TACCHI_OK;
 }
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "tacchi_surface_displacement", "tacchi_indenter_gap", "tacchi_batch_surface_displacement", "tacchi_markers",
     "tacchi_run_until_force", "tacchi_set_contact", "tacchi_set_indenter_points",
     "tacchi_points_workspace_bytes", "tacchi_indenter_gap_workspace_bytes",
-    "tacchi_indenter_gap_noalloc", "tacchi_indenter_gap_noalloc_max",
+    "tacchi_indenter_gap_noalloc", "tacchi_indenter_gap_noalloc_max", "tacchi_batch_tuning_check",
 )
 NUM_KERNEL_CLASSES = 6
 KERNEL_CLASSES = ("bin", "p2g", "grid", "g2p", "heightmap", "render")
@@ -141,7 +141,9 @@ def lib():
         L.tacchi_batch_contact.argtypes = [_vp, ctypes.c_int32]
         L.tacchi_batch_tuning.restype = ctypes.c_int32
         L.tacchi_batch_tuning.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                          ctypes.POINTER(ctypes.c_double)]
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+        L.tacchi_batch_tuning_check.restype = ctypes.c_int32
+        L.tacchi_batch_tuning_check.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.tacchi_batch_substeps_done.restype = ctypes.c_int64
         L.tacchi_batch_substeps_done.argtypes = [_vp]
         L.tacchi_batch_sync.restype = ctypes.c_int32

@@ -135,21 +135,92 @@ def test_drawn_batch_matches_oracle(oracle_lib, gpu):
         assert err_h <= 0.1e-6
 
 
-def test_tuner_writes_and_reuses_its_cache(gpu, tmp_path):
+SETTINGS = [(t, w, q) for t in (4, 8) for w in (64, 128, 256) for q in (1, 2)]
+
+
+def test_tuner_sweeps_every_setting_and_reuses_its_cache(gpu, tmp_path):
+    """Per (material model, size class) the tuner times all 12 settings
+    (tile 4/8 x workgroup 64/128/256 x 1/2 blocks per workgroup), keeps the
+    fastest, records every candidate in the cache, and a second batch reuses
+    the cached choices without timing."""
     Batch, _ = gpu
-    S = 30
+    S = 240  # the tuner advances 200 substeps into the press before it times
     contacts = [W.batch_contact(seed, steps=S) for seed in (7, 8, 9)]
+    neo = dict(W.batch_contact(7, steps=S))
+    neo["cfg"] = dict(neo["cfg"], model=W.NEOHOOKEAN)
+    contacts.append(neo)  # same size class as seed 7, other material model: its own entry
     path = str(tmp_path / "tune.json")
     a = Batch(contacts, S, tune_cache=path, tune=True)
     ta = a.tuning()
     data = json.load(open(path))
-    classes = {int(math.floor(math.log2(W.lattice_count(c["cfg"])))) for c in contacts}
-    assert {e["log2n"] for e in data["entries"]} == classes
+    classes = {(c["cfg"]["model"], int(math.floor(math.log2(W.lattice_count(c["cfg"]))))) for c in contacts}
+    assert {(e["model"], e["log2n"]) for e in data["entries"]} == classes
     for e in data["entries"]:
-        assert e["tile"] in (4, 8) and e["wg"] in (128, 256) and e["us_per_substep"] > 0
+        assert e["precision"] == "f32"
+        cands = e["candidates"]
+        assert sorted(tuple(c[:3]) for c in cands) == sorted(SETTINGS)
+        assert all(c[3] > 0 for c in cands)
+        best = min(cands, key=lambda c: c[3])
+        assert (e["tile"], e["wg"], e["ipw"]) == tuple(best[:3])
+        print(f"class model {e['model']} log2n {e['log2n']}: chose B{e['tile']} wg{e['wg']} ipw{e['ipw']} "
+              f"{e['us_per_substep']:.1f} us; slowest {max(c[3] for c in cands):.1f} us", flush=True)
+    # the per-class choices stand unless the whole batch ran faster with the
+    # default everywhere
+    us_tuned, us_default = a.tuning_check()
+    print(f"whole batch: {us_tuned:.1f} us per substep tuned, {us_default:.1f} default", flush=True)
+    assert us_tuned > 0 and us_default > 0
+    for i, c in enumerate(contacts):
+        cls = (c["cfg"]["model"], int(math.floor(math.log2(W.lattice_count(c["cfg"])))))
+        e = next(e for e in data["entries"] if (e["model"], e["log2n"]) == cls)
+        want = (e["tile"], e["wg"], e["ipw"]) if us_tuned <= us_default else (8, 256, 1)
+        assert tuple(ta[i][:3]) == want
     b = Batch(contacts, S, tune_cache=path, tune=False)
-    assert [t[:2] for t in b.tuning()] == [t[:2] for t in ta]
+    assert [t[:3] for t in b.tuning()] == [
+        (e["tile"], e["wg"], e["ipw"]) for e in (next(e for e in data["entries"] if (e["model"], e["log2n"]) == (
+            c["cfg"]["model"], int(math.floor(math.log2(W.lattice_count(c["cfg"])))))) for c in contacts)]
+    assert b.tuning_check() == (0.0, 0.0)  # read from the cache, not timed
     a.run(S)
     b.run(S)
-    for i in range(3):
+    for i in range(len(contacts)):
         assert np.array_equal(to_np(a.contact(i).read_particles()[0]), to_np(b.contact(i).read_particles()[0]))
+
+
+@pytest.mark.parametrize("setting", [(4, 64, 2), (8, 64, 1), (8, 128, 2), (4, 256, 1)],
+                         ids=lambda s: f"B{s[0]}_wg{s[1]}_ipw{s[2]}")
+def test_every_tuner_setting_gives_the_same_substeps(gpu, tmp_path, setting):
+    """A setting forced through the cache runs the same substeps bit for bit
+    as the default launch of the same tile (the work per block does not
+    depend on the workgroup size or on how many blocks a workgroup takes)."""
+    Batch, _ = gpu
+    S = 60
+    contacts = [W.batch_contact(seed, steps=S) for seed in (3, 4)]
+    tile, wg, ipw = setting
+    path = str(tmp_path / "forced.json")
+    ref_path = str(tmp_path / "ref.json")
+    entries = []
+    for c in contacts:
+        cls = int(math.floor(math.log2(W.lattice_count(c["cfg"]))))
+        entries.append({"arch": "", "precision": "f32", "model": c["cfg"]["model"], "log2n": cls})
+    import torch as _t
+    arch = _t.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+    def write(p, t, w, q):
+        with open(p, "w") as f:
+            json.dump({"entries": [dict(e, arch=arch, tile=t, wg=w, ipw=q, us_per_substep=1.0, candidates=[])
+                                   for e in entries]}, f)
+
+    write(path, tile, wg, ipw)
+    write(ref_path, tile, 256, 1)
+    a = Batch(contacts, S, tune_cache=path, tune=False)
+    assert all(tuple(t[:3]) == setting for t in a.tuning())
+    b = Batch(contacts, S, tune_cache=ref_path, tune=False)
+    assert all(tuple(t[:3]) == (tile, 256, 1) for t in b.tuning())
+    a.run(S)
+    b.run(S)
+    a.sync()
+    b.sync()
+    for i in range(len(contacts)):
+        xa = to_np(a.contact(i).read_particles()[0])
+        xb = to_np(b.contact(i).read_particles()[0])
+        assert np.array_equal(xa, xb)
+        assert np.abs(to_np(a.contact(i).heightmap()) - W.top_z(contacts[i]["cfg"])).max() > 1e-6
