@@ -466,6 +466,75 @@ __device__ __forceinline__ void coulomb_contact(const double V[3], const double 
 // contact decision does not depend on the simulation precision.
 constexpr int CONTACT_STICKY = 0, CONTACT_COULOMB = 1, CONTACT_PARTICLES = 2;
 
+// Velocity of one grid node from its gathered mass and momentum mp (Eq. 6
+// with the contact of Eq. 10, floor and walls; the rules above), in cells/s;
+// a contact node adds its reaction M (V_before - V_after)/dt to f (in FP64).
+template <typename T, int CONTACT>
+__device__ __forceinline__ void node_velocity(const SimDev<T> &S, const IndenterDev<double> &I, int gx, int gy, int gz,
+                                              const T mp[4], T dt, T inv_dt, T V[3], double f[3])
+{
+    const T m = mp[0];
+    T V0 = T(0), V1 = T(0), V2 = T(0);
+    if (m > S.m_floor && gx < S.g0 && gy < S.g1 && gz < S.g2) {
+        const T im = T(1) / m;
+        V0 = mp[1] * im + dt * S.grav[0];
+        V1 = mp[2] * im + dt * S.grav[1];
+        V2 = mp[3] * im + dt * S.grav[2];
+        if (I.shape >= 0) {
+            // node relative to the indenter origin, metres, then indenter frame
+            const double r0 = ((double)gx - I.tip[0]) * I.dx, r1 = ((double)gy - I.tip[1]) * I.dx,
+                         r2 = ((double)gz - I.tip[2]) * I.dx;
+            const double px = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
+            const double py = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
+            const double pz = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
+            // particle indenter: the node is in contact where the points
+            // scattered mass; else where the shape's signed distance is <= 0
+            const double mi = CONTACT == CONTACT_PARTICLES && gx >= I.blo[0] && gx <= I.bhi[0] &&
+                                      gy >= I.blo[1] && gy <= I.bhi[1] && gz >= I.blo[2] && gz <= I.bhi[2]
+                                  ? I.MI[gx + (int64_t)S.g0 * (gy + (int64_t)S.g1 * gz)]
+                                  : 0.0;
+            // below the solid's lowest level the node is outside: the
+            // signed distance (the plate's noise above all) is skipped
+            if (CONTACT == CONTACT_PARTICLES ? mi > 0.0
+                                             : (pz >= I.zmin && indenter_phi<double>(I, px, py, pz) <= 0.0)) {
+                // rigid velocity v_c + omega x r, converted to cells/s
+                const double ir = 1.0 / I.dx;
+                const double wd[3] = {I.vc[0] + (I.om[1] * r2 - I.om[2] * r1) * ir,
+                                      I.vc[1] + (I.om[2] * r0 - I.om[0] * r2) * ir,
+                                      I.vc[2] + (I.om[0] * r1 - I.om[1] * r0) * ir};
+                T w0 = T(wd[0]), w1 = T(wd[1]), w2 = T(wd[2]);
+                double nrm[3];
+                if (CONTACT == CONTACT_COULOMB && indenter_normal(I, px, py, pz, nrm)) {
+                    const double Vd[3] = {(double)V0, (double)V1, (double)V2};
+                    double Va[3];
+                    coulomb_contact(Vd, wd, nrm, I.mu, Va);
+                    w0 = T(Va[0]); w1 = T(Va[1]); w2 = T(Va[2]);
+                }
+                if (CONTACT == CONTACT_PARTICLES) {
+                    // the points move with the rigid velocity (Eq. 10): their
+                    // momentum on the node is mi w (APIC with the rigid velocity
+                    // gradient is exact), and the node takes the velocity of
+                    // the summed momentum
+                    const double md = (double)m;
+                    w0 = T((md * (double)V0 + mi * wd[0]) / (md + mi));
+                    w1 = T((md * (double)V1 + mi * wd[1]) / (md + mi));
+                    w2 = T((md * (double)V2 + mi * wd[2]) / (md + mi));
+                }
+                const T sc = m * T(I.dx) * inv_dt;
+                f[0] += (double)(sc * (V0 - w0));
+                f[1] += (double)(sc * (V1 - w1));
+                f[2] += (double)(sc * (V2 - w2));
+                V0 = w0; V1 = w1; V2 = w2;
+            }
+        }
+        if (gz <= S.floor_node) V0 = V1 = V2 = T(0);
+        if ((gx < S.wall && V0 < T(0)) || (gx > S.g0 - 1 - S.wall && V0 > T(0))) V0 = T(0);
+        if ((gy < S.wall && V1 < T(0)) || (gy > S.g1 - 1 - S.wall && V1 > T(0))) V1 = T(0);
+        if ((gz < S.wall && V2 < T(0)) || (gz > S.g2 - 1 - S.wall && V2 > T(0))) V2 = T(0);
+    }
+    V[0] = V0; V[1] = V1; V[2] = V2;
+}
+
 template <typename T, int B, int WG, int CONTACT = CONTACT_STICKY>
 __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, const IndenterDev<double> &I, T dt)
 {
@@ -485,76 +554,19 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
 #pragma unroll
     for (int t = 0; t < 27; ++t) live27 |= nc27[t] > 0 ? 1u << t : 0u;
     if (!live27) return;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
+    double f[3] = {0.0, 0.0, 0.0};
     const T inv_dt = T(1) / dt;
     for (int l = threadIdx.x; l < B3; l += WG) {
         const int lx = l % B, ly = (l / B) % B, lz = l / (B * B);
         const int gx = bx * B + lx, gy = by * B + ly, gz = bz * B + lz;
         const int64_t addr = (int64_t)b * B3 + node_local<B>(lx, ly, lz);
-        T mp[4];
+        T mp[4], V[3];
         gather_node<T, B>(S, bx, by, bz, lx, ly, lz, mp, live27);
-        const T m = mp[0];
-        T V0 = T(0), V1 = T(0), V2 = T(0);
-        if (m > S.m_floor && gx < S.g0 && gy < S.g1 && gz < S.g2) {
-            const T im = T(1) / m;
-            V0 = mp[1] * im + dt * S.grav[0];
-            V1 = mp[2] * im + dt * S.grav[1];
-            V2 = mp[3] * im + dt * S.grav[2];
-            if (I.shape >= 0) {
-                // node relative to the indenter origin, metres, then indenter frame
-                const double r0 = ((double)gx - I.tip[0]) * I.dx, r1 = ((double)gy - I.tip[1]) * I.dx,
-                             r2 = ((double)gz - I.tip[2]) * I.dx;
-                const double px = I.R[0] * r0 + I.R[3] * r1 + I.R[6] * r2;
-                const double py = I.R[1] * r0 + I.R[4] * r1 + I.R[7] * r2;
-                const double pz = I.R[2] * r0 + I.R[5] * r1 + I.R[8] * r2;
-                // particle indenter: the node is in contact where the points
-                // scattered mass; else where the shape's signed distance is <= 0
-                const double mi = CONTACT == CONTACT_PARTICLES && gx >= I.blo[0] && gx <= I.bhi[0] &&
-                                          gy >= I.blo[1] && gy <= I.bhi[1] && gz >= I.blo[2] && gz <= I.bhi[2]
-                                      ? I.MI[gx + (int64_t)S.g0 * (gy + (int64_t)S.g1 * gz)]
-                                      : 0.0;
-                // below the solid's lowest level the node is outside: the
-                // signed distance (the plate's noise above all) is skipped
-                if (CONTACT == CONTACT_PARTICLES ? mi > 0.0
-                                                 : (pz >= I.zmin && indenter_phi<double>(I, px, py, pz) <= 0.0)) {
-                    // rigid velocity v_c + omega x r, converted to cells/s
-                    const double ir = 1.0 / I.dx;
-                    const double wd[3] = {I.vc[0] + (I.om[1] * r2 - I.om[2] * r1) * ir,
-                                          I.vc[1] + (I.om[2] * r0 - I.om[0] * r2) * ir,
-                                          I.vc[2] + (I.om[0] * r1 - I.om[1] * r0) * ir};
-                    T w0 = T(wd[0]), w1 = T(wd[1]), w2 = T(wd[2]);
-                    double nrm[3];
-                    if (CONTACT == CONTACT_COULOMB && indenter_normal(I, px, py, pz, nrm)) {
-                        const double Vd[3] = {(double)V0, (double)V1, (double)V2};
-                        double Va[3];
-                        coulomb_contact(Vd, wd, nrm, I.mu, Va);
-                        w0 = T(Va[0]); w1 = T(Va[1]); w2 = T(Va[2]);
-                    }
-                    if (CONTACT == CONTACT_PARTICLES) {
-                        // the points move with the rigid velocity (Eq. 10): their
-                        // momentum on the node is mi w (APIC with the rigid velocity
-                        // gradient is exact), and the node takes the velocity of
-                        // the summed momentum
-                        const double md = (double)m;
-                        w0 = T((md * (double)V0 + mi * wd[0]) / (md + mi));
-                        w1 = T((md * (double)V1 + mi * wd[1]) / (md + mi));
-                        w2 = T((md * (double)V2 + mi * wd[2]) / (md + mi));
-                    }
-                    const T s = m * T(I.dx) * inv_dt;
-                    fx += (double)(s * (V0 - w0));
-                    fy += (double)(s * (V1 - w1));
-                    fz += (double)(s * (V2 - w2));
-                    V0 = w0; V1 = w1; V2 = w2;
-                }
-            }
-            if (gz <= S.floor_node) V0 = V1 = V2 = T(0);
-            if ((gx < S.wall && V0 < T(0)) || (gx > S.g0 - 1 - S.wall && V0 > T(0))) V0 = T(0);
-            if ((gy < S.wall && V1 < T(0)) || (gy > S.g1 - 1 - S.wall && V1 > T(0))) V1 = T(0);
-            if ((gz < S.wall && V2 < T(0)) || (gz > S.g2 - 1 - S.wall && V2 > T(0))) V2 = T(0);
-        }
+        node_velocity<T, CONTACT>(S, I, gx, gy, gz, mp, dt, inv_dt, V, f);
         T *vv = S.V + 3 * addr;
-        vv[0] = V0; vv[1] = V1; vv[2] = V2;
+        vv[0] = V[0]; vv[1] = V[1]; vv[2] = V[2];
     }
+    double fx = f[0], fy = f[1], fz = f[2];
     if (I.shape >= 0) {
         __shared__ double red[3][WG / 64];
         fx = wave_sum(fx); fy = wave_sum(fy); fz = wave_sum(fz);
@@ -892,7 +904,7 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
                 }
                 T vn[3] = {s0[0], s0[1], s0[2]};
                 if (li2 < S.n_fixed) vn[0] = vn[1] = vn[2] = T(0);
-#pragma unroll
+    #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     S.v[r * N + p] = vn[r];
                     uu[r] += dt * vn[r];
@@ -932,6 +944,7 @@ __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
 {
     g2p_block<T, B, MODEL, kWG, SORT>(S, xcd_block(blockIdx.x, S.nblk, S.xcd_chunk), dt, stress_coef);
 }
+
 
 // ---------------------------------------------------------------- outputs
 

@@ -354,3 +354,33 @@ def test_corotated_press_trajectory(oracle_lib, gpu, precision):
     print(f"corotated {precision}: max |dx| = {err_x:.3e} m, max |dH| = {err_h:.3e} m")
     assert err_x <= 1e-5 * 24e-3
     assert err_h <= 0.1e-6
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_step_matches_the_phase_calls(gpu, precision):
+    """tacchi_step (one call per substep) and the three phase calls (P2G, grid
+    update, G2P) give the same substeps: bit for bit in FP32 (fixed-point P2G
+    sums do not depend on the order of the atomics), to FP64 rounding in FP64
+    (its P2G adds in atomic order); the contact force to rounding of its
+    per-workgroup sums."""
+    Sim, _ = gpu
+    wl = W.small_sphere_contact(seed=2)
+    poses, dt, S = wl["poses"], wl["dt"], 300
+    a = Sim(wl["cfg"], poses[0], precision=precision)
+    b = Sim(wl["cfg"], poses[0], precision=precision)
+    fa, fb = [], []
+    for k in range(1, S + 1):
+        a.step(poses[k], dt)
+        b.p2g(dt)
+        b.grid_update(poses[k], dt)
+        b.g2p(dt)
+        if k % 50 == 0:
+            fa.append(a.force())
+            fb.append(b.force())
+    xa, xb = (to_np(s.read_particles()[0]) for s in (a, b))
+    assert np.abs(fa[-1][2]) > 0
+    if precision == "f32":
+        assert np.array_equal(xa, xb)
+    else:
+        np.testing.assert_allclose(xa, xb, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(np.array(fa), np.array(fb), rtol=1e-12, atol=1e-15)
