@@ -137,8 +137,9 @@ def surrogate_leg(args):
     inf_s = (time.perf_counter() - t0) / reps
     ftr = SP.train_features(meta["train_samples"], meta["h_m"])
     prior = meta.get("heldout", {}).get("height_rmse_um_by_group")
+    stats = meta.get("heldout", {}).get("height_ms_um2_stats_by_group")
     rep = SP.serve_benchmark(net, ftr, meta["threshold"], meta["h_m"], args.queries, args.plain_sample,
-                             prior_rmse_um=prior, log=log)
+                             prior_rmse_um=prior, prior_stats=stats, log=log)
     r, p = rep["router"], rep["plain_mpm"]
     return {"metric": "tactile frames/s, surrogate + MPM fallback vs plain batched MPM",
             "frames_per_s": r["frames_per_s"], "plain_mpm_frames_per_s": p["frames_per_s"],
@@ -156,6 +157,7 @@ def surrogate_leg(args):
             "breaker_tripped_at_start": r["breaker_tripped_at_start"],
             "breaker_rerouted_in_batch": r["breaker_rerouted_in_batch"],
             "per_family": r["per_class"],
+            "router_policy": r["policy"], "router_budget": r.get("budget"),
             "inference_frames_per_s": 512 / inf_s,
             "inference_tflops": 512 * forward_flops(meta["res"]) / inf_s / 1e12,
             "plain_mpm_sample": p["queries"], "data_h_m": meta["h_m"], "train_samples": meta["train_samples"],

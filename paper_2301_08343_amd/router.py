@@ -10,14 +10,23 @@ Each query is a contact (indenter, pose, depth). Per batch of queries:
      the MPM;
   3. a seeded 2% audit sends further queries to the MPM, where the surrogate's
      height error is measured against the MPM's answer;
-  4. a circuit breaker routes every later query to the MPM once the RMSE of
-     the most recent audits exceeds the limit (5 um by default). A breaker
-     starts tripped when the held-out error measured for its queries is
-     already above the limit, and audits are applied in stream order: when
-     one trips the breaker, every later query of the batch that the
-     surrogate was going to answer under that breaker is solved by the MPM
-     as well, so no surrogate answer leaves after the breaker has seen the
-     error;
+  4. a guard decides which queries the surrogate may answer at all, from the
+     audits (applied in stream order: when the guard closes on a query's
+     indenter family, every later query of the batch that the surrogate was
+     going to answer for that family is solved by the MPM as well, so no
+     surrogate answer leaves after the audit that closed it):
+     * "breaker": a circuit breaker (per indenter family, or one for all
+       queries) routes every later query to the MPM once the RMSE of its
+       most recent audits exceeds the limit (5 um by default); a breaker
+       starts tripped when the held-out error of its queries is above it;
+     * "budget": the limit bounds the error of all served answers together.
+       Each family's mean squared height error is estimated from its
+       held-out samples and its audits, as an upper confidence bound (mean
+       plus z standard errors, z = 1.645: one-sided 95 %); families are
+       admitted in increasing order of that bound while the mean of the
+       bounds, weighted by each family's share of the queries so far, stays
+       within the limit squared. The admitted set is recomputed after every
+       audit and at every batch;
   5. the MPM answers every query sent to it; the rest keep the surrogate's.
 Latency of a query = its batch's start -> its answer ready (all queries are
 queued at time zero and batches run back to back).
@@ -65,18 +74,70 @@ def audit_draws(n, rate, seed):
     return np.array([rng.next_u64() < lim for _ in range(n)], dtype=bool)
 
 
-class Router:
-    """Surrogate answers with OOD and audit fallbacks to the MPM. The circuit
-    breaker is kept per indenter family when per_class is set (the query names
-    its indenter), else one breaker covers every query. prior_rmse_um maps a
-    breaker key to the surrogate's held-out height RMSE for its queries;
-    breakers whose prior exceeds the limit start tripped."""
+class FamilyError:
+    """Running count, sum and sum of squares of per-sample height mean
+    squared errors (um^2) of one indenter family."""
 
-    # route codes
+    def __init__(self, n=0, mean=0.0, sd=0.0):
+        self.n = int(n)
+        self.s1 = self.n * float(mean)
+        self.s2 = self.n * (float(sd) ** 2 + float(mean) ** 2)
+
+    def add(self, sq):
+        self.n += 1
+        self.s1 += sq
+        self.s2 += sq * sq
+
+    def mean(self):
+        return self.s1 / self.n if self.n else math.inf
+
+    def upper(self, z):
+        """Mean plus z standard errors of the mean; infinite without samples."""
+        if self.n == 0:
+            return math.inf
+        m = self.s1 / self.n
+        var = max(0.0, self.s2 / self.n - m * m)
+        return m + z * math.sqrt(var / self.n)
+
+
+def admit(bounds, shares, limit_sq):
+    """Families admitted under an error budget: in increasing order of their
+    error bound, the longest run whose share-weighted mean bound is at most
+    limit_sq (adding a larger bound only raises the mean, so the run is a
+    prefix of that order)."""
+    order = sorted(bounds, key=lambda f: (bounds[f], f))
+    out, w, ws = set(), 0.0, 0.0
+    for f in order:
+        if not math.isfinite(bounds[f]):
+            break
+        w1, ws1 = w + shares.get(f, 0.0) * bounds[f], ws + shares.get(f, 0.0)
+        if ws1 > 0 and w1 > limit_sq * ws1:
+            break
+        out.add(f)
+        w, ws = w1, ws1
+    return out
+
+
+class Router:
+    """Surrogate answers with OOD and audit fallbacks to the MPM.
+
+    policy "breaker": the circuit breaker is kept per indenter family when
+    per_class is set (the query names its indenter), else one breaker covers
+    every query; prior_rmse_um maps a breaker key to the surrogate's
+    held-out height RMSE for its queries, and breakers whose prior exceeds
+    the limit start tripped.
+    policy "budget": prior_stats maps each indenter family to the count,
+    mean and standard deviation of its held-out samples' height mean squared
+    error (um^2); a family without them is never admitted."""
+
+    # route codes (BREAKER: the guard was closed for the query's family when
+    # its batch started; BREAKER_IN_BATCH: an audit of the same batch closed it)
     SURROGATE, OOD, AUDIT, BREAKER, BREAKER_IN_BATCH = 0, 1, 2, 3, 4
 
     def __init__(self, net: Net, train_features, threshold, audit_rate=0.02, audit_seed=7, rmse_limit_um=5.0,
-                 window=20, per_class=True, prior_rmse_um=None):
+                 window=20, per_class=True, prior_rmse_um=None, policy="breaker", prior_stats=None, z=1.645):
+        if policy not in ("breaker", "budget"):
+            raise ValueError(f"unknown router policy {policy!r}")
         self.net = net
         self.train_features = train_features.contiguous()
         self.threshold = float(threshold)
@@ -84,8 +145,11 @@ class Router:
         self.audit_seed = audit_seed
         self.rmse_limit_um = rmse_limit_um
         self.window = window
-        self.per_class = per_class
+        self.per_class = per_class or policy == "budget"
         self.prior_rmse_um = {int(k): float(v) for k, v in (prior_rmse_um or {}).items()}
+        self.policy = policy
+        self.prior_stats = {int(k): dict(v) for k, v in (prior_stats or {}).items()}
+        self.z = z
 
     @staticmethod
     def calibrate(train_features, heldout_features, q=0.995):
@@ -97,7 +161,8 @@ class Router:
         return math.sqrt(sum(recent) / len(recent)) > self.rmse_limit_um
 
     def serve(self, contacts, batch=512, log=None):
-        """Answer every contact; returns (answers [n][res][res][3] in Y_UNIT, report dict)."""
+        """Answer every contact; returns (answers [n][res][res][3] in Y_UNIT,
+        report dict, route code per query)."""
         n = len(contacts)
         audit = audit_draws(n, self.audit_rate, self.audit_seed)
         key = np.array([c["cfg"]["shape"] if self.per_class else 0 for c in contacts])
@@ -105,8 +170,23 @@ class Router:
         lat = np.zeros(n)
         route = np.zeros(n, dtype=np.int8)
         audits_sq = {}
-        tripped = {k for k, e in self.prior_rmse_um.items() if e > self.rmse_limit_um} if self.per_class else set()
-        tripped_at_start = sorted(tripped)
+        budget = self.policy == "budget"
+        fams = sorted(set(int(k) for k in np.unique(key)) | set(self.prior_stats))
+        err = {f: FamilyError(**{k: self.prior_stats[f][k] for k in ("n", "mean", "sd")})
+               if f in self.prior_stats else FamilyError() for f in fams}
+        seen = {f: 0 for f in fams}
+
+        def admitted_now():
+            tot = sum(seen.values())
+            shares = {f: seen[f] / tot if tot else 1.0 / len(fams) for f in fams}
+            return admit({f: err[f].upper(self.z) for f in fams}, shares, self.rmse_limit_um ** 2)
+
+        if budget:
+            closed = set()
+        else:
+            closed = {k for k, e in self.prior_rmse_um.items() if e > self.rmse_limit_um} if self.per_class else set()
+        closed_at_start = None
+        admitted_log = []
         n_mpm = 0
         torch.cuda.synchronize()
         t_all = time.perf_counter()
@@ -116,7 +196,14 @@ class Router:
             kb = key[k0:k0 + m]
             rb = route[k0:k0 + m]  # view
             t0 = time.perf_counter()
-            brk = np.array([k in tripped for k in kb], dtype=bool)
+            if budget:
+                for f in kb:
+                    seen[int(f)] += 1
+                closed = set(fams) - admitted_now()
+                admitted_log.append((k0, sorted(set(fams) - closed)))
+            if closed_at_start is None:
+                closed_at_start = sorted(closed)
+            brk = np.array([k in closed for k in kb], dtype=bool)
             x = D.inputs(cs)
             pred = None
             send = brk.copy()
@@ -142,20 +229,26 @@ class Router:
                 if aud_idx:
                     ai = torch.tensor(aud_idx, device="cuda")
                     e = per_sample_rmse(pred.index_select(0, it.index_select(0, ai)), ym.index_select(0, ai), 2)
-                    # audits in stream order: a breaker that trips re-routes the
-                    # later surrogate answers of its key in this batch
+                    # audits in stream order: a guard that closes re-routes the
+                    # later surrogate answers of its family in this batch
                     for j, v in zip(aud_idx, (e * D.Y_UNIT * 1e6).cpu().tolist()):
                         kk = int(kb[idx[j]])
                         sq = audits_sq.setdefault(kk, [])
                         sq.append(v * v)
-                        if kk not in tripped and self._over_limit(sq):
-                            tripped.add(kk)
-                            late += [i for i in range(idx[j] + 1, m) if kb[i] == kk and rb[i] == self.SURROGATE]
+                        if budget:
+                            err[kk].add(v * v)
+                            newly = (set(fams) - admitted_now()) - closed
+                            admitted_log.append((k0 + int(idx[j]), sorted(set(fams) - closed - newly)))
+                        else:
+                            newly = {kk} if kk not in closed and self._over_limit(sq) else set()
+                        closed |= newly
+                        if newly:
+                            late += [i for i in range(idx[j] + 1, m) if kb[i] in newly and rb[i] == self.SURROGATE]
                 answers.index_copy_(0, it + k0, ym)
                 torch.cuda.synchronize()
                 lat[k0 + idx] = time.perf_counter() - t0
             if late:
-                late = np.array(sorted(late))
+                late = np.array(sorted(set(late)))
                 yl = D.solve([cs[i] for i in late])
                 n_mpm += len(late)
                 answers.index_copy_(0, torch.tensor(late, device="cuda") + k0, yl)
@@ -163,21 +256,21 @@ class Router:
                 torch.cuda.synchronize()
                 lat[k0 + late] = time.perf_counter() - t0
             if log:
-                log(f"router: {k0 + m}/{n} answered, {n_mpm} by MPM, tripped={sorted(tripped)}")
+                log(f"router: {k0 + m}/{n} answered, {n_mpm} by MPM, closed={sorted(closed)}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_all
         all_sq = [v for sq in audits_sq.values() for v in sq]
         audited = math.sqrt(sum(all_sq) / len(all_sq)) if all_sq else float("nan")
         rep = {
-            "queries": n, "wall_s": wall, "frames_per_s": n / wall,
+            "policy": self.policy, "queries": n, "wall_s": wall, "frames_per_s": n / wall,
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mpm_fallbacks": int(n_mpm), "ood": int((route == self.OOD).sum()),
             "audited": int((route == self.AUDIT).sum()),
             "breaker_routed": int((route == self.BREAKER).sum()),
             "breaker_rerouted_in_batch": int((route == self.BREAKER_IN_BATCH).sum()),
-            "breaker_tripped_at_start": [int(k) for k in tripped_at_start],
-            "breaker_tripped": sorted(int(k) for k in tripped),
+            "breaker_tripped_at_start": [int(k) for k in (closed_at_start or [])],
+            "breaker_tripped": sorted(int(k) for k in closed),
             "served_by_surrogate": int((route == self.SURROGATE).sum()),
             "audited_height_rmse_um": audited,
             "prior_rmse_um": {str(k): v for k, v in sorted(self.prior_rmse_um.items())},
@@ -186,10 +279,29 @@ class Router:
                                         "audits": len(audits_sq.get(int(k), [])),
                                         "audited_rmse_um": (math.sqrt(sum(audits_sq[int(k)]) / len(audits_sq[int(k)]))
                                                             if audits_sq.get(int(k)) else None),
-                                        "tripped": int(k) in tripped,
-                                        "tripped_at_start": int(k) in tripped_at_start}
+                                        "tripped": int(k) in closed,
+                                        "tripped_at_start": int(k) in (closed_at_start or [])}
                           for k in np.unique(key)},
         }
+        if budget:
+            served = [f for f in fams if f not in closed]
+            tot = sum(seen.values())
+            for f in fams:
+                pc = rep["per_class"].setdefault(str(f), {})
+                pc["error_bound_um2"] = err[f].upper(self.z)
+                pc["error_mean_um2"] = err[f].mean()
+                pc["error_samples"] = err[f].n
+            ws = sum(seen[f] for f in served)
+            rep["budget"] = {
+                "limit_um": self.rmse_limit_um, "z": self.z,
+                "admitted_at_end": served,
+                "bound_rmse_um_of_admitted": (math.sqrt(sum(seen[f] * err[f].upper(self.z) for f in served) / ws)
+                                              if ws else None),
+                "expected_rmse_um_of_admitted": (math.sqrt(sum(seen[f] * err[f].mean() for f in served) / ws)
+                                                 if ws else None),
+                "changes": [(int(i), a) for (i, a), prev in zip(admitted_log, [None] + admitted_log[:-1])
+                            if prev is None or prev[1] != a],
+                "shares": {str(f): seen[f] / tot for f in fams} if tot else {}}
         return answers, rep, route
 
 

@@ -101,14 +101,20 @@ def served_sample(n, k, seed=11):
     return [i for i in range(n) if rng.next_u64() < lim]
 
 
-def serve_benchmark(net, ftr, thr, h, queries, plain_sample, prior_rmse_um=None, log=log):
+def serve_benchmark(net, ftr, thr, h, queries, plain_sample, prior_rmse_um=None, prior_stats=None, log=log):
     """The query stream through the router, and plain batched MPM on a seeded
     sample of about `plain_sample` queries spread over the whole stream: its
     rate is the plain MPM's frames/s, and its answers measure the error of
-    the answers the router served for those queries (per family too)."""
+    the answers the router served for those queries (per family too). With
+    prior_stats (per family: count, mean and sd of the held-out height mean
+    squared error) the router runs its error-budget policy, else per-family
+    breakers started from prior_rmse_um."""
     rep = {}
     qs = D.contacts_for(range(QUERY_SEED0, QUERY_SEED0 + queries), h, full=False)
-    r = RT.Router(net, ftr, thr, prior_rmse_um=prior_rmse_um)
+    if prior_stats:
+        r = RT.Router(net, ftr, thr, policy="budget", prior_stats=prior_stats)
+    else:
+        r = RT.Router(net, ftr, thr, prior_rmse_um=prior_rmse_um)
     ans, rrep, route = r.serve(qs, log=log)
     rep["router"] = rrep
     log(f"router: {json.dumps(rrep)}")
@@ -174,6 +180,29 @@ def resolution_check(weights, n, h_full=0.1e-3, gen_batch=64, log=log):
     return rep
 
 
+def evaluate_weights(a, rep):
+    """Held-out evaluation of committed weights (--evaluate): the held-out
+    contacts are solved again (the same seeds and spacing as in training), the
+    model's errors replace the `heldout` entry of its metadata, and the query
+    stream is served with them."""
+    net, meta = load_compact(a.weights, batch=512)
+    h = meta["h_m"]
+    xte, yte = D.generate(range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout), h=h, batch=a.gen_batch, log=log)
+    rep["heldout"] = TR.evaluate(net, xte, yte, groups=[s % 5 for s in range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout)])
+    log(f"held-out: {json.dumps(rep['heldout'])}")
+    thr = meta.pop("threshold")
+    meta["heldout"] = rep["heldout"]
+    save_compact(os.path.join(a.out, "surrogate_compact.safetensors"), net, thr, meta)
+    if a.queries > 0:
+        ftr = train_features(meta["train_samples"], h)
+        rep.update(serve_benchmark(net, ftr, thr, h, a.queries, a.plain_sample,
+                                   prior_rmse_um=rep["heldout"].get("height_rmse_um_by_group"),
+                                   prior_stats=rep["heldout"].get("height_ms_um2_stats_by_group")))
+    with open(os.path.join(a.out, "report.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=16384)
@@ -190,7 +219,10 @@ def main(argv=None):
     ap.add_argument("--resolution-check", type=int, default=0, metavar="N",
                     help="only compare N held-out solves at the data spacing with 0.1 mm solves "
                          "(and the --weights model against both)")
-    ap.add_argument("--weights", default=None, help="compact weights for --resolution-check")
+    ap.add_argument("--weights", default=None, help="compact weights for --resolution-check or --evaluate")
+    ap.add_argument("--evaluate", action="store_true",
+                    help="no training: evaluate the --weights model on the held-out solves, write it again with "
+                         "those errors in its metadata (DIR/surrogate_compact.safetensors), then serve the queries")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
@@ -202,6 +234,11 @@ def main(argv=None):
         with open(os.path.join(a.out, "resolution.json"), "w") as f:
             json.dump(rep, f, indent=1)
         return 0
+
+    if a.evaluate:
+        if not a.weights:
+            ap.error("--evaluate needs --weights")
+        return evaluate_weights(a, rep)
 
     t = time.perf_counter()
     xtr, ytr = D.generate(range(a.train), h=a.h, batch=a.gen_batch, log=log)
@@ -244,7 +281,8 @@ def main(argv=None):
         serve_net.flat.copy_(net.flat)
         serve_net.repack()
         rep.update(serve_benchmark(serve_net, ftr, thr, a.h, a.queries, a.plain_sample,
-                                   prior_rmse_um=rep["heldout"].get("height_rmse_um_by_group")))
+                                   prior_rmse_um=rep["heldout"].get("height_rmse_um_by_group"),
+                                   prior_stats=rep["heldout"].get("height_ms_um2_stats_by_group")))
 
     with open(os.path.join(a.out, "report.json"), "w") as f:
         json.dump(rep, f, indent=1)

@@ -112,4 +112,11 @@ def evaluate(net: Net, x, y, groups=None):
         g = torch.as_tensor(groups)
         out["height_rmse_um_by_group"] = {
             str(int(k)): float((hz_c[g == k] ** 2).mean().sqrt()) for k in torch.unique(g)}
+        # per label: count, mean and standard deviation of the per-sample
+        # height mean squared error (um^2), what the router's error budget
+        # starts from
+        sq = hz_c.double() ** 2
+        out["height_ms_um2_stats_by_group"] = {
+            str(int(k)): {"n": int((g == k).sum()), "mean": float(sq[g == k].mean()),
+                          "sd": float(sq[g == k].std(unbiased=False))} for k in torch.unique(g)}
     return out

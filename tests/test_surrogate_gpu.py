@@ -394,7 +394,8 @@ def test_network_gradients_are_deterministic(T):
 
 
 def test_training_reduces_the_loss(T):
-    """A fixed smooth target field: 150 AdamW steps cut the MSE by 5x."""
+    """A fixed smooth target field: 150 AdamW steps cut the MSE by 10x
+    (measured 20x: 1.21e-2 -> 6.0e-4)."""
     from paper_2301_08343_amd.surrogate import Net
     net = Net(batch=8, res=32, seed=5)
     rng = np.random.default_rng(111)
@@ -413,7 +414,7 @@ def test_training_reduces_the_loss(T):
         last = net.train_step(x, y, lr=2e-3)
     last = float(last.item())
     print(f"loss {first:.4e} -> {last:.4e}")
-    assert last < 0.2 * first
+    assert last < 0.1 * first
 
 
 def test_router_features_and_per_sample_mse(T):

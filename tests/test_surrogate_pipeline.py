@@ -89,3 +89,57 @@ def test_breaker_starts_tripped_from_the_heldout_error(gpu):
     idx = np.nonzero(bad)[0]
     ym = D.solve([qs[i] for i in idx])
     assert torch.allclose(ans[torch.tensor(idx, device="cuda")], ym, rtol=0, atol=1e-4)
+
+
+def test_budget_admits_families_by_their_error_bound(gpu):
+    """Error-budget policy without audits: the families whose held-out bounds
+    fit the budget together get surrogate answers, the rest the MPM's."""
+    from paper_2301_08343_amd import dataset as D
+    from paper_2301_08343_amd import router as RT
+    from paper_2301_08343_amd.surrogate import Net
+    net = Net(batch=64, seed=1)
+    ftr = RT.features(D.inputs(D.contacts_for(range(64), 0.5e-3)))
+    qs = D.contacts_for(range(2000, 2064), 0.5e-3)
+    fam = np.array([c["cfg"]["shape"] for c in qs])
+    stats = {0: {"n": 100, "mean": 0.5, "sd": 0.5}, 1: {"n": 100, "mean": 30.0, "sd": 30.0},
+             2: {"n": 100, "mean": 0.4, "sd": 0.4}, 3: {"n": 100, "mean": 33.0, "sd": 30.0},
+             4: {"n": 100, "mean": 500.0, "sd": 400.0}}
+    r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.0, rmse_limit_um=5.0, policy="budget", prior_stats=stats)
+    ans, rep, route = r.serve(qs, batch=32)
+    shares = {f: float((fam == f).mean()) for f in range(5)}
+    want = RT.admit({f: RT.FamilyError(**stats[f]).upper(1.645) for f in range(5)}, shares, 25.0)
+    assert 4 not in want and {0, 2} <= want
+    assert rep["budget"]["admitted_at_end"] == sorted(want)
+    ok = np.isin(fam, sorted(want))
+    assert np.all(route[ok] == RT.Router.SURROGATE)
+    assert np.all(route[~ok] == RT.Router.BREAKER)
+    idx = np.nonzero(~ok)[0]
+    ym = D.solve([qs[i] for i in idx])
+    assert torch.allclose(ans[torch.tensor(idx, device="cuda")], ym, rtol=0, atol=1e-4)
+
+
+def test_budget_closes_a_family_at_its_first_bad_audit(gpu):
+    """An untrained network with priors claiming 1 um RMSE and a 1.2 um limit
+    (all families admitted at the start): each family's first audit shows an
+    error of tens of micrometres, which alone lifts the share-weighted mean
+    bound past the limit, so that family closes; no surrogate answer of a
+    family is served after its first audit."""
+    from paper_2301_08343_amd import dataset as D
+    from paper_2301_08343_amd import router as RT
+    from paper_2301_08343_amd.surrogate import Net
+    net = Net(batch=64, seed=1)
+    ftr = RT.features(D.inputs(D.contacts_for(range(64), 0.5e-3)))
+    qs = D.contacts_for(range(1000, 1096), 0.5e-3)
+    fam = np.array([c["cfg"]["shape"] for c in qs])
+    stats = {f: {"n": 2, "mean": 1.0, "sd": 0.0} for f in range(5)}
+    r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.5, rmse_limit_um=1.2, policy="budget", prior_stats=stats)
+    ans, rep, route = r.serve(qs, batch=32)
+    assert rep["breaker_tripped_at_start"] == []
+    for f in range(5):
+        aud = np.nonzero((fam == f) & (route == RT.Router.AUDIT))[0]
+        if len(aud):
+            later = np.arange(len(qs)) > aud[0]
+            assert not np.any(route[later & (fam == f)] == RT.Router.SURROGATE), f
+            assert rep["per_class"][str(f)]["tripped"]
+    assert rep["breaker_rerouted_in_batch"] + rep["breaker_routed"] > 0
+    assert rep["mpm_fallbacks"] == rep["ood"] + rep["audited"] + rep["breaker_routed"] + rep["breaker_rerouted_in_batch"]
