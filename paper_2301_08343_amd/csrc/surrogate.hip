@@ -103,6 +103,54 @@ struct ConvArgs {
     float *out32;
 };
 
+// Epilogue of both convolution kernels: lane holds acc[i][j][v] = out[pixel
+// pix0 + 16 j + r16][channel co0 + 16 i + 4 (lane/16) + v].
+template <int WCO, int WPX, int EPI>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs &a, const f32x4 (&acc)[WCO][WPX], int pix0, int co0,
+                                              const bool (&pv)[WPX], int lane)
+{
+    const int r16 = lane & 15;
+#pragma unroll
+    for (int j = 0; j < WPX; ++j) {
+        if (!pv[j]) continue;
+        const int64_t p = pix0 + j * 16 + r16;
+#pragma unroll
+        for (int i = 0; i < WCO; ++i) {
+            const int cb = co0 + i * 16 + (lane >> 4) * 4;
+            if (EPI == TSG_EPI_F32) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (cb + v < a.cout) a.out32[p * a.cout + cb + v] = acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f);
+                continue;
+            }
+            if (cb >= a.cout) continue;
+            uint16_t o[4];
+            if (EPI == TSG_EPI_BIAS_GELU) {
+                uint16_t zz[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float s = acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f);
+                    zz[v] = f2bf(s);
+                    o[v] = f2bf(gelu(s));
+                }
+                *(uint2 *)(a.z + p * a.z_ld + a.z_off + cb) =
+                    uint2{(uint32_t)zz[0] | ((uint32_t)zz[1] << 16), (uint32_t)zz[2] | ((uint32_t)zz[3] << 16)};
+            } else if (EPI == TSG_EPI_DGELU) {
+                const uint2 zr = *(const uint2 *)(a.z + p * a.z_ld + a.z_off + cb);
+                const uint16_t zz[4] = {(uint16_t)(zr.x & 0xffffu), (uint16_t)(zr.x >> 16), (uint16_t)(zr.y & 0xffffu),
+                                        (uint16_t)(zr.y >> 16)};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = f2bf(acc[i][j][v] * dgelu(bf2f(zz[v])));
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = f2bf(acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f));
+            }
+            *(uint2 *)(a.out + p * a.out_ld + a.out_off + cb) =
+                uint2{(uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16)};
+        }
+    }
+}
+
 // One wave computes (WCO*16) output channels x (WPX*16) pixels; 4 waves per
 // workgroup along the pixels.
 template <int WCO, int WPX, int TAPS, int EPI>
@@ -155,46 +203,7 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a)
             for (int j = 0; j < WPX; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    // lane holds acc[i][j][v] = out[pixel pix0 + 16 j + r16][channel co0 + 16 i + 4 (lane/16) + v]
-#pragma unroll
-    for (int j = 0; j < WPX; ++j) {
-        if (!pv[j]) continue;
-        const int64_t p = pix0 + j * 16 + r16;
-#pragma unroll
-        for (int i = 0; i < WCO; ++i) {
-            const int cb = co0 + i * 16 + (lane >> 4) * 4;
-            if (EPI == TSG_EPI_F32) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (cb + v < a.cout) a.out32[p * a.cout + cb + v] = acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f);
-                continue;
-            }
-            if (cb >= a.cout) continue;
-            uint16_t o[4];
-            if (EPI == TSG_EPI_BIAS_GELU) {
-                uint16_t zz[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float s = acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f);
-                    zz[v] = f2bf(s);
-                    o[v] = f2bf(gelu(s));
-                }
-                *(uint2 *)(a.z + p * a.z_ld + a.z_off + cb) =
-                    uint2{(uint32_t)zz[0] | ((uint32_t)zz[1] << 16), (uint32_t)zz[2] | ((uint32_t)zz[3] << 16)};
-            } else if (EPI == TSG_EPI_DGELU) {
-                const uint2 zr = *(const uint2 *)(a.z + p * a.z_ld + a.z_off + cb);
-                const uint16_t zz[4] = {(uint16_t)(zr.x & 0xffffu), (uint16_t)(zr.x >> 16), (uint16_t)(zr.y & 0xffffu),
-                                        (uint16_t)(zr.y >> 16)};
-#pragma unroll
-                for (int v = 0; v < 4; ++v) o[v] = f2bf(acc[i][j][v] * dgelu(bf2f(zz[v])));
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) o[v] = f2bf(acc[i][j][v] + (a.bias ? a.bias[cb + v] : 0.0f));
-            }
-            *(uint2 *)(a.out + p * a.out_ld + a.out_off + cb) =
-                uint2{(uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16)};
-        }
-    }
+    conv_epilogue<WCO, WPX, EPI>(a, acc, pix0, co0, pv, lane);
 }
 
 template <int WCO, int TAPS>
@@ -213,6 +222,239 @@ tsg_status launch_conv_epi(const ConvArgs &a, int epi, hipStream_t st)
     }
     TSG_LAUNCHED();
     return 0;
+}
+
+// 3x3 convolutions from an LDS copy of their input and weights. A tile is
+// 256 consecutive output pixels, i.e. R = 256 / w whole image rows (w a power
+// of two, 4..64), times 32 output channels; waves and lanes take a tile's
+// pixels as in k_conv (wave q: pixels 64 q .. 64 q + 63). Per chunk of 32
+// input channels a workgroup stages the global rows row0 - 1 .. row0 + R
+// with a zero column on either side, and the chunk's weights of all nine
+// taps; every MFMA operand then comes from LDS, so the input is read from
+// memory about (R + 2) / R times instead of nine times and no tap waits on a
+// global load. A staged row that belongs to another image (or lies past the
+// batch) is never used: a tap whose row leaves the output pixel's image
+// reads zero instead. A staged pixel and a staged weight row take 40 bf16
+// (32 + 8): 16 consecutive pixels or rows then start 20 banks apart, and a
+// fragment's 16 lanes read 64 distinct banks.
+constexpr int kConvCC = 32, kConvCP = 40, kConvCo = 32;
+constexpr int kConvWVec = 9 * kConvCo * 4;      // 16-byte weight vectors per chunk
+constexpr int kConvXVecMax = 66 * 6 * 4;        // input vectors per chunk, largest (w = 4 or 64)
+
+__host__ __device__ constexpr int conv_lds_weights() { return 9 * kConvCo * kConvCP; }
+
+// A lane's four pixels of tile `tile`: LDS offset of the pixel's centre tap
+// (plus its K group), the pixel's row in its image, and whether it exists.
+__device__ __forceinline__ void conv_tile_pixels(const ConvArgs &a, int tile, int lgw, int wave, int lane,
+                                                 int (&sb)[4], int (&yy)[4], bool (&pv)[4])
+{
+    const int R = 256 >> lgw, W2 = a.w + 2, nrows = a.n * a.h;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int lp = wave * 64 + j * 16 + (lane & 15);
+        const int lr = lp >> lgw, lc = lp & (a.w - 1), g = tile * R + lr;
+        pv[j] = g < nrows;
+        yy[j] = pv[j] ? g % a.h : 0;
+        sb[j] = ((lr + 1) * W2 + lc + 1) * kConvCP + (lane >> 4) * 8;
+    }
+}
+
+// The nine taps of one staged chunk: acc += W x im2col, operands from LDS.
+__device__ __forceinline__ void conv_tile_taps(const uint16_t *wst, const uint16_t *xst, int W2, int h, int lane,
+                                               const int (&sb)[4], const int (&yy)[4], const bool (&pv)[4],
+                                               f32x4 (&acc)[2][4])
+{
+    const int r16 = lane & 15, kg = (lane >> 4) * 8;
+#pragma unroll 3
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dh = tap / 3 - 1, dw = tap - (tap / 3) * 3 - 1;
+        const int soff = (dh * W2 + dw) * kConvCP;
+        bf16x8 av[2], bv[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            av[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)(wst + (tap * kConvCo + i * 16 + r16) * kConvCP + kg));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bv[j] = pv[j] && (unsigned)(yy[j] + dh) < (unsigned)h
+                        ? __builtin_bit_cast(bf16x8, *(const uint4 *)(xst + sb[j] + soff))
+                        : zero8();
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Staging vector t of a chunk: the weight vector (tap, co, v) for t < kConvWVec,
+// else input vector (staged pixel pc, v). Returns the LDS destination and,
+// through src, the global element offset (-1: stays zero) for tile row0 and
+// channel offset c0.
+__device__ __forceinline__ int conv_stage_vector(const ConvArgs &a, int t, int total, int row0, int c0, int co0,
+                                                 int64_t &src)
+{
+    const int W2 = a.w + 2, nrows = a.n * a.h;
+    src = -1;
+    if (t < kConvWVec) {
+        const int v = t & 3, rc = t >> 2, tap = rc >> 5, co = co0 + (rc & 31);
+        if (co < a.cout) src = (int64_t)co * a.kp + tap * a.cin_p + c0 + v * 8;
+        return rc * kConvCP + v * 8;
+    }
+    if (t >= total) return -1;
+    const int u = t - kConvWVec, v = u & 3, pc = u >> 2;
+    const int sr = pc / W2, x = pc - sr * W2 - 1, g = row0 - 1 + sr;
+    if (g >= 0 && g < nrows && (unsigned)x < (unsigned)a.w)
+        src = ((int64_t)g * a.w + x) * a.in_ld + a.in_off + c0 + v * 8;
+    return conv_lds_weights() + pc * kConvCP + v * 8;
+}
+
+// One tile per workgroup, any number of chunks: each chunk is staged (eight
+// vectors per thread loaded before any is stored: one memory round trip per
+// 2048 vectors), then computed.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int lgw)
+{
+    constexpr int NB = 8;
+    extern __shared__ __align__(16) uint16_t stage[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int R = 256 >> lgw, W2 = a.w + 2;
+    const int tile = blockIdx.x, co0 = blockIdx.y * kConvCo;
+    const int total = kConvWVec + ((R + 2) * W2 << 2);
+    int sb[4], yy[4];
+    bool pv[4];
+    conv_tile_pixels(a, tile, lgw, wave, lane, sb, yy, pv);
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int c0 = 0; c0 < a.cin_p; c0 += kConvCC) {
+        if (c0) __syncthreads();
+        for (int t0 = threadIdx.x; t0 < total; t0 += NB * 256) {
+            uint4 val[NB];
+            int dst[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                int64_t src;
+                dst[q] = conv_stage_vector(a, t0 + q * 256, total, tile * R, c0, co0, src);
+                val[q] = uint4{0u, 0u, 0u, 0u};
+                if (src >= 0) val[q] = *(const uint4 *)((t0 + q * 256 < kConvWVec ? a.wp : a.in) + src);
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (dst[q] >= 0) *(uint4 *)(stage + dst[q]) = val[q];
+        }
+        __syncthreads();
+        conv_tile_taps(stage, stage + conv_lds_weights(), W2, a.h, lane, sb, yy, pv, acc);
+    }
+    conv_epilogue<2, 4, EPI>(a, acc, tile * 256 + wave * 64, co0, pv, lane);
+}
+
+// One chunk of 32 input channels, a contiguous run of tiles per workgroup
+// (the halo rows two neighbouring tiles share stay in its L2): the weights
+// are staged once, and the next tile's input is loaded into registers while
+// the current tile is computed.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_conv_lds1(ConvArgs a, int lgw, int tiles_per_wg)
+{
+    constexpr int NV = (kConvXVecMax + 255) / 256;
+    extern __shared__ __align__(16) uint16_t stage[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int R = 256 >> lgw, W2 = a.w + 2;
+    const int ntiles = (a.n * a.h + R - 1) / R;
+    const int t_begin = blockIdx.x * tiles_per_wg, t_end = min(ntiles, t_begin + tiles_per_wg);
+    if (t_begin >= t_end) return;
+    const int co0 = blockIdx.y * kConvCo;
+    const int total = kConvWVec + ((R + 2) * W2 << 2);
+    // the weights, once
+    for (int t = threadIdx.x; t < kConvWVec; t += 256) {
+        int64_t src;
+        const int d = conv_stage_vector(a, t, total, 0, 0, co0, src);
+        *(uint4 *)(stage + d) = src >= 0 ? *(const uint4 *)(a.wp + src) : uint4{0u, 0u, 0u, 0u};
+    }
+    uint4 pre[NV];
+    int dst[NV];
+    auto fetch = [&](int tile) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            int64_t src;
+            dst[q] = conv_stage_vector(a, kConvWVec + threadIdx.x + q * 256, total, tile * R, 0, co0, src);
+            pre[q] = src >= 0 ? *(const uint4 *)(a.in + src) : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    fetch(t_begin);
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        int sb[4], yy[4];
+        bool pv[4];
+        conv_tile_pixels(a, tile, lgw, wave, lane, sb, yy, pv);
+        __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (dst[q] >= 0) *(uint4 *)(stage + dst[q]) = pre[q];
+        __syncthreads();
+        if (tile + 1 < t_end) fetch(tile + 1);
+        f32x4 acc[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        conv_tile_taps(stage, stage + conv_lds_weights(), W2, a.h, lane, sb, yy, pv, acc);
+        conv_epilogue<2, 4, EPI>(a, acc, tile * 256 + wave * 64, co0, pv, lane);
+    }
+}
+
+// bytes of the staged weights and input of k_conv_lds / k_conv_lds1
+size_t conv_lds_bytes(int w)
+{
+    const int R = 256 / w;
+    return (size_t)(conv_lds_weights() + (R + 2) * (w + 2) * kConvCP) * 2;
+}
+
+// Workgroups of a k_conv_lds1 launch: about kConvWGs in all (two per CU at
+// its LDS size, two rounds). Measured on the 64 x 64 layers with 32 input
+// channels, runs of four tiles per workgroup gain 12 % over one tile per
+// workgroup; for layers with more input channels the register prefetch of
+// the next chunk cost more than it hid (20 % on the 32 x 32 layers), so
+// those run k_conv_lds, one tile per workgroup.
+constexpr int kConvWGs = 1024;
+
+tsg_status launch_conv_lds(const ConvArgs &a, int epi, hipStream_t st)
+{
+    int lgw = 0;
+    while ((1 << lgw) < a.w) ++lgw;
+    const int R = 256 >> lgw;
+    const int ntiles = (a.n * a.h + R - 1) / R, cot = (a.cout + kConvCo - 1) / kConvCo;
+    const size_t lds = conv_lds_bytes(a.w);
+    if (a.cin_p == kConvCC) {
+        const int want = std::max(1, kConvWGs / cot);
+        const int per = (ntiles + want - 1) / want;
+        const dim3 grid((ntiles + per - 1) / per, cot);
+        switch (epi) {
+        case TSG_EPI_BIAS: hipLaunchKernelGGL((k_conv_lds1<TSG_EPI_BIAS>), grid, dim3(256), lds, st, a, lgw, per); break;
+        case TSG_EPI_BIAS_GELU:
+            hipLaunchKernelGGL((k_conv_lds1<TSG_EPI_BIAS_GELU>), grid, dim3(256), lds, st, a, lgw, per);
+            break;
+        default: hipLaunchKernelGGL((k_conv_lds1<TSG_EPI_DGELU>), grid, dim3(256), lds, st, a, lgw, per); break;
+        }
+    } else {
+        const dim3 grid(ntiles, cot);
+        switch (epi) {
+        case TSG_EPI_BIAS: hipLaunchKernelGGL((k_conv_lds<TSG_EPI_BIAS>), grid, dim3(256), lds, st, a, lgw); break;
+        case TSG_EPI_BIAS_GELU:
+            hipLaunchKernelGGL((k_conv_lds<TSG_EPI_BIAS_GELU>), grid, dim3(256), lds, st, a, lgw);
+            break;
+        default: hipLaunchKernelGGL((k_conv_lds<TSG_EPI_DGELU>), grid, dim3(256), lds, st, a, lgw); break;
+        }
+    }
+    TSG_LAUNCHED();
+    return 0;
+}
+
+// k_conv_lds applies to 3x3 layers with BF16 outputs whose input channels
+// come in multiples of 32 and whose rows are 4..64 pixels, a power of two
+bool conv_lds_fits(int taps, int epi, int cin_p, int w)
+{
+    return taps == 9 && epi != TSG_EPI_F32 && cin_p % 32 == 0 && w >= 4 && w <= 64 && (w & (w - 1)) == 0;
 }
 
 // ------------------------------------------------------------------ weight gradient
@@ -933,6 +1175,7 @@ tsg_status tsg_conv(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t
                zbuf, z_ld, z_off, out32};
     hipStream_t st = (hipStream_t)stream;
     const int wco = cout >= 64 ? 4 : (cout >= 32 ? 2 : 1);
+    if (conv_lds_fits(taps, epi, cin_p, w)) return launch_conv_lds(a, epi, st);
     if (taps == 9) {
         if (wco == 4) return launch_conv_epi<4, 9>(a, epi, st);
         if (wco == 2) return launch_conv_epi<2, 9>(a, epi, st);

@@ -75,6 +75,13 @@ CONV_CASES = [
     (1, 13, 11, 40, 40, 56, 16, 20, 9),  # channel slice of a wider buffer, ragged cout
     (3, 8, 8, 64, 64, 64, 0, 128, 9),    # 64-channel tiles of the deep layers
     (2, 5, 6, 32, 32, 32, 0, 48, 1),     # 1x1
+    # the LDS-staged kernel (rows of 4..64 pixels, channels in 32s): images
+    # shorter than a workgroup's 256 pixels and a partial last workgroup,
+    # 32-channel chunks of a channel slice, a ragged 32-channel output tile
+    (3, 5, 8, 32, 32, 48, 8, 48, 9),
+    (1, 6, 64, 64, 64, 64, 0, 32, 9),     # 64-pixel rows, 4 rows per workgroup
+    (2, 7, 4, 96, 96, 96, 0, 64, 9),      # 4-pixel rows, three 32-channel chunks
+    (1, 9, 32, 64, 64, 128, 64, 32, 9),   # 32-pixel rows, second half of a 128-channel buffer
 ]
 
 
@@ -114,7 +121,8 @@ def test_conv_forward(T, case, epi):
         assert np.all(np.abs(got - g) <= U_BF * (np.abs(g) + LIP * acc_tol) + LIP * acc_tol + 1e-6 * (1 + np.abs(g)))
 
 
-@pytest.mark.parametrize("case", [(2, 9, 7, 32, 32, 9), (1, 16, 16, 64, 128, 9), (2, 6, 5, 48, 24, 9)])
+@pytest.mark.parametrize("case", [(2, 9, 7, 32, 32, 9), (1, 16, 16, 64, 128, 9), (2, 6, 5, 48, 24, 9),
+                                  (2, 8, 32, 32, 64, 9)])
 @pytest.mark.parametrize("fuse_gelu", [False, True])
 def test_conv_input_gradient(T, case, fuse_gelu):
     """Transposed, flipped packs give the input gradient; DGELU multiplies by
