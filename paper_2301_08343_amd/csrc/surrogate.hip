@@ -286,78 +286,59 @@ __device__ __forceinline__ void conv_tile_taps(const uint16_t *wst, const uint16
     }
 }
 
-// Staging vector t of a chunk: the weight vector (tap, co, v) for t < kConvWVec,
-// else input vector (staged pixel pc, v). Returns the LDS destination and,
-// through src, the global element offset (-1: stays zero) for tile row0 and
-// channel offset c0.
-__device__ __forceinline__ int conv_stage_vector(const ConvArgs &a, int t, int total, int row0, int c0, int co0,
-                                                 int64_t &src)
+// A thread's share of staging one chunk: weight vectors t and input vectors
+// u = thread + 256 q, with their LDS destinations (-1: none) and global
+// element offsets (-1: stays zero) that depend on neither the tile nor the
+// chunk; worked out once per workgroup (the input's staged row and column
+// take a division, the per-chunk loads none). An input offset counts from
+// the start of global row row0 - 1 of the tile; weight vector t is (tap, co,
+// v) = (t / 128, t / 4 % 32, t % 4), input vector u is (staged pixel u / 4,
+// v = u % 4).
+constexpr int kConvNW = (kConvWVec + 255) / 256, kConvNX = (kConvXVecMax + 255) / 256;
+
+struct ConvStagePlan {
+    int wdst[kConvNW], wsrc[kConvNW];
+    int xdst[kConvNX], xrow[kConvNX], xsrc[kConvNX];
+};
+
+__device__ __forceinline__ void conv_stage_plan(const ConvArgs &a, int R, int co0, ConvStagePlan &P)
 {
-    const int W2 = a.w + 2, nrows = a.n * a.h;
-    src = -1;
-    if (t < kConvWVec) {
+    const int W2 = a.w + 2, nin = (R + 2) * W2 * 4;
+#pragma unroll
+    for (int q = 0; q < kConvNW; ++q) {
+        const int t = threadIdx.x + q * 256;
         const int v = t & 3, rc = t >> 2, tap = rc >> 5, co = co0 + (rc & 31);
-        if (co < a.cout) src = (int64_t)co * a.kp + tap * a.cin_p + c0 + v * 8;
-        return rc * kConvCP + v * 8;
+        P.wdst[q] = t < kConvWVec ? rc * kConvCP + v * 8 : -1;
+        P.wsrc[q] = t < kConvWVec && co < a.cout ? co * a.kp + tap * a.cin_p + v * 8 : -1;
     }
-    if (t >= total) return -1;
-    const int u = t - kConvWVec, v = u & 3, pc = u >> 2;
-    const int sr = pc / W2, x = pc - sr * W2 - 1, g = row0 - 1 + sr;
-    if (g >= 0 && g < nrows && (unsigned)x < (unsigned)a.w)
-        src = ((int64_t)g * a.w + x) * a.in_ld + a.in_off + c0 + v * 8;
-    return conv_lds_weights() + pc * kConvCP + v * 8;
+#pragma unroll
+    for (int q = 0; q < kConvNX; ++q) {
+        const int u = threadIdx.x + q * 256;
+        const int v = u & 3, pc = u >> 2, sr = pc / W2, x = pc - sr * W2 - 1;
+        P.xdst[q] = u < nin ? conv_lds_weights() + pc * kConvCP + v * 8 : -1;
+        P.xrow[q] = sr;
+        P.xsrc[q] = u < nin && (unsigned)x < (unsigned)a.w ? (sr * a.w + x) * a.in_ld + a.in_off + v * 8 : -1;
+    }
 }
 
-// One tile per workgroup, any number of chunks: each chunk is staged (eight
-// vectors per thread loaded before any is stored: one memory round trip per
-// 2048 vectors), then computed.
-template <int EPI>
-__global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int lgw)
+// Input vector q of the chunk at channel offset c0 of the tile whose first
+// row is row0 (zero outside the batch's rows and the image's columns).
+__device__ __forceinline__ uint4 conv_stage_load_x(const ConvArgs &a, const ConvStagePlan &P, int q, int row0, int c0)
 {
-    constexpr int NB = 8;
-    extern __shared__ __align__(16) uint16_t stage[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int R = 256 >> lgw, W2 = a.w + 2;
-    const int tile = blockIdx.x, co0 = blockIdx.y * kConvCo;
-    const int total = kConvWVec + ((R + 2) * W2 << 2);
-    int sb[4], yy[4];
-    bool pv[4];
-    conv_tile_pixels(a, tile, lgw, wave, lane, sb, yy, pv);
-    f32x4 acc[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int c0 = 0; c0 < a.cin_p; c0 += kConvCC) {
-        if (c0) __syncthreads();
-        for (int t0 = threadIdx.x; t0 < total; t0 += NB * 256) {
-            uint4 val[NB];
-            int dst[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                int64_t src;
-                dst[q] = conv_stage_vector(a, t0 + q * 256, total, tile * R, c0, co0, src);
-                val[q] = uint4{0u, 0u, 0u, 0u};
-                if (src >= 0) val[q] = *(const uint4 *)((t0 + q * 256 < kConvWVec ? a.wp : a.in) + src);
-            }
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (dst[q] >= 0) *(uint4 *)(stage + dst[q]) = val[q];
-        }
-        __syncthreads();
-        conv_tile_taps(stage, stage + conv_lds_weights(), W2, a.h, lane, sb, yy, pv, acc);
-    }
-    conv_epilogue<2, 4, EPI>(a, acc, tile * 256 + wave * 64, co0, pv, lane);
+    const int g = row0 - 1 + P.xrow[q];
+    if (P.xsrc[q] < 0 || g < 0 || g >= a.n * a.h) return uint4{0u, 0u, 0u, 0u};
+    return *(const uint4 *)(a.in + (int64_t)(row0 - 1) * a.w * a.in_ld + P.xsrc[q] + c0);
 }
 
-// One chunk of 32 input channels, a contiguous run of tiles per workgroup
-// (the halo rows two neighbouring tiles share stay in its L2): the weights
-// are staged once, and the next tile's input is loaded into registers while
-// the current tile is computed.
+// A workgroup walks a contiguous run of tiles (the halo rows two
+// neighbouring tiles share stay in its L2) and, per tile, the chunks of 32
+// input channels. The weight and input vectors of the next (tile, chunk) are
+// loaded into registers while the current one is computed, so a chunk waits
+// for memory only when its compute is shorter than a round trip; with one
+// chunk per tile the weights are staged once.
 template <int EPI>
-__global__ void __launch_bounds__(256) k_conv_lds1(ConvArgs a, int lgw, int tiles_per_wg)
+__global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int lgw, int tiles_per_wg)
 {
-    constexpr int NV = (kConvXVecMax + 255) / 256;
     extern __shared__ __align__(16) uint16_t stage[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int R = 256 >> lgw, W2 = a.w + 2;
@@ -365,57 +346,60 @@ __global__ void __launch_bounds__(256) k_conv_lds1(ConvArgs a, int lgw, int tile
     const int t_begin = blockIdx.x * tiles_per_wg, t_end = min(ntiles, t_begin + tiles_per_wg);
     if (t_begin >= t_end) return;
     const int co0 = blockIdx.y * kConvCo;
-    const int total = kConvWVec + ((R + 2) * W2 << 2);
-    // the weights, once
-    for (int t = threadIdx.x; t < kConvWVec; t += 256) {
-        int64_t src;
-        const int d = conv_stage_vector(a, t, total, 0, 0, co0, src);
-        *(uint4 *)(stage + d) = src >= 0 ? *(const uint4 *)(a.wp + src) : uint4{0u, 0u, 0u, 0u};
-    }
-    uint4 pre[NV];
-    int dst[NV];
-    auto fetch = [&](int tile) {
+    const int nch = a.cin_p / kConvCC;
+    ConvStagePlan P;
+    conv_stage_plan(a, R, co0, P);
+    uint4 wv[kConvNW], xv[kConvNX];
+    auto fetch = [&](int tile, int c0, bool with_w) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            int64_t src;
-            dst[q] = conv_stage_vector(a, kConvWVec + threadIdx.x + q * 256, total, tile * R, 0, co0, src);
-            pre[q] = src >= 0 ? *(const uint4 *)(a.in + src) : uint4{0u, 0u, 0u, 0u};
-        }
+        for (int q = 0; q < kConvNW; ++q)
+            wv[q] = with_w && P.wsrc[q] >= 0 ? *(const uint4 *)(a.wp + P.wsrc[q] + c0) : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < kConvNX; ++q) xv[q] = conv_stage_load_x(a, P, q, tile * R, c0);
     };
-    fetch(t_begin);
+    fetch(t_begin, 0, true);
+    bool with_w = true;
     for (int tile = t_begin; tile < t_end; ++tile) {
         int sb[4], yy[4];
         bool pv[4];
         conv_tile_pixels(a, tile, lgw, wave, lane, sb, yy, pv);
-        __syncthreads();  // the previous tile's LDS reads are done
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-            if (dst[q] >= 0) *(uint4 *)(stage + dst[q]) = pre[q];
-        __syncthreads();
-        if (tile + 1 < t_end) fetch(tile + 1);
         f32x4 acc[2][4];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        conv_tile_taps(stage, stage + conv_lds_weights(), W2, a.h, lane, sb, yy, pv, acc);
+        for (int ch = 0; ch < nch; ++ch) {
+            __syncthreads();  // the previous chunk's LDS reads are done
+            if (with_w) {
+#pragma unroll
+                for (int q = 0; q < kConvNW; ++q)
+                    if (P.wdst[q] >= 0) *(uint4 *)(stage + P.wdst[q]) = wv[q];
+            }
+#pragma unroll
+            for (int q = 0; q < kConvNX; ++q)
+                if (P.xdst[q] >= 0) *(uint4 *)(stage + P.xdst[q]) = xv[q];
+            __syncthreads();
+            with_w = nch > 1;
+            const int nt = ch + 1 < nch ? tile : tile + 1, nc = ch + 1 < nch ? ch + 1 : 0;
+            if (nt < t_end) fetch(nt, nc * kConvCC, with_w);
+            conv_tile_taps(stage, stage + conv_lds_weights(), W2, a.h, lane, sb, yy, pv, acc);
+        }
         conv_epilogue<2, 4, EPI>(a, acc, tile * 256 + wave * 64, co0, pv, lane);
     }
 }
 
-// bytes of the staged weights and input of k_conv_lds / k_conv_lds1
+// bytes of the staged weights and input of k_conv_lds
 size_t conv_lds_bytes(int w)
 {
     const int R = 256 / w;
     return (size_t)(conv_lds_weights() + (R + 2) * (w + 2) * kConvCP) * 2;
 }
 
-// Workgroups of a k_conv_lds1 launch: about kConvWGs in all (two per CU at
-// its LDS size, two rounds). Measured on the 64 x 64 layers with 32 input
-// channels, runs of four tiles per workgroup gain 12 % over one tile per
-// workgroup; for layers with more input channels the register prefetch of
-// the next chunk cost more than it hid (20 % on the 32 x 32 layers), so
-// those run k_conv_lds, one tile per workgroup.
+// Tiles per workgroup of a k_conv_lds launch: runs sized for about kConvWGs
+// workgroups in all (two per CU at the LDS size, two rounds). Measured
+// against one tile per workgroup: runs of four gain the 64 x 64 layers 10-15 %
+// and the 32 x 32 layers 10 %; layers with fewer tiles than that keep one
+// tile per workgroup (runs of four there cost 2-3x: too few workgroups).
 constexpr int kConvWGs = 1024;
 
 tsg_status launch_conv_lds(const ConvArgs &a, int epi, hipStream_t st)
@@ -425,26 +409,15 @@ tsg_status launch_conv_lds(const ConvArgs &a, int epi, hipStream_t st)
     const int R = 256 >> lgw;
     const int ntiles = (a.n * a.h + R - 1) / R, cot = (a.cout + kConvCo - 1) / kConvCo;
     const size_t lds = conv_lds_bytes(a.w);
-    if (a.cin_p == kConvCC) {
-        const int want = std::max(1, kConvWGs / cot);
-        const int per = (ntiles + want - 1) / want;
-        const dim3 grid((ntiles + per - 1) / per, cot);
-        switch (epi) {
-        case TSG_EPI_BIAS: hipLaunchKernelGGL((k_conv_lds1<TSG_EPI_BIAS>), grid, dim3(256), lds, st, a, lgw, per); break;
-        case TSG_EPI_BIAS_GELU:
-            hipLaunchKernelGGL((k_conv_lds1<TSG_EPI_BIAS_GELU>), grid, dim3(256), lds, st, a, lgw, per);
-            break;
-        default: hipLaunchKernelGGL((k_conv_lds1<TSG_EPI_DGELU>), grid, dim3(256), lds, st, a, lgw, per); break;
-        }
-    } else {
-        const dim3 grid(ntiles, cot);
-        switch (epi) {
-        case TSG_EPI_BIAS: hipLaunchKernelGGL((k_conv_lds<TSG_EPI_BIAS>), grid, dim3(256), lds, st, a, lgw); break;
-        case TSG_EPI_BIAS_GELU:
-            hipLaunchKernelGGL((k_conv_lds<TSG_EPI_BIAS_GELU>), grid, dim3(256), lds, st, a, lgw);
-            break;
-        default: hipLaunchKernelGGL((k_conv_lds<TSG_EPI_DGELU>), grid, dim3(256), lds, st, a, lgw); break;
-        }
+    const int want = std::max(1, kConvWGs / cot);
+    const int per = (ntiles + want - 1) / want;
+    const dim3 grid((ntiles + per - 1) / per, cot);
+    switch (epi) {
+    case TSG_EPI_BIAS: hipLaunchKernelGGL((k_conv_lds<TSG_EPI_BIAS>), grid, dim3(256), lds, st, a, lgw, per); break;
+    case TSG_EPI_BIAS_GELU:
+        hipLaunchKernelGGL((k_conv_lds<TSG_EPI_BIAS_GELU>), grid, dim3(256), lds, st, a, lgw, per);
+        break;
+    default: hipLaunchKernelGGL((k_conv_lds<TSG_EPI_DGELU>), grid, dim3(256), lds, st, a, lgw, per); break;
     }
     TSG_LAUNCHED();
     return 0;
