@@ -522,6 +522,18 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h,
 // chunks inside one image (h w % kWgChunk == 0) and 16 <= w <= 64, w % 16 == 0.
 constexpr int kW9Halo = kWgChunk + 2 * 64;
 
+// bf16 element k of a uint2 holding four
+__device__ __forceinline__ uint32_t bf_at(const uint2 &v, int k)
+{
+    return ((k < 2 ? v.x : v.y) >> ((k & 1) * 16)) & 0xffffu;
+}
+
+// Eight bf16 (element k of each of e[0..7]) as one 16-byte vector
+__device__ __forceinline__ uint4 pack8(const uint32_t (&e)[8])
+{
+    return uint4{e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16)};
+}
+
 __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h, int w, int in_ld, int in_off,
                                                 int cin_p, const uint16_t *dout, int d_ld, int d_off, int cout,
                                                 int pix_per_split, float *part, float *bpart)
@@ -539,53 +551,67 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;
-    const int lp = tid >> 3, lc = (tid & 7) * 4;
-    for (int p0 = pbeg; p0 < pend; p0 += kWgChunk) {
+    // staging item of this thread: an 8-pixel window `win` of 4 channels
+    // lc .. lc+3, transposed in registers and stored as four 16-byte rows.
+    // dout: windows 0..15 of the chunk (threads 0..127); input: windows
+    // 0..halo/8-1 of the haloed chunk, read with one pixel on either side for
+    // the copies shifted by dw = -1 and +1. The next chunk is loaded while
+    // the current one computes.
+    const int win = tid >> 3, lc = (tid & 7) * 4;
+    const bool a_item = win < kWgChunk / 8, b_item = win * 8 < halo;
+    uint2 va[8], vb[10];
+    auto load = [&](int p0) {
         const int64_t ibeg = (int64_t)(p0 / hw) * hw, iend = ibeg + hw;
-        uint2 va[kWgChunk / 32], vb[kW9Halo / 32];
 #pragma unroll
-        for (int j = 0; j < kWgChunk / 32; ++j) {
-            const int p = p0 + lp + 32 * j;
-            va[j] = uint2{0u, 0u};
-            if (p < pend && co0 + lc < cout) va[j] = *(const uint2 *)(dout + (int64_t)p * d_ld + d_off + co0 + lc);
+        for (int k = 0; k < 8; ++k) {
+            const int p = p0 + win * 8 + k;
+            va[k] = uint2{0u, 0u};
+            if (a_item && p < pend && co0 + lc < cout) va[k] = *(const uint2 *)(dout + (int64_t)p * d_ld + d_off + co0 + lc);
         }
 #pragma unroll
-        for (int j = 0; j < kW9Halo / 32; ++j) {
-            const int i = lp + 32 * j;
+        for (int k = 0; k < 10; ++k) {
+            const int i = win * 8 + k - 1;
             const int64_t r = (int64_t)p0 - w + i;
-            vb[j] = uint2{0u, 0u};
-            if (i < halo && r >= ibeg && r < iend && ci0 + lc < cin_p)
-                vb[j] = *(const uint2 *)(in + r * in_ld + in_off + ci0 + lc);
+            vb[k] = uint2{0u, 0u};
+            if (b_item && i >= 0 && i < halo && r >= ibeg && r < iend && ci0 + lc < cin_p)
+                vb[k] = *(const uint2 *)(in + r * in_ld + in_off + ci0 + lc);
         }
-        __syncthreads();
+    };
+    load(pbeg);
+    for (int p0 = pbeg; p0 < pend; p0 += kWgChunk) {
+        __syncthreads();  // the previous chunk's LDS reads are done
+        if (a_item) {
 #pragma unroll
-        for (int j = 0; j < kWgChunk / 32; ++j) {
-            const int q = lp + 32 * j;
-            sA[lc + 0][q] = (uint16_t)(va[j].x & 0xffffu);
-            sA[lc + 1][q] = (uint16_t)(va[j].x >> 16);
-            sA[lc + 2][q] = (uint16_t)(va[j].y & 0xffffu);
-            sA[lc + 3][q] = (uint16_t)(va[j].y >> 16);
+            for (int c = 0; c < 4; ++c) {
+                uint32_t e[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) e[k] = bf_at(va[k], c);
+                *(uint4 *)&sA[lc + c][win * 8] = pack8(e);
+            }
         }
+        if (b_item) {
+            // entry e of copy dw + 1 holds pixel e + dw of the same row (zero
+            // past the row's ends); an 8-entry window lies inside one row
+            // (w % 16 == 0, and the haloed chunk starts at a row start)
+            const bool row_first = (win * 8) % w == 0, row_last = (win * 8 + 8) % w == 0;
 #pragma unroll
-        for (int j = 0; j < kW9Halo / 32; ++j) {
-            const int i = lp + 32 * j;
-            if (i < halo) {
-                const uint16_t v[4] = {(uint16_t)(vb[j].x & 0xffffu), (uint16_t)(vb[j].x >> 16),
-                                       (uint16_t)(vb[j].y & 0xffffu), (uint16_t)(vb[j].y >> 16)};
-                const int ww = i % w;  // p0 - w is a row start
+            for (int c = 0; c < 4; ++c) {
+                uint32_t e0[8], e1[8], e2[8];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    sB[1][lc + k][i] = v[k];
-                    // dw = +1: entry i-1 reads this pixel; the row's last entry reads past the row
-                    if (ww >= 1) sB[2][lc + k][i - 1] = v[k];
-                    if (ww == w - 1) sB[2][lc + k][i] = 0;
-                    // dw = -1: entry i+1 reads this pixel; the row's first entry reads before the row
-                    if (ww <= w - 2) sB[0][lc + k][i + 1] = v[k];
-                    if (ww == 0) sB[0][lc + k][i] = 0;
+                for (int k = 0; k < 8; ++k) {
+                    e0[k] = bf_at(vb[k], c);
+                    e1[k] = bf_at(vb[k + 1], c);
+                    e2[k] = bf_at(vb[k + 2], c);
                 }
+                if (row_first) e0[0] = 0;
+                if (row_last) e2[7] = 0;
+                *(uint4 *)&sB[0][lc + c][win * 8] = pack8(e0);
+                *(uint4 *)&sB[1][lc + c][win * 8] = pack8(e1);
+                *(uint4 *)&sB[2][lc + c][win * 8] = pack8(e2);
             }
         }
         __syncthreads();
+        if (p0 + kWgChunk < pend) load(p0 + kWgChunk);
         const int r16 = lane & 15, kg = (lane >> 4) * 8;
 #pragma unroll
         for (int j = 0; j < kWgChunk / 32; ++j) {
