@@ -128,7 +128,7 @@ __device__ __forceinline__ bool finite3(T a, T b, T c)
 // layer and none is left with the empty border rows only (chunks that tile
 // the layer were measured 10-15 % slower than this). Blocks past the last
 // whole round of 8 chunks keep their index. A bijection of [0, n).
-__device__ __forceinline__ int xcd_block(int i, int n, int C)
+__host__ __device__ __forceinline__ int xcd_block(int i, int n, int C)
 {
     const int R = 8 * C;
     if (C <= 1 || i >= (n / R) * R) return i;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void stencil_base(const T xr[3], const T uu[3], int b
 // are stored segment region by segment region (z, then y, then x), each
 // region x-fastest, and a neighbour's share is a few contiguous runs.
 template <int B>
-__device__ __forceinline__ int node_local(int lx, int ly, int lz)
+__host__ __device__ __forceinline__ int node_local(int lx, int ly, int lz)
 {
     auto seg = [](int l) { return l <= 1 ? 0 : (l <= B - 2 ? 1 : 2); };
     auto start = [](int r) { return r == 0 ? 0 : (r == 1 ? 2 : B - 1); };
@@ -233,7 +233,7 @@ __device__ __forceinline__ int node_local(int lx, int ly, int lz)
 }
 
 template <int B>
-__device__ __forceinline__ int64_t node_addr(int nb0, int nb1, int x, int y, int z)
+__host__ __device__ __forceinline__ int64_t node_addr(int nb0, int nb1, int x, int y, int z)
 {
     constexpr int LB = Log2B<B>::v;
     int bx = x >> LB, by = y >> LB, bz = z >> LB;

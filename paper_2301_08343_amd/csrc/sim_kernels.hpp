@@ -86,22 +86,22 @@ struct TileAcc<float> {
 template <int B>
 struct TileRegions {
     static constexpr int TB = B + 3;
-    __device__ static int size(int r) { return r == 0 ? 1 : (r == 1 ? B : 2); }
-    __device__ static int start(int r) { return r == 0 ? 0 : (r == 1 ? 1 : B + 1); }
-    __device__ static int region(int t) { return t == 0 ? 0 : (t <= B ? 1 : 2); }
-    __device__ static int slot(int rx, int ux, int ry, int uy, int rz, int uz)
+    __host__ __device__ static int size(int r) { return r == 0 ? 1 : (r == 1 ? B : 2); }
+    __host__ __device__ static int start(int r) { return r == 0 ? 0 : (r == 1 ? 1 : B + 1); }
+    __host__ __device__ static int region(int t) { return t == 0 ? 0 : (t <= B ? 1 : 2); }
+    __host__ __device__ static int slot(int rx, int ux, int ry, int uy, int rz, int uz)
     {
         const int sx = size(rx), sy = size(ry), sz = size(rz);
         return start(rz) * TB * TB + sz * start(ry) * TB + sz * sy * start(rx) + (uz * sy + uy) * sx + ux;
     }
     // slot of tile coordinates (x, y, z)
-    __device__ static int slot_of(int x, int y, int z)
+    __host__ __device__ static int slot_of(int x, int y, int z)
     {
         const int rx = region(x), ry = region(y), rz = region(z);
         return slot(rx, x - start(rx), ry, y - start(ry), rz, z - start(rz));
     }
     // tile coordinates of slot s (inverse of slot_of)
-    __device__ static void coords(int s, int &x, int &y, int &z)
+    __host__ __device__ static void coords(int s, int &x, int &y, int &z)
     {
         const int rz = s < TB * TB ? 0 : (s < (B + 1) * TB * TB ? 1 : 2);
         s -= start(rz) * TB * TB;
@@ -118,11 +118,31 @@ struct TileRegions {
         y = start(ry) + (q & ((1 << ly) - 1));
         z = start(rz) + (q >> ly);
     }
-    __device__ static int lg(int r) { return r == 0 ? 0 : (r == 1 ? Log2B<B>::v : 1); }
+    __host__ __device__ static int lg(int r) { return r == 0 ? 0 : (r == 1 ? Log2B<B>::v : 1); }
 };
 
 constexpr double kFixedUnits = 268435456.0;     // 2^28 units per particle mass and per m/dt
 constexpr float kFixedLimit = 2147483520.0f;     // largest float below 2^31: bound of a scaled contribution
+
+// LDS layout of a P2G tile, four channels per node of the (B+3)^3 tile:
+// row (y, z) holds channel 0 (plane 0) or 2 (plane 1) at x and channel 1 or
+// 3 at HALF + x; plane 1 starts TLP slots after plane 0.
+template <int B>
+struct P2GTileLayout {
+    static constexpr int TB = B + 3, HALF = B == 8 ? 12 : TB, RP = 2 * HALF, TLP = TB * TB * RP, SLOTS = 2 * TLP;
+    __host__ __device__ static constexpr int at(int x, int y, int z, int ch)
+    {
+        return (ch >> 1) * TLP + (ch & 1) * HALF + (z * TB + y) * RP + x;
+    }
+};
+
+// LDS layout of a G2P velocity tile, three components per node of the
+// (B+3)^3 tile: row (y, z) holds component r at r TB + x.
+template <int B>
+struct G2PTileLayout {
+    static constexpr int TB = B + 3, RP = B == 8 ? 40 : 3 * TB, SLOTS = TB * TB * RP;
+    __host__ __device__ static constexpr int at(int x, int y, int z, int r) { return (z * TB + y) * RP + r * TB + x; }
+};
 
 // One workgroup per grid block: particles binned to the block scatter mass
 // and momentum (Eqs. 2-5) into a (B+3)^3 LDS tile; the whole tile is then
@@ -145,8 +165,9 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
     // 8 x 8 particle patch touches then start 16 banks apart modulo 64 and
     // each 64-bit atomic is conflict free, where rows of 11 or 12 slots
     // conflict two-way; the two channels per row cost no extra LDS.
-    constexpr int HALF = B == 8 ? 12 : TB, RP = 2 * HALF, TLP = TB * TB * RP;
-    __shared__ Slot tile[2 * TLP];
+    using L = P2GTileLayout<B>;
+    constexpr int HALF = L::HALF, TLP = L::TLP;
+    __shared__ Slot tile[L::SLOTS];
     // a force-terminated run that has stopped skips its remaining substeps
     if (S.stop && *S.stop) return;
     // the next substep's bin counts start from zero; the force of the coming
@@ -173,7 +194,7 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
 #pragma unroll
         for (int k = 0; k < 9; ++k) fA[k] = S.A[k * N + pf];
     }
-    for (int i = threadIdx.x; i < 2 * TLP; i += WG) tile[i] = Slot(0);
+    for (int i = threadIdx.x; i < L::SLOTS; i += WG) tile[i] = Slot(0);
     __syncthreads();
     const int bx = b % S.nb0, byz = b / S.nb0, by = byz % S.nb1, bz = byz / S.nb1;
     // tile node (0,0,0) is grid node (lo - 1): a block's particles are those
@@ -270,7 +291,7 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const T wt = wab * wz[c];
-                    const int li = ((l2 + c) * TB + (l1 + bb)) * RP + (l0 + a);
+                    const int li = L::at(l0 + a, l1 + bb, l2 + c, 0);
                     Acc::add(&tile[li], wt * m);
                     Acc::add(&tile[HALF + li], wt * (qa[0] + Am[2] * T(c)));
                     Acc::add(&tile[TLP + li], wt * (qa[1] + Am[5] * T(c)));
@@ -286,7 +307,7 @@ __device__ __forceinline__ void p2g_block(const SimDev<T> &S, const int b, T fix
         T *d = dst + 4 * si;
         int x, y, z;
         TileRegions<B>::coords(si, x, y, z);
-        const int ls = (z * TB + y) * RP + x;
+        const int ls = L::at(x, y, z, 0);
         d[0] = Acc::value(tile[ls]) * munit;
         d[1] = Acc::value(tile[HALF + ls]) * punit;
         d[2] = Acc::value(tile[TLP + ls]) * punit;
@@ -325,23 +346,29 @@ __device__ __forceinline__ uint32_t live_mask(const SimDev<T> &S, int bx, int by
     return m;
 }
 
+// Blocks whose (B+3)^3 tile covers local coordinate l of a block along one
+// axis, as offsets in increasing order: (-1, 0) when l <= 1, (0, +1) when
+// l = B-1, else (0) alone (two = false; o1 = o0 = 0). Block c's tile spans
+// nodes lo_c - 1 .. lo_c + B + 1.
+template <int B>
+__host__ __device__ __forceinline__ void gather_cover(int l, int &o0, int &o1, bool &two)
+{
+    const int nb = l <= 1 ? -1 : (l == B - 1 ? 1 : 0);
+    o0 = nb < 0 ? nb : 0;
+    o1 = nb > 0 ? nb : 0;
+    two = nb != 0;
+}
+
 template <typename T, int B>
 __device__ __forceinline__ void gather_node(const SimDev<T> &S, int bx, int by, int bz, int lx, int ly, int lz,
                                             T out[4], uint32_t live27)
 {
     constexpr int TB = B + 3, TN = TB * TB * TB;
-    // per axis at most two covering blocks, in increasing offset: (-1, 0)
-    // when l <= 1, (0, +1) when l = B-1, else (0) alone
     const int l[3] = {lx, ly, lz};
     int o[3][2];
     bool two[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int nb = l[a] <= 1 ? -1 : (l[a] == B - 1 ? 1 : 0);
-        o[a][0] = min(nb, 0);
-        o[a][1] = max(nb, 0);
-        two[a] = nb != 0;
-    }
+    for (int a = 0; a < 3; ++a) gather_cover<B>(l[a], o[a][0], o[a][1], two[a]);
     // all eight candidate loads are issued before the sum (one memory round
     // trip); a candidate that does not cover the node or wrote no tile reads
     // the node's own slot in its own block, in bounds, and is dropped
@@ -739,8 +766,9 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
     // rows of an 8 x 8 particle patch then start on distinct multiples of 8
     // banks modulo 64 and every LDS read of the gather is conflict free,
     // where rows of 11 words conflict.
-    constexpr int RP = B == 8 ? 40 : 3 * TB;
-    __shared__ T tile[TB * TB * RP];
+    using L = G2PTileLayout<B>;
+    constexpr int RP = L::RP;
+    __shared__ T tile[L::SLOTS];
     // the thread's first list entry is read with the count (speculatively,
     // as in P2G) and its particle's state behind the tile's staging loads:
     // the barrier does not wait for global loads, so the particle work
@@ -790,9 +818,9 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
         const int li = threadIdx.x + k * WG;
         if (li < TN) {
             const int x = li % TB, yz = li / TB;
-            tile[yz * RP + x] = st[k][0];
-            tile[yz * RP + TB + x] = st[k][1];
-            tile[yz * RP + 2 * TB + x] = st[k][2];
+            tile[L::at(x, yz, 0, 0)] = st[k][0];
+            tile[L::at(x, yz, 0, 1)] = st[k][1];
+            tile[L::at(x, yz, 0, 2)] = st[k][2];
         }
     }
     __syncthreads();
@@ -859,7 +887,7 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
                 bspline3(f[2], wz);
                 // velocities relative to the stencil centre keep the affine
                 // sums well conditioned in FP32
-                const int lc = ((l2 + 1) * TB + (l1 + 1)) * RP + (l0 + 1);
+                const int lc = L::at(l0 + 1, l1 + 1, l2 + 1, 0);
                 const T vr[3] = {tile[lc], tile[TB + lc], tile[2 * TB + lc]};
                 // The weights are a tensor product, so the sums over the 27
                 // nodes of w D, w D a, w D b, w D c (D = V - vr, offsets a, b,
@@ -874,7 +902,7 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
                         T t[3], tz[3];
 #pragma unroll
                         for (int bb = 0; bb < 3; ++bb) {
-                            const int li = ((l2 * TB + (l1 + bb)) * RP + l0 + a) + r * TB;
+                            const int li = L::at(l0 + a, l1 + bb, l2, r);
                             const T d0 = tile[li] - vr[r];
                             const T d1 = tile[li + TB * RP] - vr[r];
                             const T d2 = tile[li + 2 * TB * RP] - vr[r];

@@ -6,6 +6,7 @@ and the HIP stream; all computation happens in the library's kernels.
 from __future__ import annotations
 
 import ctypes
+import json
 
 import numpy as np
 import torch
@@ -157,6 +158,30 @@ class Sim:
         assert ts[2].shape == (9, self.N) and ts[3].shape == (9, self.N)
         N.check(N.lib().tacchi_write_particles(self._h, *(ctypes.c_void_p(t.data_ptr()) for t in ts), 1))
         self.stream.synchronize()
+
+    # ------------------------------------------------------------ checkpoints
+    def save_checkpoint(self, path) -> None:
+        """Write what the press needs to continue to an .npz file: the
+        particle state (x, v, C, F as read_particles returns it, SI units),
+        the indenter pose reached by the last substep, the configuration and
+        the precision. The contact model and a point-cloud indenter are set
+        on the handle by their own calls and are not part of the file."""
+        x, v, C, F = (t.double().cpu().numpy() for t in self.read_particles())
+        cfg = json.dumps(self.cfg, default=lambda o: o.item() if hasattr(o, "item") else list(o))
+        np.savez(path, x=x, v=v, C=C, F=F, pose=self.pose(), cfg=np.array(cfg),
+                 precision=np.array("f64" if self.precision == N.F64 else "f32"))
+
+    @classmethod
+    def from_checkpoint(cls, path, tile: int = 0, device="cuda"):
+        """A simulator that continues the press saved by save_checkpoint: the
+        same configuration and precision, the indenter at the saved pose and
+        the saved particle state."""
+        with np.load(path, allow_pickle=False) as d:
+            cfg = json.loads(str(d["cfg"]))
+            cfg = {k: tuple(v) if isinstance(v, list) else v for k, v in cfg.items()}
+            sim = cls(cfg, d["pose"], precision=str(d["precision"]), tile=tile, device=device)
+            sim.write_particles(d["x"], d["v"], d["C"], d["F"])
+        return sim
 
     def read_grid(self, which: int):
         g = self.cfg["gn"]

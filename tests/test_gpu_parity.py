@@ -228,6 +228,30 @@ def test_checkpoint_resume(oracle_lib, gpu):
     assert np.abs(Ha - Hb).max() <= 1e-12
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_checkpoint_file_resume(oracle_lib, gpu, tmp_path, precision):
+    """A press saved to an .npz checkpoint after 300 substeps and continued by
+    a new simulator for 200 more ends where the uninterrupted press ends: to
+    FP64 rounding in FP64; in FP32 within what one write of the FP32 state
+    through SI units costs (the round trip rounds each position once)."""
+    Sim, _ = gpu
+    wl = W.small_sphere_contact(seed=2)
+    poses, dt = wl["poses"], wl["dt"]
+    a = Sim(wl["cfg"], poses[0], precision=precision)
+    a.run(poses[1:301], dt)
+    a.save_checkpoint(tmp_path / "press.npz")
+    a.run(poses[301:501], dt)
+    xa, Ha = to_np(a.read_particles()[0]), to_np(a.heightmap())
+    b = Sim.from_checkpoint(tmp_path / "press.npz")
+    assert b.precision == a.precision and b.N == a.N
+    np.testing.assert_array_equal(b.pose(), poses[300])
+    b.run(poses[301:501], dt)
+    xb, Hb = to_np(b.read_particles()[0]), to_np(b.heightmap())
+    tol = 1e-12 if precision == "f64" else 1e-7
+    assert np.abs(xa - xb).max() <= tol
+    assert np.abs(Ha - Hb).max() <= tol
+
+
 def test_error_paths_are_reported(oracle_lib, gpu):
     from paper_2301_08343_amd.native import TacchiError, E_UNSTABLE, E_OUT_OF_GRID
     Sim, aos_to_soa = gpu
