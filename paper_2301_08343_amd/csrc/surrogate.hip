@@ -519,8 +519,10 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h,
 // leaves the row, and zero for rows of another image), and every tap reads
 // its MFMA operand from a 16-byte aligned offset of one copy. The per-tap
 // kernel reads the output gradient and the input once per tap. Requires
-// chunks inside one image (h w % kWgChunk == 0) and 16 <= w <= 64, w % 16 == 0.
-constexpr int kW9Halo = kWgChunk + 2 * 64;
+// chunks of CH pixels inside one image (h w % CH == 0, CH % w == 0) and
+// 8 <= w <= 64, w % 8 == 0: CH = 128 for rows of 16..64 pixels, 64 for 8.
+template <int CH>
+constexpr int wgrad9_halo() { return CH + 2 * 64; }
 
 // bf16 element k of a uint2 holding four
 __device__ __forceinline__ uint32_t bf_at(const uint2 &v, int k)
@@ -534,31 +536,32 @@ __device__ __forceinline__ uint4 pack8(const uint32_t (&e)[8])
     return uint4{e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16)};
 }
 
+template <int CH>
 __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h, int w, int in_ld, int in_off,
                                                 int cin_p, const uint16_t *dout, int d_ld, int d_off, int cout,
                                                 int pix_per_split, float *part, float *bpart)
 {
-    __shared__ __align__(16) uint16_t sA[32][kWgChunk + 8];     // [co][pixel]
-    __shared__ __align__(16) uint16_t sB[3][32][kW9Halo + 8];   // [dw + 1][ci][haloed pixel]
+    __shared__ __align__(16) uint16_t sA[32][CH + 8];     // [co][pixel]
+    __shared__ __align__(16) uint16_t sB[3][32][wgrad9_halo<CH>() + 8];   // [dw + 1][ci][haloed pixel]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int hw = h * w, npix = n * hw;
     const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32, split = blockIdx.z;
     const int pbeg = split * pix_per_split, pend = min(npix, pbeg + pix_per_split);
     const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
     const bool do_bias = bpart != nullptr && blockIdx.y == 0;
-    const int halo = kWgChunk + 2 * w;
+    const int halo = CH + 2 * w;
     f32x4 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;
     // staging item of this thread: an 8-pixel window `win` of 4 channels
     // lc .. lc+3, transposed in registers and stored as four 16-byte rows.
-    // dout: windows 0..15 of the chunk (threads 0..127); input: windows
+    // dout: windows 0..CH/8-1 of the chunk; input: windows
     // 0..halo/8-1 of the haloed chunk, read with one pixel on either side for
     // the copies shifted by dw = -1 and +1. The next chunk is loaded while
     // the current one computes.
     const int win = tid >> 3, lc = (tid & 7) * 4;
-    const bool a_item = win < kWgChunk / 8, b_item = win * 8 < halo;
+    const bool a_item = win < CH / 8, b_item = win * 8 < halo;
     uint2 va[8], vb[10];
     auto load = [&](int p0) {
         const int64_t ibeg = (int64_t)(p0 / hw) * hw, iend = ibeg + hw;
@@ -578,7 +581,7 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
         }
     };
     load(pbeg);
-    for (int p0 = pbeg; p0 < pend; p0 += kWgChunk) {
+    for (int p0 = pbeg; p0 < pend; p0 += CH) {
         __syncthreads();  // the previous chunk's LDS reads are done
         if (a_item) {
 #pragma unroll
@@ -592,7 +595,7 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
         if (b_item) {
             // entry e of copy dw + 1 holds pixel e + dw of the same row (zero
             // past the row's ends); an 8-entry window lies inside one row
-            // (w % 16 == 0, and the haloed chunk starts at a row start)
+            // (w % 8 == 0, and the haloed chunk starts at a row start)
             const bool row_first = (win * 8) % w == 0, row_last = (win * 8 + 8) % w == 0;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -611,10 +614,10 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
             }
         }
         __syncthreads();
-        if (p0 + kWgChunk < pend) load(p0 + kWgChunk);
+        if (p0 + CH < pend) load(p0 + CH);
         const int r16 = lane & 15, kg = (lane >> 4) * 8;
 #pragma unroll
-        for (int j = 0; j < kWgChunk / 32; ++j) {
+        for (int j = 0; j < CH / 32; ++j) {
             const bf16x8 a8 = __builtin_bit_cast(bf16x8, *(const uint4 *)&sA[wm + r16][32 * j + kg]);
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
@@ -625,7 +628,7 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
             }
         }
         if (do_bias && tid < 32) {
-            for (int q = 0; q < kWgChunk; ++q) bsum += bf2f(sA[tid][q]);
+            for (int q = 0; q < CH; ++q) bsum += bf2f(sA[tid][q]);
         }
     }
     const int ci = ci0 + wn + (lane & 15);
@@ -1187,19 +1190,25 @@ tsg_status tsg_conv(const uint16_t *in, int32_t n, int32_t h, int32_t w, int32_t
 
 // the all-taps kernel applies where its chunks stay inside one image and
 // its shifted rows stay aligned
-static bool wgrad9_ok(int h, int w, int taps)
+// Pixels per chunk of the all-taps weight gradient for this layer, 0 when
+// the per-tap kernel runs instead.
+static int wgrad9_chunk(int h, int w, int taps)
 {
-    return taps == 9 && w >= 16 && w <= 64 && w % 16 == 0 && ((int64_t)h * w) % kWgChunk == 0;
+    if (taps != 9 || w < 8 || w > 64 || w % 8) return 0;
+    const int64_t hw = (int64_t)h * w;
+    if (w >= 16 && hw % 128 == 0) return 128;
+    if (hw % 64 == 0 && 64 % w == 0) return 64;
+    return 0;
 }
 
 static int wgrad_splits(int64_t npix, int h, int w, int cout, int cin_p, int taps)
 {
-    if (wgrad9_ok(h, w, taps)) {
+    if (const int ch = wgrad9_chunk(h, w, taps)) {
         // ~2 workgroups per CU (the staged halo takes ~59 KB of LDS), each
         // over at least 4 chunks
         const int64_t tiles = (int64_t)((cout + 31) / 32) * ((cin_p + 31) / 32);
         int64_t s = std::max<int64_t>(1, 512 / tiles);
-        s = std::min<int64_t>(s, std::max<int64_t>(1, npix / (4 * kWgChunk)));
+        s = std::min<int64_t>(s, std::max<int64_t>(1, npix / (4 * ch)));
         return (int)s;
     }
     const int64_t tiles = (int64_t)((cout + 31) / 32) * taps * ((cin_p + 31) / 32);
@@ -1229,13 +1238,18 @@ tsg_status tsg_conv_wgrad(const uint16_t *in, int32_t n, int32_t h, int32_t w, i
     hipStream_t st = (hipStream_t)stream;
     const int64_t npix = (int64_t)n * h * w;
     const int splits = wgrad_splits(npix, h, w, cout, cin_p, taps);
+    const int ch9 = wgrad9_chunk(h, w, taps), chunk = ch9 ? ch9 : kWgChunk;
     int pps = (int)((npix + splits - 1) / splits);
-    pps = ((pps + kWgChunk - 1) / kWgChunk) * kWgChunk;
+    pps = ((pps + chunk - 1) / chunk) * chunk;
     float *bpart = db ? scratch + (size_t)splits * cout * taps * cin_p : nullptr;
-    if (wgrad9_ok(h, w, taps)) {
+    if (ch9) {
         const dim3 grid((cout + 31) / 32, (cin_p + 31) / 32, splits);
-        hipLaunchKernelGGL(k_wgrad9, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld, d_off,
-                           cout, pps, scratch, bpart);
+        if (ch9 == 128)
+            hipLaunchKernelGGL(k_wgrad9<128>, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld,
+                               d_off, cout, pps, scratch, bpart);
+        else
+            hipLaunchKernelGGL(k_wgrad9<64>, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld,
+                               d_off, cout, pps, scratch, bpart);
     } else {
         const dim3 grid((cout + 31) / 32, taps * ((cin_p + 31) / 32), splits);
         hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, in, n, h, w, in_ld, in_off, cin_p, dout, d_ld, d_off,

@@ -164,6 +164,8 @@ def test_conv_input_gradient(T, case, fuse_gelu):
     (2, 32, 32, 32, 32, 32, 0, 32, 32, 0, 9),
     (1, 64, 64, 40, 48, 48, 0, 24, 24, 0, 9),
     (3, 16, 16, 20, 24, 48, 24, 36, 40, 4, 9),
+    # 8-pixel rows: the all-taps kernel with 64-pixel chunks (one 8 x 8 image each)
+    (5, 8, 8, 32, 32, 64, 32, 64, 64, 0, 9),
 ])
 def test_conv_weight_gradient(T, case):
     n, h, w, cin, cin_p, ld, off, cout, gld, goff, taps = case
