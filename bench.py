@@ -73,7 +73,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic(kernel):
+def committed_profile(kernel, field="bytes_per_launch"):
+    """A per-launch counter figure of `kernel` from the committed profile
+    summary (HBM bytes or VALU instructions), or None when the kernel sources
+    have changed since it was taken."""
     try:
         with open(PROFILE) as fh:
             text = fh.read()
@@ -85,7 +88,21 @@ def committed_traffic(kernel):
     d = json.loads(m.group(1))
     if d.get("source_sha256") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch", {}).get(kernel)
+    return d.get(field, {}).get(kernel)
+
+
+def committed_traffic(kernel):
+    return committed_profile(kernel, "bytes_per_launch")
+
+
+# VALU issue: one wave instruction holds its SIMD 4 cycles (16 lanes per
+# cycle, no packed FP32 here): 1024 SIMDs x 2.4 GHz / 4 wave instructions/s
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
+
+
+def valu_issue_frac(kernel, launch_ms):
+    n = committed_profile(kernel, "valu_instr_per_launch")
+    return None if n is None else n / VALU_ISSUE_PER_S / (launch_ms * 1e-3)
 
 
 def parse():
@@ -535,7 +552,7 @@ def main():
         b = BYTES_PER_PARTICLE[k] * N + BYTES_PER_ACTIVE_NODE[k] * nodes
         per_kernel[k] = {"algorithmic_bytes_per_launch": b, "avg_launch_ms": k_ms[k],
                          "achieved": b / (k_ms[k] * 1e-3) / 1e9, "launches": timing[k][1],
-                         "traffic": committed_traffic(k),
+                         "traffic": committed_traffic(k), "valu_issue_frac": valu_issue_frac(k, k_ms[k]),
                          "design_bytes_per_launch": design_bytes(k, N, active, args.tile)}
     algo_bytes = per_kernel[dom]["algorithmic_bytes_per_launch"]
     achieved = per_kernel[dom]["achieved"]
