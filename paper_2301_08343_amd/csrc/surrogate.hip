@@ -50,11 +50,35 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf(x) by Abramowitz & Stegun (1964), eq. 7.1.26 (Hastings' rational
+// form): erf(|x|) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+// t = 1 / (1 + p |x|), absolute error <= 1.5e-7 on the whole line (plus a
+// few FP32 ulps of 1 from the hardware reciprocal and exp2), far below the
+// bf16 rounding (2^-9 relative) of every value GELU and GELU' feed. e
+// returns exp(-x^2), which GELU' needs as well. About 12 instructions.
+__device__ __forceinline__ float erf_as(float x, float &e)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    const float poly =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+    e = __builtin_amdgcn_exp2f(-(ax * ax) * 1.44269504088896341f);
+    return copysignf(fmaf(-poly, e, 1.0f), x);
+}
 
+// GELU(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2
+__device__ __forceinline__ float gelu(float z)
+{
+    float e;
+    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, e));
+}
+
+// GELU'(z) = Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi)
 __device__ __forceinline__ float dgelu(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    float e;
+    const float r = erf_as(z * 0.70710678118654752f, e);
+    return 0.5f * (1.0f + r) + z * 0.39894228040143268f * e;
 }
 
 __device__ __forceinline__ bf16x8 load8(const uint16_t *p)
