@@ -722,7 +722,19 @@ __global__ void k_head_wgrad(const uint16_t *in, int npix, int in_ld, int in_off
     const int co = t / (cin + 1), ci = t % (cin + 1);
     const int r0 = split * rows_per_split, r1 = min(npix, r0 + rows_per_split);
     float s = 0.0f;
-    for (int r = r0; r < r1; ++r) {
+    // eight rows' loads are issued before their (in-order) accumulation
+    int r = r0;
+    for (; r + 8 <= r1; r += 8) {
+        float g[8], x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            g[k] = dout[(int64_t)(r + k) * cout + co];
+            x[k] = ci < cin ? bf2f(in[(int64_t)(r + k) * in_ld + in_off + ci]) : 1.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += ci < cin ? g[k] * x[k] : g[k];
+    }
+    for (; r < r1; ++r) {
         const float g = dout[(int64_t)r * cout + co];
         s += ci < cin ? g * bf2f(in[(int64_t)r * in_ld + in_off + ci]) : g;
     }
@@ -757,17 +769,46 @@ __global__ void __launch_bounds__(256) k_head_reduce(const float *part, int spli
     }
 }
 
+// Input gradient of the 1x1 head: din[p][ci] = sum_co dout[p][co] w[co][ci]
+// (times GELU'(z) with z). One thread per (pixel, channel); npix * cin <
+// 2^31 (checked by the caller), so the index splits in 32-bit arithmetic.
 __global__ void k_head_dgrad(const float *dout, int npix, int cout, const float *w, int cin, uint16_t *din, int ld,
                              int off, const uint16_t *z, int z_ld, int z_off)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)npix * cin) return;
-    const int64_t p = idx / cin;
-    const int ci = (int)(idx % cin);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= npix * cin) return;
+    const int p = idx / cin, ci = idx - p * cin;
     float s = 0.0f;
-    for (int co = 0; co < cout; ++co) s += dout[p * cout + co] * w[(int64_t)co * cin + ci];
-    if (z) s *= dgelu(bf2f(z[p * z_ld + z_off + ci]));
-    din[p * ld + off + ci] = f2bf(s);
+    for (int co = 0; co < cout; ++co) s += dout[(int64_t)p * cout + co] * w[co * cin + ci];
+    if (z) s *= dgelu(bf2f(z[(int64_t)p * z_ld + z_off + ci]));
+    din[(int64_t)p * ld + off + ci] = f2bf(s);
+}
+
+// The same for 8 channels of a pixel per thread (cin, ld, off, z_ld, z_off
+// multiples of 8 and 16-byte aligned views): one 16-byte store.
+__global__ void k_head_dgrad_v8(const float *dout, int npix, int cout, const float *w, int cin, uint16_t *din,
+                                int ld, int off, const uint16_t *z, int z_ld, int z_off)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g8 = cin >> 3;
+    if (idx >= npix * g8) return;
+    const int p = idx / g8, c0 = (idx - p * g8) * 8;
+    float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int co = 0; co < cout; ++co) {
+        const float g = dout[(int64_t)p * cout + co];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += g * w[co * cin + c0 + k];
+    }
+    if (z) {
+        const uint4 zr = *(const uint4 *)(z + (int64_t)p * z_ld + z_off + c0);
+        const uint32_t zw[4] = {zr.x, zr.y, zr.z, zr.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] *= dgelu(bf2f((uint16_t)(zw[k >> 1] >> ((k & 1) * 16))));
+    }
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = (uint32_t)f2bf(s[2 * k]) | ((uint32_t)f2bf(s[2 * k + 1]) << 16);
+    *(uint4 *)(din + (int64_t)p * ld + off + c0) = uint4{o[0], o[1], o[2], o[3]};
 }
 
 // ------------------------------------------------------------------ pooling, upsampling, elementwise
@@ -1319,9 +1360,14 @@ tsg_status tsg_head_dgrad(const float *dout, int32_t npix, int32_t cout, const f
                           int32_t din_ld, int32_t din_off, const uint16_t *zbuf, int32_t z_ld, int32_t z_off,
                           void *stream)
 {
-    if (!dout || !w || !din) return fail(-1, "tsg_head_dgrad: bad arguments");
-    hipLaunchKernelGGL(k_head_dgrad, dim3(blocks_for((int64_t)npix * cin)), dim3(256), 0, (hipStream_t)stream, dout,
-                       npix, cout, w, cin, din, din_ld, din_off, zbuf, z_ld, z_off);
+    if (!dout || !w || !din || npix < 1 || cin < 1 || cout < 1 || (int64_t)npix * cin >= ((int64_t)1 << 31))
+        return fail(-1, "tsg_head_dgrad: bad arguments");
+    if (cin % 8 == 0 && v8_ok(din, cin, din_ld, din_off) && (!zbuf || v8_ok(zbuf, cin, z_ld, z_off)))
+        hipLaunchKernelGGL(k_head_dgrad_v8, dim3(blocks_for((int64_t)npix * (cin / 8))), dim3(256), 0,
+                           (hipStream_t)stream, dout, npix, cout, w, cin, din, din_ld, din_off, zbuf, z_ld, z_off);
+    else
+        hipLaunchKernelGGL(k_head_dgrad, dim3(blocks_for((int64_t)npix * cin)), dim3(256), 0, (hipStream_t)stream,
+                           dout, npix, cout, w, cin, din, din_ld, din_off, zbuf, z_ld, z_off);
     TSG_LAUNCHED();
     return 0;
 }

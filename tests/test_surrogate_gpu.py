@@ -193,9 +193,10 @@ def test_conv_weight_gradient(T, case):
     assert torch.equal(dw, dw2)
 
 
-def test_head_gradients(T):
-    n, h, w, cin, cout = 2, 16, 12, 32, 3
-    rng = np.random.default_rng(31)
+@pytest.mark.parametrize("cin,with_z", [(32, True), (32, False), (20, True)])  # 8-channel path, and per channel
+def test_head_gradients(T, cin, with_z):
+    n, h, w, cout = 2, 16, 12, 3
+    rng = np.random.default_rng(31 + cin)
     x = R.round_bf16(rng.standard_normal((n, h, w, cin)))
     z = R.round_bf16(rng.standard_normal((n, h, w, cin)))
     g = rng.standard_normal((n, h, w, cout)).astype(np.float32).astype(np.float64)
@@ -209,14 +210,14 @@ def test_head_gradients(T):
                db.data_ptr(), scratch.data_ptr(), nb, stream())
     din = torch.zeros(n, h, w, cin, dtype=torch.bfloat16, device="cuda")
     T.tsg_call("tsg_head_dgrad", gdv.data_ptr(), n * h * w, cout, wd.data_ptr(), cin, din.data_ptr(), cin, 0,
-               zd.data_ptr(), cin, 0, stream())
+               zd.data_ptr() if with_z else None, cin, 0, stream())
     dx, rdw, rdb = R.conv_backward(x, wt, g)
     _, adw, adb = R.conv_backward(np.abs(x), wt, np.abs(g))
     adx, _, _ = R.conv_backward(x, np.abs(wt), np.abs(g))
     npix = n * h * w
     assert np.all(np.abs(host(dw) - rdw[:, 0, :]) <= 2 * npix * U_32 * adw[:, 0, :])
     assert np.all(np.abs(host(db) - rdb) <= 2 * npix * U_32 * adb)
-    ref = dx * R.gelu_grad(z)
+    ref = dx * R.gelu_grad(z) if with_z else dx
     acc = cout * U_32 * adx
     assert np.all(np.abs(host(din) - ref) <= U_BF * (np.abs(ref) + LIP * acc) + LIP * acc + 1e-6 * np.abs(dx))
 
