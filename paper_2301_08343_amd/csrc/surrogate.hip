@@ -669,44 +669,33 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
 // dw[co][tap][ci] = sum over splits of the partials, ci < cin. 32 outputs
 // per workgroup, 8 lanes per output: lane g sums splits g, g+8, ... and the
 // eight lane sums are added in lane order, a fixed order (bit-reproducible).
+// Workgroups from nw_blocks on sum the bias partials [splits][cout] into db
+// the same way (one launch for both sums).
 __global__ void __launch_bounds__(256) k_wgrad_reduce(const float *part, int splits, int cout, int taps, int cin,
-                                                      int cin_p, float *dw)
+                                                      int cin_p, float *dw, int nw_blocks, const float *bpart,
+                                                      float *db)
 {
     __shared__ float red[8][33];
     const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const int64_t idx = (int64_t)blockIdx.x * 32 + o;
-    const int64_t total = (int64_t)cout * taps * cin;
+    const bool bias = (int)blockIdx.x >= nw_blocks;
+    const int64_t idx = (int64_t)(bias ? blockIdx.x - nw_blocks : blockIdx.x) * 32 + o;
+    const int64_t total = bias ? cout : (int64_t)cout * taps * cin;
     float s = 0.0f;
     if (idx < total) {
-        const int ci = (int)(idx % cin);
-        const int64_t ct = idx / cin;  // co * taps + tap
-        for (int k = g; k < splits; k += 8) s += part[((int64_t)k * cout * taps + ct) * cin_p + ci];
+        if (bias) {
+            for (int k = g; k < splits; k += 8) s += bpart[(int64_t)k * cout + idx];
+        } else {
+            const int ci = (int)(idx % cin);
+            const int64_t ct = idx / cin;  // co * taps + tap
+            for (int k = g; k < splits; k += 8) s += part[((int64_t)k * cout * taps + ct) * cin_p + ci];
+        }
     }
     red[g][o] = s;
     __syncthreads();
     if (g == 0 && idx < total) {
         float t = 0.0f;
         for (int q = 0; q < 8; ++q) t += red[q][o];
-        dw[idx] = t;
-    }
-}
-
-// Sum over splits of per-split partials [splits][c], as k_wgrad_reduce
-// (32 channels per workgroup, 8 lanes each, fixed order).
-__global__ void __launch_bounds__(256) k_colsum_reduce(const float *part, int splits, int c, float *out)
-{
-    __shared__ float red[8][33];
-    const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const int ch = blockIdx.x * 32 + o;
-    float s = 0.0f;
-    if (ch < c)
-        for (int k = g; k < splits; k += 8) s += part[(int64_t)k * c + ch];
-    red[g][o] = s;
-    __syncthreads();
-    if (g == 0 && ch < c) {
-        float t = 0.0f;
-        for (int q = 0; q < 8; ++q) t += red[q][o];
-        out[ch] = t;
+        (bias ? db : dw)[idx] = t;
     }
 }
 
@@ -1321,13 +1310,11 @@ tsg_status tsg_conv_wgrad(const uint16_t *in, int32_t n, int32_t h, int32_t w, i
                            cout, taps, pps, scratch, bpart);
     }
     TSG_LAUNCHED();
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(((int64_t)cout * taps * cin + 31) / 32)), dim3(256), 0, st,
-                       scratch, splits, cout, taps, cin, cin_p, dw);
+    const int nw_blocks = (int)(((int64_t)cout * taps * cin + 31) / 32);
+    const int nb_blocks = db ? (cout + 31) / 32 : 0;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(nw_blocks + nb_blocks)), dim3(256), 0, st, scratch, splits, cout,
+                       taps, cin, cin_p, dw, nw_blocks, bpart, db);
     TSG_LAUNCHED();
-    if (db) {
-        hipLaunchKernelGGL(k_colsum_reduce, dim3((cout + 31) / 32), dim3(256), 0, st, bpart, splits, cout, db);
-        TSG_LAUNCHED();
-    }
     return 0;
 }
 
