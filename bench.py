@@ -153,10 +153,14 @@ def surrogate_leg(args):
     torch.cuda.synchronize()
     inf_s = (time.perf_counter() - t0) / reps
     ftr = SP.train_features(meta["train_samples"], meta["h_m"])
-    prior = meta.get("heldout", {}).get("height_rmse_um_by_group")
-    stats = meta.get("heldout", {}).get("height_ms_um2_stats_by_group")
+    held = meta.get("heldout", {})
+    prior = held.get("height_rmse_um_by_group")
+    # the error budget over (family, depth bin) classes when the weights carry
+    # their statistics, else over families
+    edges = held.get("router_depth_edges_m")
+    stats = held.get("height_ms_um2_stats_by_class") if edges else held.get("height_ms_um2_stats_by_group")
     rep = SP.serve_benchmark(net, ftr, meta["threshold"], meta["h_m"], args.queries, args.plain_sample,
-                             prior_rmse_um=prior, prior_stats=stats, log=log)
+                             prior_rmse_um=prior, prior_stats=stats, depth_edges=edges, log=log)
     r, p = rep["router"], rep["plain_mpm"]
     return {"metric": "tactile frames/s, surrogate + MPM fallback vs plain batched MPM",
             "frames_per_s": r["frames_per_s"], "plain_mpm_frames_per_s": p["frames_per_s"],

@@ -20,11 +20,13 @@ Each query is a contact (indenter, pose, depth). Per batch of queries:
        most recent audits exceeds the limit (5 um by default); a breaker
        starts tripped when the held-out error of its queries is above it;
      * "budget": the limit bounds the error of all served answers together.
-       Each family's mean squared height error is estimated from its
+       Queries fall into classes: the indenter family, or (with depth
+       edges) the family and the press depth's bin, both known from the
+       query. Each class's mean squared height error is estimated from its
        held-out samples and its audits, as an upper confidence bound (mean
-       plus z standard errors, z = 1.645: one-sided 95 %); families are
+       plus z standard errors, z = 1.645: one-sided 95 %); classes are
        admitted in increasing order of that bound while the mean of the
-       bounds, weighted by each family's share of the queries so far, stays
+       bounds, weighted by each class's share of the queries so far, stays
        within the limit squared. The admitted set is recomputed after every
        audit and at every batch;
   5. the MPM answers every query sent to it; the rest keep the surrogate's.
@@ -33,6 +35,7 @@ queued at time zero and batches run back to back).
 """
 from __future__ import annotations
 
+import bisect
 import math
 import time
 
@@ -65,6 +68,15 @@ def nn_distance(q, ref):
     native.tsg_call("tsg_nn_dist", q.data_ptr(), q.shape[0], ref.data_ptr(), ref.shape[0], q.shape[1],
                     d2.data_ptr(), idx.data_ptr(), torch.cuda.current_stream().cuda_stream)
     return d2.sqrt(), idx
+
+
+def query_class(contact, depth_edges=None) -> int:
+    """Router class of a query: its indenter family, or with depth_edges (m,
+    ascending) family * (len(edges) + 1) + the index of its depth's bin."""
+    fam = int(contact["cfg"]["shape"])
+    if not depth_edges:
+        return fam
+    return fam * (len(depth_edges) + 1) + bisect.bisect_right(list(depth_edges), float(contact["depth"]))
 
 
 def audit_draws(n, rate, seed):
@@ -126,16 +138,18 @@ class Router:
     every query; prior_rmse_um maps a breaker key to the surrogate's
     held-out height RMSE for its queries, and breakers whose prior exceeds
     the limit start tripped.
-    policy "budget": prior_stats maps each indenter family to the count,
-    mean and standard deviation of its held-out samples' height mean squared
-    error (um^2); a family without them is never admitted."""
+    policy "budget": prior_stats maps each query class (query_class with
+    depth_edges) to the count, mean and standard deviation of its held-out
+    samples' height mean squared error (um^2); a class without them is never
+    admitted."""
 
     # route codes (BREAKER: the guard was closed for the query's family when
     # its batch started; BREAKER_IN_BATCH: an audit of the same batch closed it)
     SURROGATE, OOD, AUDIT, BREAKER, BREAKER_IN_BATCH = 0, 1, 2, 3, 4
 
     def __init__(self, net: Net, train_features, threshold, audit_rate=0.02, audit_seed=7, rmse_limit_um=5.0,
-                 window=20, per_class=True, prior_rmse_um=None, policy="breaker", prior_stats=None, z=1.645):
+                 window=20, per_class=True, prior_rmse_um=None, policy="breaker", prior_stats=None, z=1.645,
+                 depth_edges=None):
         if policy not in ("breaker", "budget"):
             raise ValueError(f"unknown router policy {policy!r}")
         self.net = net
@@ -150,6 +164,7 @@ class Router:
         self.policy = policy
         self.prior_stats = {int(k): dict(v) for k, v in (prior_stats or {}).items()}
         self.z = z
+        self.depth_edges = [float(e) for e in depth_edges] if depth_edges else None
 
     @staticmethod
     def calibrate(train_features, heldout_features, q=0.995):
@@ -165,7 +180,7 @@ class Router:
         report dict, route code per query)."""
         n = len(contacts)
         audit = audit_draws(n, self.audit_rate, self.audit_seed)
-        key = np.array([c["cfg"]["shape"] if self.per_class else 0 for c in contacts])
+        key = np.array([query_class(c, self.depth_edges) if self.per_class else 0 for c in contacts])
         answers = torch.empty(n, D.RES, D.RES, 3, dtype=torch.float32, device="cuda")
         lat = np.zeros(n)
         route = np.zeros(n, dtype=np.int8)
@@ -262,7 +277,7 @@ class Router:
         all_sq = [v for sq in audits_sq.values() for v in sq]
         audited = math.sqrt(sum(all_sq) / len(all_sq)) if all_sq else float("nan")
         rep = {
-            "policy": self.policy, "queries": n, "wall_s": wall, "frames_per_s": n / wall,
+            "policy": self.policy, "depth_edges_m": self.depth_edges, "queries": n, "wall_s": wall, "frames_per_s": n / wall,
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mpm_fallbacks": int(n_mpm), "ood": int((route == self.OOD).sum()),

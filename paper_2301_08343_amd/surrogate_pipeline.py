@@ -27,6 +27,22 @@ from .surrogate import Net, forward_flops
 
 HELDOUT_SEED0 = 50_000
 QUERY_SEED0 = 100_000
+# the router's classes split each indenter family at these press depths:
+# three equal bins of the drawn depth range, 0.2 .. 1.5 mm
+DEPTH_EDGES_M = (0.2e-3 + 1.3e-3 / 3, 0.2e-3 + 2.6e-3 / 3)
+
+
+def heldout_report(net, x, y, seeds, h):
+    """Held-out errors by indenter family, plus the per-class statistics
+    (family and depth bin, the router's classes) its error budget starts
+    from, and the class definition."""
+    rep = TR.evaluate(net, x, y, groups=[s % 5 for s in seeds])
+    cs = D.contacts_for(seeds, h, full=False)
+    by_class = TR.evaluate(net, x, y, groups=[RT.query_class(c, DEPTH_EDGES_M) for c in cs])
+    rep["height_ms_um2_stats_by_class"] = by_class["height_ms_um2_stats_by_group"]
+    rep["height_rmse_um_by_class"] = by_class["height_rmse_um_by_group"]
+    rep["router_depth_edges_m"] = list(DEPTH_EDGES_M)
+    return rep
 
 
 def log(msg):
@@ -101,7 +117,8 @@ def served_sample(n, k, seed=11):
     return [i for i in range(n) if rng.next_u64() < lim]
 
 
-def serve_benchmark(net, ftr, thr, h, queries, plain_sample, prior_rmse_um=None, prior_stats=None, log=log):
+def serve_benchmark(net, ftr, thr, h, queries, plain_sample, prior_rmse_um=None, prior_stats=None, depth_edges=None,
+                    log=log):
     """The query stream through the router, and plain batched MPM on a seeded
     sample of about `plain_sample` queries spread over the whole stream: its
     rate is the plain MPM's frames/s, and its answers measure the error of
@@ -112,7 +129,7 @@ def serve_benchmark(net, ftr, thr, h, queries, plain_sample, prior_rmse_um=None,
     rep = {}
     qs = D.contacts_for(range(QUERY_SEED0, QUERY_SEED0 + queries), h, full=False)
     if prior_stats:
-        r = RT.Router(net, ftr, thr, policy="budget", prior_stats=prior_stats)
+        r = RT.Router(net, ftr, thr, policy="budget", prior_stats=prior_stats, depth_edges=depth_edges)
     else:
         r = RT.Router(net, ftr, thr, prior_rmse_um=prior_rmse_um)
     ans, rrep, route = r.serve(qs, log=log)
@@ -188,7 +205,7 @@ def evaluate_weights(a, rep):
     net, meta = load_compact(a.weights, batch=512)
     h = meta["h_m"]
     xte, yte = D.generate(range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout), h=h, batch=a.gen_batch, log=log)
-    rep["heldout"] = TR.evaluate(net, xte, yte, groups=[s % 5 for s in range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout)])
+    rep["heldout"] = heldout_report(net, xte, yte, list(range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout)), h)
     log(f"held-out: {json.dumps(rep['heldout'])}")
     thr = meta.pop("threshold")
     meta["heldout"] = rep["heldout"]
@@ -197,7 +214,8 @@ def evaluate_weights(a, rep):
         ftr = train_features(meta["train_samples"], h)
         rep.update(serve_benchmark(net, ftr, thr, h, a.queries, a.plain_sample,
                                    prior_rmse_um=rep["heldout"].get("height_rmse_um_by_group"),
-                                   prior_stats=rep["heldout"].get("height_ms_um2_stats_by_group")))
+                                   prior_stats=rep["heldout"].get("height_ms_um2_stats_by_class"),
+                                   depth_edges=rep["heldout"].get("router_depth_edges_m")))
     with open(os.path.join(a.out, "report.json"), "w") as f:
         json.dump(rep, f, indent=1)
     return 0
@@ -260,7 +278,7 @@ def main(argv=None):
     rep["train"] = {"epochs": a.epochs, "seconds": tsec, "samples_per_s": steps * a.batch / tsec,
                     "tflops": flops / tsec / 1e12, "final_loss": hist[-1][1],
                     "loss_curve": [h[1] for h in hist]}
-    rep["heldout"] = TR.evaluate(net, xte, yte, groups=[s % 5 for s in range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout)])
+    rep["heldout"] = heldout_report(net, xte, yte, list(range(HELDOUT_SEED0, HELDOUT_SEED0 + a.heldout)), a.h)
     rep["train_fit"] = TR.evaluate(net, xtr[:a.heldout], ytr[:a.heldout], groups=[s % 5 for s in range(a.heldout)])
     log(f"held-out: {json.dumps(rep['heldout'])}")
 
@@ -282,7 +300,8 @@ def main(argv=None):
         serve_net.repack()
         rep.update(serve_benchmark(serve_net, ftr, thr, a.h, a.queries, a.plain_sample,
                                    prior_rmse_um=rep["heldout"].get("height_rmse_um_by_group"),
-                                   prior_stats=rep["heldout"].get("height_ms_um2_stats_by_group")))
+                                   prior_stats=rep["heldout"].get("height_ms_um2_stats_by_class"),
+                                   depth_edges=rep["heldout"].get("router_depth_edges_m")))
 
     with open(os.path.join(a.out, "report.json"), "w") as f:
         json.dump(rep, f, indent=1)

@@ -69,3 +69,16 @@ def test_budget_of_the_committed_families():
     assert admit(bounds, shares, 25.0) == {0, 1, 2, 3}
     # a smaller budget drops the larger of the two middle bounds first
     assert admit(bounds, shares, 16.0) == {0, 1, 2}
+
+
+def test_query_class_splits_families_by_depth():
+    """Classes are the family alone without edges; with edges, family *
+    (bins) + the bin of the press depth (a depth on an edge falls in the
+    upper bin)."""
+    from paper_2301_08343_amd.router import query_class
+    q = lambda fam, depth: {"cfg": {"shape": fam}, "depth": depth}  # noqa: E731
+    edges = (0.6e-3, 1.0e-3)
+    assert query_class(q(3, 0.9e-3)) == 3
+    assert [query_class(q(0, d), edges) for d in (0.2e-3, 0.6e-3 - 1e-9, 0.6e-3, 1.2e-3)] == [0, 0, 1, 2]
+    assert query_class(q(4, 1.5e-3), edges) == 14
+    assert query_class(q(2, 0.7e-3), edges) == 7

@@ -32,9 +32,10 @@ def test_pipeline_small(gpu, tmp_path):
     # the served answers' error is measured on a sample spread over the stream
     assert rep["served_sample"]["queries"] >= 32 and rep["served_sample"]["last_index"] >= 200
     # 2% of 300 draws are audited, unless the few-epoch network's held-out
-    # error already trips every family at the start (then nothing is served
-    # by it)
-    assert r["audited"] >= 1 or (r["served_by_surrogate"] == 0 and len(r["breaker_tripped_at_start"]) == 5)
+    # error already closes every class (family and depth bin) at the start
+    # (then nothing is served by it)
+    assert r["audited"] >= 1 or (r["served_by_surrogate"] == 0
+                                 and set(r["breaker_tripped_at_start"]) == {int(k) for k in r["per_class"]})
     assert (tmp_path / "surrogate.safetensors").exists()
 
 
@@ -143,3 +144,28 @@ def test_budget_closes_a_family_at_its_first_bad_audit(gpu):
             assert rep["per_class"][str(f)]["tripped"]
     assert rep["breaker_rerouted_in_batch"] + rep["breaker_routed"] > 0
     assert rep["mpm_fallbacks"] == rep["ood"] + rep["audited"] + rep["breaker_routed"] + rep["breaker_rerouted_in_batch"]
+
+
+def test_budget_admits_classes_by_family_and_depth(gpu):
+    """With depth edges the budget's classes are (family, depth bin): a
+    family whose shallow presses have a small error bound and whose deep
+    ones a large one gets surrogate answers for the shallow ones only."""
+    from paper_2301_08343_amd import dataset as D
+    from paper_2301_08343_amd import router as RT
+    from paper_2301_08343_amd.surrogate import Net
+    net = Net(batch=64, seed=1)
+    ftr = RT.features(D.inputs(D.contacts_for(range(64), 0.5e-3)))
+    qs = D.contacts_for(range(3000, 3096), 0.5e-3)
+    edges = (0.2e-3 + 1.3e-3 / 3, 0.2e-3 + 2.6e-3 / 3)
+    cls = np.array([RT.query_class(c, edges) for c in qs])
+    # every family's first two depth bins cheap, the deepest bin expensive
+    stats = {k: {"n": 50, "mean": (900.0 if k % 3 == 2 else 1.0), "sd": 1.0} for k in range(15)}
+    r = RT.Router(net, ftr, threshold=1e9, audit_rate=0.0, rmse_limit_um=5.0, policy="budget", prior_stats=stats,
+                  depth_edges=edges)
+    ans, rep, route = r.serve(qs, batch=32)
+    deep = cls % 3 == 2
+    assert deep.any() and (~deep).any()
+    assert np.all(route[~deep] == RT.Router.SURROGATE)
+    assert np.all(route[deep] == RT.Router.BREAKER)
+    assert rep["depth_edges_m"] == list(edges)
+    assert set(rep["budget"]["admitted_at_end"]) == {k for k in range(15) if k % 3 != 2}
