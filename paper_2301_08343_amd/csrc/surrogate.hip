@@ -252,55 +252,64 @@ tsg_status launch_conv_epi(const ConvArgs &a, int epi, hipStream_t st)
 // 256 consecutive output pixels, i.e. R = 256 / w whole image rows (w a power
 // of two, 4..64), times 32 output channels; waves and lanes take a tile's
 // pixels as in k_conv (wave q: pixels 64 q .. 64 q + 63). Per chunk of 32
-// input channels a workgroup stages the global rows row0 - 1 .. row0 + R
-// with a zero column on either side, and the chunk's weights of all nine
-// taps; every MFMA operand then comes from LDS, so the input is read from
-// memory about (R + 2) / R times instead of nine times and no tap waits on a
-// global load. A staged row that belongs to another image (or lies past the
-// batch) is never used: a tap whose row leaves the output pixel's image
-// reads zero instead. A staged pixel and a staged weight row take 40 bf16
-// (32 + 8): 16 consecutive pixels or rows then start 20 banks apart, and a
-// fragment's 16 lanes read 64 distinct banks.
+// input channels a workgroup stages the global rows row0 - 1 .. row0 + R and
+// the chunk's weights of all nine taps; every MFMA operand then comes from
+// LDS, so the input is read from memory about (R + 2) / R times instead of
+// nine times and no tap waits on a global load. A tap whose row leaves the
+// output pixel's image (a staged row of another image, or past the batch)
+// or whose column leaves the row reads zero instead: each lane keeps, per
+// pixel, a mask of its valid taps. A staged pixel and a staged weight row
+// take 40 bf16 (32 + 8): 16 consecutive pixels or rows then start 20 banks
+// apart, and a fragment's 16 lanes read 64 distinct banks. The staged input
+// is at most 6 w pixels (w = 64) and the LDS of a workgroup at most 52.5 KiB,
+// so three workgroups share a CU at every width.
 constexpr int kConvCC = 32, kConvCP = 40, kConvCo = 32;
 constexpr int kConvWVec = 9 * kConvCo * 4;      // 16-byte weight vectors per chunk
-constexpr int kConvXVecMax = 66 * 6 * 4;        // input vectors per chunk, largest (w = 4 or 64)
+constexpr int kConvXVecMax = 6 * 64 * 4;        // input vectors per chunk, largest: (R + 2) w 4 at w = 64
 
 __host__ __device__ constexpr int conv_lds_weights() { return 9 * kConvCo * kConvCP; }
 
-// A lane's four pixels of tile `tile`: LDS offset of the pixel's centre tap
-// (plus its K group), the pixel's row in its image, and whether it exists.
-__device__ __forceinline__ void conv_tile_pixels(const ConvArgs &a, int tile, int lgw, int wave, int lane,
-                                                 int (&sb)[4], int (&yy)[4], bool (&pv)[4])
+// A lane's four pixels of tile `tile` (local pixel lp = 64 wave + 16 j +
+// lane % 16): the mask of its valid taps (bit 3 (dh + 1) + dw + 1; none for
+// a pixel past the batch). Its centre tap is staged pixel lp + w, at LDS
+// offset conv_tile_centre + 16 j kConvCP (plus the lane's K group).
+__device__ __forceinline__ int conv_tile_centre(int w, int wave, int lane)
 {
-    const int R = 256 >> lgw, W2 = a.w + 2, nrows = a.n * a.h;
+    return (wave * 64 + (lane & 15) + w) * kConvCP + (lane >> 4) * 8;
+}
+
+__device__ __forceinline__ void conv_tile_pixels(const ConvArgs &a, int tile, int lgw, int wave, int lane,
+                                                 uint32_t (&tm)[4])
+{
+    const int R = 256 >> lgw, nrows = a.n * a.h;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int lp = wave * 64 + j * 16 + (lane & 15);
         const int lr = lp >> lgw, lc = lp & (a.w - 1), g = tile * R + lr;
-        pv[j] = g < nrows;
-        yy[j] = pv[j] ? g % a.h : 0;
-        sb[j] = ((lr + 1) * W2 + lc + 1) * kConvCP + (lane >> 4) * 8;
+        const int y = g % a.h;
+        const uint32_t rows = 0x038u | (y > 0 ? 0x007u : 0u) | (y < a.h - 1 ? 0x1c0u : 0u);
+        const uint32_t cols = 0x092u | (lc > 0 ? 0x049u : 0u) | (lc < a.w - 1 ? 0x124u : 0u);
+        tm[j] = g < nrows ? rows & cols : 0u;
     }
 }
 
 // The nine taps of one staged chunk: acc += W x im2col, operands from LDS.
-__device__ __forceinline__ void conv_tile_taps(const uint16_t *wst, const uint16_t *xst, int W2, int h, int lane,
-                                               const int (&sb)[4], const int (&yy)[4], const bool (&pv)[4],
-                                               f32x4 (&acc)[2][4])
+__device__ __forceinline__ void conv_tile_taps(const uint16_t *wst, const uint16_t *xst, int w, int wave, int lane,
+                                               const uint32_t (&tm)[4], f32x4 (&acc)[2][4])
 {
-    const int r16 = lane & 15, kg = (lane >> 4) * 8;
+    const int r16 = lane & 15, kg = (lane >> 4) * 8, sb = conv_tile_centre(w, wave, lane);
 #pragma unroll 3
     for (int tap = 0; tap < 9; ++tap) {
         const int dh = tap / 3 - 1, dw = tap - (tap / 3) * 3 - 1;
-        const int soff = (dh * W2 + dw) * kConvCP;
+        const int soff = (dh * w + dw) * kConvCP;
         bf16x8 av[2], bv[4];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
             av[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)(wst + (tap * kConvCo + i * 16 + r16) * kConvCP + kg));
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            bv[j] = pv[j] && (unsigned)(yy[j] + dh) < (unsigned)h
-                        ? __builtin_bit_cast(bf16x8, *(const uint4 *)(xst + sb[j] + soff))
+            bv[j] = (tm[j] >> tap) & 1u
+                        ? __builtin_bit_cast(bf16x8, *(const uint4 *)(xst + sb + j * 16 * kConvCP + soff))
                         : zero8();
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -310,47 +319,46 @@ __device__ __forceinline__ void conv_tile_taps(const uint16_t *wst, const uint16
     }
 }
 
-// A thread's share of staging one chunk: weight vectors t and input vectors
-// u = thread + 256 q, with their LDS destinations (-1: none) and global
-// element offsets (-1: stays zero) that depend on neither the tile nor the
-// chunk; worked out once per workgroup (the input's staged row and column
-// take a division, the per-chunk loads none). An input offset counts from
-// the start of global row row0 - 1 of the tile; weight vector t is (tap, co,
-// v) = (t / 128, t / 4 % 32, t % 4), input vector u is (staged pixel u / 4,
-// v = u % 4).
+// A thread's share of staging one chunk: weight vectors t = thread + 256 q
+// and input vectors u = thread + 256 q, with their LDS destinations (-1:
+// none) and global element offsets (-1: stays zero) that depend on neither
+// the tile nor the chunk; worked out once per workgroup. Weight vector t is
+// (tap, co, v) = (t / 128, t / 4 % 32, t % 4): t + 256 is the same output
+// channel two taps on, so one destination and one source offset serve every
+// q. Input vector u is (staged pixel u / 4, v = u % 4): staged pixel pc is
+// global pixel pc of the rows from row0 - 1 on; its LDS destination (below
+// 2^15) and staged row share one register.
 constexpr int kConvNW = (kConvWVec + 255) / 256, kConvNX = (kConvXVecMax + 255) / 256;
 
 struct ConvStagePlan {
-    int wdst[kConvNW], wsrc[kConvNW];
-    int xdst[kConvNX], xrow[kConvNX], xsrc[kConvNX];
+    int wdst, wsrc;          // weight vector q: wdst + q 64 kConvCP, wsrc + 2 q cin_p
+    int xdr[kConvNX];        // LDS destination | staged row << 16, or -1
+    int xsrc[kConvNX];       // element offset from the start of row row0 - 1
 };
 
-__device__ __forceinline__ void conv_stage_plan(const ConvArgs &a, int R, int co0, ConvStagePlan &P)
+__device__ __forceinline__ void conv_stage_plan(const ConvArgs &a, int R, int lgw, int co0, ConvStagePlan &P)
 {
-    const int W2 = a.w + 2, nin = (R + 2) * W2 * 4;
-#pragma unroll
-    for (int q = 0; q < kConvNW; ++q) {
-        const int t = threadIdx.x + q * 256;
-        const int v = t & 3, rc = t >> 2, tap = rc >> 5, co = co0 + (rc & 31);
-        P.wdst[q] = t < kConvWVec ? rc * kConvCP + v * 8 : -1;
-        P.wsrc[q] = t < kConvWVec && co < a.cout ? co * a.kp + tap * a.cin_p + v * 8 : -1;
-    }
+    const int nin = (R + 2) * a.w * 4;
+    const int t = threadIdx.x, v = t & 3, rc = t >> 2, co = co0 + (rc & 31);
+    P.wdst = rc * kConvCP + v * 8;
+    P.wsrc = co < a.cout ? co * a.kp + (rc >> 5) * a.cin_p + v * 8 : -1;
 #pragma unroll
     for (int q = 0; q < kConvNX; ++q) {
-        const int u = threadIdx.x + q * 256;
-        const int v = u & 3, pc = u >> 2, sr = pc / W2, x = pc - sr * W2 - 1;
-        P.xdst[q] = u < nin ? conv_lds_weights() + pc * kConvCP + v * 8 : -1;
-        P.xrow[q] = sr;
-        P.xsrc[q] = u < nin && (unsigned)x < (unsigned)a.w ? (sr * a.w + x) * a.in_ld + a.in_off + v * 8 : -1;
+        const int u = threadIdx.x + q * 256, pc = u >> 2;
+        P.xdr[q] = u < nin ? (conv_lds_weights() + pc * kConvCP + (u & 3) * 8) | ((pc >> lgw) << 16) : -1;
+        P.xsrc[q] = pc * a.in_ld + a.in_off + (u & 3) * 8;
     }
 }
 
+// Weight vector q of a thread exists (the last q covers half the threads).
+__device__ __forceinline__ bool conv_stage_has_w(int q) { return q * 256 + (int)threadIdx.x < kConvWVec; }
+
 // Input vector q of the chunk at channel offset c0 of the tile whose first
-// row is row0 (zero outside the batch's rows and the image's columns).
+// row is row0 (zero outside the batch's rows).
 __device__ __forceinline__ uint4 conv_stage_load_x(const ConvArgs &a, const ConvStagePlan &P, int q, int row0, int c0)
 {
-    const int g = row0 - 1 + P.xrow[q];
-    if (P.xsrc[q] < 0 || g < 0 || g >= a.n * a.h) return uint4{0u, 0u, 0u, 0u};
+    const int g = row0 - 1 + (P.xdr[q] >> 16);
+    if (P.xdr[q] < 0 || g < 0 || g >= a.n * a.h) return uint4{0u, 0u, 0u, 0u};
     return *(const uint4 *)(a.in + (int64_t)(row0 - 1) * a.w * a.in_ld + P.xsrc[q] + c0);
 }
 
@@ -361,32 +369,36 @@ __device__ __forceinline__ uint4 conv_stage_load_x(const ConvArgs &a, const Conv
 // for memory only when its compute is shorter than a round trip; with one
 // chunk per tile the weights are staged once.
 template <int EPI>
-__global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int lgw, int tiles_per_wg)
+__global__ void __launch_bounds__(256, 3) k_conv_lds(ConvArgs a, int lgw, int tiles_per_wg)
 {
     extern __shared__ __align__(16) uint16_t stage[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int R = 256 >> lgw, W2 = a.w + 2;
+    const int R = 256 >> lgw;
     const int ntiles = (a.n * a.h + R - 1) / R;
     const int t_begin = blockIdx.x * tiles_per_wg, t_end = min(ntiles, t_begin + tiles_per_wg);
     if (t_begin >= t_end) return;
     const int co0 = blockIdx.y * kConvCo;
     const int nch = a.cin_p / kConvCC;
     ConvStagePlan P;
-    conv_stage_plan(a, R, co0, P);
+    conv_stage_plan(a, R, lgw, co0, P);
     uint4 wv[kConvNW], xv[kConvNX];
     auto fetch = [&](int tile, int c0, bool with_w) {
 #pragma unroll
         for (int q = 0; q < kConvNW; ++q)
-            wv[q] = with_w && P.wsrc[q] >= 0 ? *(const uint4 *)(a.wp + P.wsrc[q] + c0) : uint4{0u, 0u, 0u, 0u};
+            wv[q] = with_w && P.wsrc >= 0 && conv_stage_has_w(q)
+                        ? *(const uint4 *)(a.wp + P.wsrc + 2 * q * a.cin_p + c0)
+                        : uint4{0u, 0u, 0u, 0u};
 #pragma unroll
         for (int q = 0; q < kConvNX; ++q) xv[q] = conv_stage_load_x(a, P, q, tile * R, c0);
     };
     fetch(t_begin, 0, true);
     bool with_w = true;
     for (int tile = t_begin; tile < t_end; ++tile) {
-        int sb[4], yy[4];
+        uint32_t tm[4];
+        conv_tile_pixels(a, tile, lgw, wave, lane, tm);
         bool pv[4];
-        conv_tile_pixels(a, tile, lgw, wave, lane, sb, yy, pv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pv[j] = tm[j] != 0u;
         f32x4 acc[2][4];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -397,16 +409,16 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int lgw, int tiles
             if (with_w) {
 #pragma unroll
                 for (int q = 0; q < kConvNW; ++q)
-                    if (P.wdst[q] >= 0) *(uint4 *)(stage + P.wdst[q]) = wv[q];
+                    if (conv_stage_has_w(q)) *(uint4 *)(stage + P.wdst + q * 64 * kConvCP) = wv[q];
             }
 #pragma unroll
             for (int q = 0; q < kConvNX; ++q)
-                if (P.xdst[q] >= 0) *(uint4 *)(stage + P.xdst[q]) = xv[q];
+                if (P.xdr[q] >= 0) *(uint4 *)(stage + (P.xdr[q] & 0xffff)) = xv[q];
             __syncthreads();
             with_w = nch > 1;
             const int nt = ch + 1 < nch ? tile : tile + 1, nc = ch + 1 < nch ? ch + 1 : 0;
             if (nt < t_end) fetch(nt, nc * kConvCC, with_w);
-            conv_tile_taps(stage, stage + conv_lds_weights(), W2, a.h, lane, sb, yy, pv, acc);
+            conv_tile_taps(stage, stage + conv_lds_weights(), a.w, wave, lane, tm, acc);
         }
         conv_epilogue<2, 4, EPI>(a, acc, tile * 256 + wave * 64, co0, pv, lane);
     }
@@ -416,15 +428,17 @@ __global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, int lgw, int tiles
 size_t conv_lds_bytes(int w)
 {
     const int R = 256 / w;
-    return (size_t)(conv_lds_weights() + (R + 2) * (w + 2) * kConvCP) * 2;
+    return (size_t)(conv_lds_weights() + (R + 2) * w * kConvCP) * 2;
 }
 
 // Tiles per workgroup of a k_conv_lds launch: runs sized for about kConvWGs
-// workgroups in all (two per CU at the LDS size, two rounds). Measured
-// against one tile per workgroup: runs of four gain the 64 x 64 layers 10-15 %
-// and the 32 x 32 layers 10 %; layers with fewer tiles than that keep one
-// tile per workgroup (runs of four there cost 2-3x: too few workgroups).
-constexpr int kConvWGs = 1024;
+// workgroups in all (three per CU at the LDS and register size, one round).
+// Measured against one tile per workgroup: runs of four gain the 64 x 64
+// layers 10-15 % and the 32 x 32 layers 10 %; layers with fewer tiles than
+// that keep one tile per workgroup (runs of four there cost 2-3x: too few
+// workgroups). Against 1024 and 1536 workgroups, 768 gains the 64 x 64 and
+// 32 x 32 layers 5-12 % and leaves the 16 x 16 and 8 x 8 ones unchanged.
+constexpr int kConvWGs = 768;
 
 tsg_status launch_conv_lds(const ConvArgs &a, int epi, hipStream_t st)
 {
@@ -548,16 +562,19 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t *in, int n, int h,
 template <int CH>
 constexpr int wgrad9_halo() { return CH + 2 * 64; }
 
-// bf16 element k of a uint2 holding four
-__device__ __forceinline__ uint32_t bf_at(const uint2 &v, int k)
+// Channel c (0..3) of two 4-channel bf16 vectors lo and hi as one bf16 pair
+// (lo's in the low half): one byte permute. v_perm_b32's selector bytes 0-3
+// pick the bytes of its second operand, 4-7 those of its first.
+__device__ __forceinline__ uint32_t pair_at(const uint2 &lo, const uint2 &hi, int c)
 {
-    return ((k < 2 ? v.x : v.y) >> ((k & 1) * 16)) & 0xffffu;
+    const uint32_t l = c < 2 ? lo.x : lo.y, h = c < 2 ? hi.x : hi.y;
+    return __builtin_amdgcn_perm(h, l, (c & 1) ? 0x07060302u : 0x05040100u);
 }
 
-// Eight bf16 (element k of each of e[0..7]) as one 16-byte vector
-__device__ __forceinline__ uint4 pack8(const uint32_t (&e)[8])
+// Channel c of each of v[0..7] as one 16-byte vector of eight bf16
+__device__ __forceinline__ uint4 pack8_at(const uint2 *v, int c)
 {
-    return uint4{e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16)};
+    return uint4{pair_at(v[0], v[1], c), pair_at(v[2], v[3], c), pair_at(v[4], v[5], c), pair_at(v[6], v[7], c)};
 }
 
 template <int CH>
@@ -609,32 +626,21 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
         __syncthreads();  // the previous chunk's LDS reads are done
         if (a_item) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                uint32_t e[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) e[k] = bf_at(va[k], c);
-                *(uint4 *)&sA[lc + c][win * 8] = pack8(e);
-            }
+            for (int c = 0; c < 4; ++c) *(uint4 *)&sA[lc + c][win * 8] = pack8_at(va, c);
         }
         if (b_item) {
             // entry e of copy dw + 1 holds pixel e + dw of the same row (zero
             // past the row's ends); an 8-entry window lies inside one row
             // (w % 8 == 0, and the haloed chunk starts at a row start)
             const bool row_first = (win * 8) % w == 0, row_last = (win * 8 + 8) % w == 0;
+            // vb[0] feeds only entry 0 of copy 0, vb[9] only entry 7 of copy 2
+            if (row_first) vb[0] = uint2{0u, 0u};
+            if (row_last) vb[9] = uint2{0u, 0u};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                uint32_t e0[8], e1[8], e2[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    e0[k] = bf_at(vb[k], c);
-                    e1[k] = bf_at(vb[k + 1], c);
-                    e2[k] = bf_at(vb[k + 2], c);
-                }
-                if (row_first) e0[0] = 0;
-                if (row_last) e2[7] = 0;
-                *(uint4 *)&sB[0][lc + c][win * 8] = pack8(e0);
-                *(uint4 *)&sB[1][lc + c][win * 8] = pack8(e1);
-                *(uint4 *)&sB[2][lc + c][win * 8] = pack8(e2);
+                *(uint4 *)&sB[0][lc + c][win * 8] = pack8_at(vb, c);
+                *(uint4 *)&sB[1][lc + c][win * 8] = pack8_at(vb + 1, c);
+                *(uint4 *)&sB[2][lc + c][win * 8] = pack8_at(vb + 2, c);
             }
         }
         __syncthreads();
@@ -651,8 +657,19 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, b8, acc[t], 0, 0, 0);
             }
         }
-        if (do_bias && tid < 32) {
-            for (int q = 0; q < CH; ++q) bsum += bf2f(sA[tid][q]);
+        if (do_bias) {
+            // output channel tid / 8, pixels (tid % 8) CH / 8 .. + CH / 8 of the chunk
+            const uint4 *src = (const uint4 *)&sA[tid >> 3][(tid & 7) * (CH / 8)];
+#pragma unroll
+            for (int q = 0; q < CH / 64; ++q) {
+                const uint4 v = src[q];
+                const uint32_t e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    bsum += __uint_as_float(e[k] << 16);
+                    bsum += __uint_as_float(e[k] & 0xffff0000u);
+                }
+            }
         }
     }
     const int ci = ci0 + wn + (lane & 15);
@@ -663,7 +680,19 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
             const int co = co0 + wm + (lane >> 4) * 4 + v;
             if (co < cout && ci < cin_p) part[(((int64_t)split * cout + co) * 9 + t) * cin_p + ci] = acc[t][v];
         }
-    if (do_bias && tid < 32 && co0 + tid < cout) bpart[(int64_t)split * cout + co0 + tid] = bsum;
+    if (do_bias) {
+        // the eight partial sums of each output channel, added in order
+        __syncthreads();  // the last chunk's reads of sA are done
+        float *red = reinterpret_cast<float *>(&sA[0][0]);
+        red[tid] = bsum;
+        __syncthreads();
+        if (tid < 32 && co0 + tid < cout) {
+            float b = 0.0f;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) b += red[tid * 8 + g];
+            bpart[(int64_t)split * cout + co0 + tid] = b;
+        }
+    }
 }
 
 // dw[co][tap][ci] = sum over splits of the partials, ci < cin. 32 outputs
