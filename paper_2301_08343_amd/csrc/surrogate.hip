@@ -621,7 +621,9 @@ __global__ void __launch_bounds__(256) k_wgrad9(const uint16_t *in, int n, int h
                 vb[k] = *(const uint2 *)(in + r * in_ld + in_off + ci0 + lc);
         }
     };
-    load(pbeg);
+    // an empty split (none is launched, see tsg_conv_wgrad) writes zero
+    // partials and reads nothing: its halo guard would name rows past the batch
+    if (pbeg < pend) load(pbeg);
     for (int p0 = pbeg; p0 < pend; p0 += CH) {
         __syncthreads();  // the previous chunk's LDS reads are done
         if (a_item) {
@@ -1320,10 +1322,14 @@ tsg_status tsg_conv_wgrad(const uint16_t *in, int32_t n, int32_t h, int32_t w, i
         return fail(-1, "tsg_conv_wgrad: scratch too small");
     hipStream_t st = (hipStream_t)stream;
     const int64_t npix = (int64_t)n * h * w;
-    const int splits = wgrad_splits(npix, h, w, cout, cin_p, taps);
+    int splits = wgrad_splits(npix, h, w, cout, cin_p, taps);
     const int ch9 = wgrad9_chunk(h, w, taps), chunk = ch9 ? ch9 : kWgChunk;
     int pps = (int)((npix + splits - 1) / splits);
     pps = ((pps + chunk - 1) / chunk) * chunk;
+    // rounding the splits up to whole chunks can leave the last ones empty:
+    // only those holding pixels are launched and summed (never more than the
+    // scratch was sized for)
+    if (pps > 0) splits = (int)std::min<int64_t>(splits, (npix + pps - 1) / pps);
     float *bpart = db ? scratch + (size_t)splits * cout * taps * cin_p : nullptr;
     if (ch9) {
         const dim3 grid((cout + 31) / 32, (cin_p + 31) / 32, splits);

@@ -166,6 +166,12 @@ def test_conv_input_gradient(T, case, fuse_gelu):
     (3, 16, 16, 20, 24, 48, 24, 36, 40, 4, 9),
     # 8-pixel rows: the all-taps kernel with 64-pixel chunks (one 8 x 8 image each)
     (5, 8, 8, 32, 32, 64, 32, 64, 64, 0, 9),
+    # 64-pixel chunks of 16- and 64-pixel rows (images of 64 pixels)
+    (4, 4, 16, 32, 32, 32, 0, 32, 32, 0, 9),
+    (3, 1, 64, 32, 32, 32, 0, 32, 32, 0, 9),
+    # 102 splits of the 81920 pixels rounded up to 896 each: the last 10
+    # would be empty (they are not launched; their halo rows lie past the batch)
+    (80, 32, 32, 32, 32, 32, 0, 160, 160, 0, 9),
 ])
 def test_conv_weight_gradient(T, case):
     n, h, w, cin, cin_p, ld, off, cout, gld, goff, taps = case
