@@ -103,6 +103,19 @@ tsg_status tsg_upsample2(const uint16_t *in, int32_t n, int32_t h, int32_t w, in
 tsg_status tsg_upsample2_bwd(const uint16_t *dout, int32_t n, int32_t h, int32_t w, int32_t c, int32_t d_ld,
                              int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, void *stream);
 
+/* The two gradients above followed by the backward through the GELU that
+ * produced the forward input of the pooling (or the upsampled tensor): din is
+ * then (its pooling / upsampling gradient, plus din's old value when
+ * accumulate) times GELU'(z), z the GELU's pre-activation in din's layout
+ * (own stride and offset), in one pass; equal to the plain call followed by
+ * tsg_dgelu up to one BF16 rounding of the intermediate. */
+tsg_status tsg_avgpool2_bwd_dgelu(const uint16_t *dout, int32_t n, int32_t h, int32_t w, int32_t c, int32_t d_ld,
+                                  int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, int32_t accumulate,
+                                  const uint16_t *z, int32_t z_ld, int32_t z_off, void *stream);
+tsg_status tsg_upsample2_bwd_dgelu(const uint16_t *dout, int32_t n, int32_t h, int32_t w, int32_t c, int32_t d_ld,
+                                   int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, const uint16_t *z,
+                                   int32_t z_ld, int32_t z_off, void *stream);
+
 /* Elementwise on views of npix pixels x c channels:
  * tsg_add_inplace: a <- a + b (gradients meeting at a skip connection);
  * tsg_dgelu: d <- d * GELU'(z) (backward through GELU where it cannot be

@@ -713,11 +713,14 @@ __global__ void __launch_bounds__(256) k_wgrad_reduce(const float *part, int spl
     const int64_t total = bias ? cout : (int64_t)cout * taps * cin;
     float s = 0.0f;
     if (idx < total) {
+        // unrolled: eight loads in flight per thread, added in the same order
         if (bias) {
+#pragma unroll 8
             for (int k = g; k < splits; k += 8) s += bpart[(int64_t)k * cout + idx];
         } else {
             const int ci = (int)(idx % cin);
             const int64_t ct = idx / cin;  // co * taps + tap
+#pragma unroll 8
             for (int k = g; k < splits; k += 8) s += part[((int64_t)k * cout * taps + ct) * cin_p + ci];
         }
     }
@@ -938,8 +941,11 @@ __global__ void k_avgpool2_v8(const uint16_t *in, int n, int h, int w, int c, in
     *(uint4 *)(out + q * old + ooff + cg) = pack8(acc);
 }
 
+// z (optional, same layout as din with its own stride and offset): the
+// result is multiplied by GELU'(z), the backward through the GELU that
+// produced the pooled input, in the same pass.
 __global__ void k_avgpool2_bwd_v8(const uint16_t *dout, int n, int h, int w, int c, int dld, int doff, uint16_t *din,
-                                  int ild, int ioff, int accumulate)
+                                  int ild, int ioff, int accumulate, const uint16_t *z, int zld, int zoff)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int g = c / 8;
@@ -955,6 +961,12 @@ __global__ void k_avgpool2_bwd_v8(const uint16_t *dout, int n, int h, int w, int
     if (accumulate) unpack8(*dst, prev);
 #pragma unroll
     for (int k = 0; k < 8; ++k) f[k] = 0.25f * f[k] + prev[k];
+    if (z) {
+        float zz[8];
+        unpack8(*(const uint4 *)(z + q * zld + zoff + cg), zz);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) f[k] *= dgelu(zz[k]);
+    }
     *dst = pack8(f);
 }
 
@@ -971,8 +983,9 @@ __global__ void k_upsample2_v8(const uint16_t *in, int n, int h, int w, int c, i
         *(const uint4 *)(in + ((int64_t)(nn * h + y / 2) * w + x / 2) * ld + off + cg);
 }
 
+// z (optional, same layout as din): the sum is multiplied by GELU'(z).
 __global__ void k_upsample2_bwd_v8(const uint16_t *dout, int n, int h, int w, int c, int dld, int doff, uint16_t *din,
-                                   int ild, int ioff)
+                                   int ild, int ioff, const uint16_t *z, int zld, int zoff)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int g = c / 8;
@@ -989,6 +1002,12 @@ __global__ void k_upsample2_bwd_v8(const uint16_t *dout, int n, int h, int w, in
 #pragma unroll
             for (int k = 0; k < 8; ++k) acc[k] += f[k];
         }
+    if (z) {
+        float zz[8];
+        unpack8(*(const uint4 *)(z + q * zld + zoff + cg), zz);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] *= dgelu(zz[k]);
+    }
     *(uint4 *)(din + q * ild + ioff + cg) = pack8(acc);
 }
 
@@ -1417,7 +1436,8 @@ tsg_status tsg_avgpool2_bwd(const uint16_t *dout, int32_t n, int32_t h, int32_t 
     if (!dout || !din || h % 2 || w % 2) return fail(-1, "tsg_avgpool2_bwd: bad arguments");
     if (v8_ok(dout, c, d_ld, d_off) && v8_ok(din, c, din_ld, din_off)) {
         hipLaunchKernelGGL(k_avgpool2_bwd_v8, dim3(blocks_for((int64_t)n * h * w * (c / 8))), dim3(256), 0,
-                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, accumulate);
+                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, accumulate,
+                           nullptr, 0, 0);
         TSG_LAUNCHED();
         return 0;
     }
@@ -1449,7 +1469,7 @@ tsg_status tsg_upsample2_bwd(const uint16_t *dout, int32_t n, int32_t h, int32_t
     if (!dout || !din) return fail(-1, "tsg_upsample2_bwd: bad arguments");
     if (v8_ok(dout, c, d_ld, d_off) && v8_ok(din, c, din_ld, din_off)) {
         hipLaunchKernelGGL(k_upsample2_bwd_v8, dim3(blocks_for((int64_t)n * h * w * (c / 8))), dim3(256), 0,
-                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off);
+                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, nullptr, 0, 0);
         TSG_LAUNCHED();
         return 0;
     }
@@ -1483,6 +1503,39 @@ tsg_status tsg_dgelu(uint16_t *d, int32_t d_ld, int32_t d_off, const uint16_t *z
                        z, z_ld, z_off, npix, c);
     TSG_LAUNCHED();
     return 0;
+}
+
+tsg_status tsg_avgpool2_bwd_dgelu(const uint16_t *dout, int32_t n, int32_t h, int32_t w, int32_t c, int32_t d_ld,
+                                  int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, int32_t accumulate,
+                                  const uint16_t *z, int32_t z_ld, int32_t z_off, void *stream)
+{
+    if (!dout || !din || !z || h % 2 || w % 2) return fail(-1, "tsg_avgpool2_bwd_dgelu: bad arguments");
+    if (v8_ok(dout, c, d_ld, d_off) && v8_ok(din, c, din_ld, din_off) && v8_ok(z, c, z_ld, z_off)) {
+        hipLaunchKernelGGL(k_avgpool2_bwd_v8, dim3(blocks_for((int64_t)n * h * w * (c / 8))), dim3(256), 0,
+                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, accumulate, z,
+                           z_ld, z_off);
+        TSG_LAUNCHED();
+        return 0;
+    }
+    // layouts the 8-channel kernels do not take: the two passes
+    if (const tsg_status e = tsg_avgpool2_bwd(dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, accumulate, stream))
+        return e;
+    return tsg_dgelu(din, din_ld, din_off, z, z_ld, z_off, n * h * w, c, stream);
+}
+
+tsg_status tsg_upsample2_bwd_dgelu(const uint16_t *dout, int32_t n, int32_t h, int32_t w, int32_t c, int32_t d_ld,
+                                   int32_t d_off, uint16_t *din, int32_t din_ld, int32_t din_off, const uint16_t *z,
+                                   int32_t z_ld, int32_t z_off, void *stream)
+{
+    if (!dout || !din || !z) return fail(-1, "tsg_upsample2_bwd_dgelu: bad arguments");
+    if (v8_ok(dout, c, d_ld, d_off) && v8_ok(din, c, din_ld, din_off) && v8_ok(z, c, z_ld, z_off)) {
+        hipLaunchKernelGGL(k_upsample2_bwd_v8, dim3(blocks_for((int64_t)n * h * w * (c / 8))), dim3(256), 0,
+                           (hipStream_t)stream, dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, z, z_ld, z_off);
+        TSG_LAUNCHED();
+        return 0;
+    }
+    if (const tsg_status e = tsg_upsample2_bwd(dout, n, h, w, c, d_ld, d_off, din, din_ld, din_off, stream)) return e;
+    return tsg_dgelu(din, din_ld, din_off, z, z_ld, z_off, n * h * w, c, stream);
 }
 
 tsg_status tsg_mse(const float *pred, const float *target, int64_t count, float *loss, float *dpred, float *scratch,

@@ -202,6 +202,10 @@ _TSG_SIGS = {
     "tsg_avgpool2_bwd": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _vp]),
     "tsg_upsample2": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp]),
     "tsg_upsample2_bwd": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp]),
+    "tsg_avgpool2_bwd_dgelu": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _i32, _i32,
+                                      _vp]),
+    "tsg_upsample2_bwd_dgelu": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _i32,
+                                       _vp]),
     "tsg_add_inplace": (_i32, [_vp, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _vp]),
     "tsg_dgelu": (_i32, [_vp, _i32, _i32, _vp, _i32, _i32, _i32, _i32, _vp]),
     "tsg_mse": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp]),

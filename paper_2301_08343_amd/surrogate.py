@@ -304,8 +304,8 @@ class Net:
                 dst, zdst = self.gB[l + 1], self.zdb[l + 1]
             else:
                 dst, zdst = self.gmB, self.zmb
-            native.tsg_call("tsg_upsample2_bwd", _ptr(self.gups[l]), n, r // 2, r // 2, hc, hc, 0, _ptr(dst), hc, 0, s)
-            native.tsg_call("tsg_dgelu", _ptr(dst), hc, 0, _ptr(zdst), hc, 0, n * (r // 2) ** 2, hc, s)
+            native.tsg_call("tsg_upsample2_bwd_dgelu", _ptr(self.gups[l]), n, r // 2, r // 2, hc, hc, 0, _ptr(dst), hc, 0,
+                            _ptr(zdst), hc, 0, s)
         r = self.res >> L
         cl = E[L - 1]
         self._wgrad("midb", n, r, self.ma, self.mid, 0, self.mid, self.mid, self.gmB, self.mid, 0)
@@ -315,9 +315,8 @@ class Net:
         self._conv("mida", n, r, self.gmA, self.mid, 0, self.mid, self.gp[L - 1], cl, 0, PLAIN, transposed=True)
         for l in reversed(range(L)):
             r, c = self.res >> l, E[l]
-            npix = n * r * r
-            native.tsg_call("tsg_avgpool2_bwd", _ptr(self.gp[l]), n, r, r, c, c, 0, _ptr(self.gcat[l]), 2 * c, c, 1, s)
-            native.tsg_call("tsg_dgelu", _ptr(self.gcat[l]), 2 * c, c, _ptr(self.zcat[l]), 2 * c, c, npix, c, s)
+            native.tsg_call("tsg_avgpool2_bwd_dgelu", _ptr(self.gp[l]), n, r, r, c, c, 0, _ptr(self.gcat[l]), 2 * c, c, 1,
+                            _ptr(self.zcat[l]), 2 * c, c, s)
             self._wgrad(f"enc{l}b", n, r, self.ea[l], c, 0, c, c, self.gcat[l], 2 * c, c)
             self._conv(f"enc{l}b", n, r, self.gcat[l], 2 * c, c, c, self.gA[l], c, 0, DGELU, self.zea[l], c, 0,
                        transposed=True)

@@ -275,6 +275,25 @@ def test_pool_upsample_and_elementwise(T, c, ld, off):
     T.tsg_call("tsg_dgelu", dd.data_ptr(), c, 0, zd.data_ptr(), c, 0, n * h * w, c, s)
     ref = a * R.gelu_grad(zz)
     assert np.all(np.abs(host(dd) - ref) <= U_BF * np.abs(ref) + 1e-6 * np.abs(a))
+    # the pooling and upsampling gradients with GELU' fused (z in its own
+    # strided layout): one rounding of the product, or two on the scalar path
+    zf = R.round_bf16(rng.standard_normal((n, h, w, c)) * 2)
+    zfd = bf16_dev(pad_channels(zf, c, off, ld))
+    gg = R.gelu_grad(zf)
+    d0 = R.round_bf16(rng.standard_normal((n, h, w, c)))
+    din = bf16_dev(d0)
+    T.tsg_call("tsg_avgpool2_bwd_dgelu", gd.data_ptr(), n, h, w, c, c, 0, din.data_ptr(), c, 0, 1, zfd.data_ptr(), ld,
+               off, s)
+    pre = d0 + R.avgpool2_backward(g)
+    ref = pre * gg
+    assert np.all(np.abs(host(din) - ref) <= 2 * U_BF * np.abs(ref) + 1e-6 * np.abs(pre))
+    ub = torch.zeros(n, h, w, c, dtype=torch.bfloat16, device="cuda")
+    T.tsg_call("tsg_upsample2_bwd_dgelu", bd.data_ptr(), n, h, w, c, c, 0, ub.data_ptr(), c, 0, zfd.data_ptr(), ld, off,
+               s)
+    pre = R.upsample2_backward(big)
+    ref = pre * gg
+    bound = 2 * U_BF * np.abs(ref) + 4 * U_32 * R.upsample2_backward(np.abs(big)) * np.abs(gg) + 1e-6 * np.abs(pre)
+    assert np.all(np.abs(host(ub) - ref) <= bound)
 
 
 def test_to_bf16_pads_channels(T):
