@@ -82,6 +82,8 @@ CONV_CASES = [
     (1, 6, 64, 64, 64, 64, 0, 32, 9),     # 64-pixel rows, 4 rows per workgroup
     (2, 7, 4, 96, 96, 96, 0, 64, 9),      # 4-pixel rows, three 32-channel chunks
     (1, 9, 32, 64, 64, 128, 64, 32, 9),   # 32-pixel rows, second half of a 128-channel buffer
+    (3, 16, 16, 32, 32, 32, 0, 32, 9),    # 16-pixel rows: one whole image per workgroup
+    (2, 64, 64, 32, 32, 32, 0, 32, 9),    # whole 64 x 64 images: edge taps masked on all four sides
 ]
 
 
@@ -122,7 +124,7 @@ def test_conv_forward(T, case, epi):
 
 
 @pytest.mark.parametrize("case", [(2, 9, 7, 32, 32, 9), (1, 16, 16, 64, 128, 9), (2, 6, 5, 48, 24, 9),
-                                  (2, 8, 32, 32, 64, 9)])
+                                  (2, 8, 32, 32, 64, 9), (3, 16, 16, 32, 32, 9)])
 @pytest.mark.parametrize("fuse_gelu", [False, True])
 def test_conv_input_gradient(T, case, fuse_gelu):
     """Transposed, flipped packs give the input gradient; DGELU multiplies by
