@@ -622,6 +622,11 @@ def main():
     out["batch"] = None if args.no_batch else batch_leg()
     if not args.no_surrogate and os.path.exists(args.surrogate):
         out["surrogate"] = surrogate_leg(args)
+    if not args.no_surrogate:
+        # the surrogate's training step on its own (batch 256, random data);
+        # the per-layer table is printed by --surrogate-steps
+        tr = surrogate_steps(10)
+        out["surrogate_training"] = {k: v for k, v in tr.items() if k != "layers"}
     print(json.dumps(out), flush=True)
 
 
