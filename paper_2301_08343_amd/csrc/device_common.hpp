@@ -64,7 +64,9 @@ struct SimDev {
     int g0, g1, g2;        // grid nodes per axis
     int nb0, nb1, nb2;     // grid blocks per axis
     int nblk;
-    int xcd_chunk;         // blocks per XCD chunk of the per-block kernels (xcd_block)
+    int bx0, by0, bz0;     // first block of the box that holds the particles at rest
+    int bxn, byn, bzn;     // its extent in blocks (dispatched first, box_first_block)
+    int box_chunk;         // XCD chunk within that box
     int ts0, ts1, ts2;     // lattice index i lies in tile (i + ts) / B
     int nt0, nt1, nt2;     // tiles per axis
     FastDiv div_nt0, div_nt1, div_n0, div_n1;
@@ -134,6 +136,59 @@ __host__ __device__ __forceinline__ int xcd_block(int i, int n, int C)
     if (C <= 1 || i >= (n / R) * R) return i;
     const int x = i & 7, j = i >> 3;
     return ((j / C) * 8 + x) * C + (j % C);
+}
+
+// Block of dispatch index i for the per-block kernels: first the blocks of
+// a box (x0..x0+xn-1, y0.., z0..; the blocks that hold the particles at
+// rest) in the XCD-aware order of xcd_block, then every other block of the
+// nb0 x nb1 x nb2 grid (the layers below and above the box, then per layer
+// of the box the rows in front of and behind it, then the rest of its rows
+// left and right of it). Workgroups of blocks that hold no particles exit at
+// once, but each holds a slot for the round trip of its count; dispatched
+// after the live ones they wait in the launch's tail instead of between
+// them. A permutation of 0 .. nb0 nb1 nb2 - 1 for any box inside the grid
+// (an empty box included); which workgroup takes a block changes no result.
+__host__ __device__ __forceinline__ int box_first_block(int i, int nb0, int nb1, int nb2, int x0, int y0, int z0, int xn,
+                                                        int yn, int zn, int C)
+{
+    const int nbox = xn * yn * zn;
+    if (i < nbox) {
+        const int k = xcd_block(i, nbox, C), t = k / xn;
+        return (x0 + k % xn) + nb0 * ((y0 + t % yn) + nb1 * (z0 + t / yn));
+    }
+    int j = i - nbox;
+    const int layer = nb0 * nb1;
+    if (j < layer * z0) return j;
+    j -= layer * z0;
+    const int above = layer * (nb2 - z0 - zn);
+    if (j < above) return layer * (z0 + zn) + j;
+    j -= above;
+    const int front = nb0 * y0, back = nb0 * (nb1 - y0 - yn), side = nb0 - xn;
+    const int per_layer = front + back + yn * side;
+    if (per_layer <= 0) return i;  // unreachable: the box layers then hold no other block
+    const int z = z0 + j / per_layer;
+    j %= per_layer;
+    int x, y;
+    if (j < front) {
+        y = j / nb0;
+        x = j % nb0;
+    } else if (j < front + back) {
+        j -= front;
+        y = y0 + yn + j / nb0;
+        x = j % nb0;
+    } else {
+        j -= front + back;
+        y = y0 + j / side;
+        x = j % side;
+        if (x >= x0) x += xn;
+    }
+    return x + nb0 * (y + nb1 * z);
+}
+
+template <typename T>
+__device__ __forceinline__ int dispatch_block(const SimDev<T> &S, int i)
+{
+    return box_first_block(i, S.nb0, S.nb1, S.nb2, S.bx0, S.by0, S.bz0, S.bxn, S.byn, S.bzn, S.box_chunk);
 }
 
 template <int B>

@@ -323,7 +323,7 @@ constexpr int kP2GWG = 512;
 template <typename T, int B, bool FIXDT, int MODEL>
 __global__ void __launch_bounds__(kP2GWG) k_p2g(SimDev<T> S, T fix_coef, T mscale, T pscale, T munit, T punit)
 {
-    p2g_block<T, B, FIXDT, MODEL, kP2GWG>(S, xcd_block(blockIdx.x, S.nblk, S.xcd_chunk), fix_coef, mscale, pscale, munit, punit);
+    p2g_block<T, B, FIXDT, MODEL, kP2GWG>(S, dispatch_block(S, (int)blockIdx.x), fix_coef, mscale, pscale, munit, punit);
 }
 
 // Mass and momentum of grid node (block (bx,by,bz), local (lx,ly,lz)): the sum,
@@ -614,7 +614,7 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
 template <typename T, int B, int CONTACT>
 __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
 {
-    grid_block<T, B, kWG, CONTACT>(S, xcd_block(blockIdx.x, S.nblk, S.xcd_chunk), I, dt);
+    grid_block<T, B, kWG, CONTACT>(S, dispatch_block(S, (int)blockIdx.x), I, dt);
 }
 
 // Zeroes MI over the node box lo..hi (inclusive; x fastest in MI).
@@ -970,7 +970,7 @@ __device__ __forceinline__ void g2p_block(const SimDev<T> &S, const int b, T dt,
 template <typename T, int B, int MODEL, bool SORT>
 __global__ void __launch_bounds__(kWG) k_g2p(SimDev<T> S, T dt, T stress_coef)
 {
-    g2p_block<T, B, MODEL, kWG, SORT>(S, xcd_block(blockIdx.x, S.nblk, S.xcd_chunk), dt, stress_coef);
+    g2p_block<T, B, MODEL, kWG, SORT>(S, dispatch_block(S, (int)blockIdx.x), dt, stress_coef);
 }
 
 

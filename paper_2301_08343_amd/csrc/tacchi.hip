@@ -359,7 +359,22 @@ SimDev<T> make_simdev(tacchi_sim *s)
     S.g0 = d.g[0]; S.g1 = d.g[1]; S.g2 = d.g[2];
     S.nb0 = d.nb[0]; S.nb1 = d.nb[1]; S.nb2 = d.nb[2];
     S.nblk = d.nblk;
-    S.xcd_chunk = 3 * d.nb[0];
+    // the blocks that hold the particles at rest (block_key of the first and
+    // last lattice position per axis) are dispatched first
+    {
+        int lo[3], n[3];
+        for (int a = 0; a < 3; ++a) {
+            const auto blk = [&](double x) {
+                const int cell = std::min(std::max((int)std::floor(x), 0), d.g[a] - 1);
+                return std::min(cell / d.B, d.nb[a] - 1);
+            };
+            lo[a] = blk(d.xr[a]);
+            n[a] = blk(d.xr[a] + (d.n[a] - 1) * d.h[a] / d.dx) - lo[a] + 1;
+        }
+        S.bx0 = lo[0]; S.by0 = lo[1]; S.bz0 = lo[2];
+        S.bxn = n[0]; S.byn = n[1]; S.bzn = n[2];
+        S.box_chunk = 3 * n[0];
+    }
     S.ts0 = d.ts[0]; S.ts1 = d.ts[1]; S.ts2 = d.ts[2];
     S.nt0 = d.nt[0]; S.nt1 = d.nt[1]; S.nt2 = d.nt[2];
     S.div_nt0 = make_fastdiv((uint32_t)d.nt[0]);

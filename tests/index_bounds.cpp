@@ -1,7 +1,7 @@
 // Host-side check of the index arithmetic the MPM kernels share (compiled
 // from the same headers, run on the CPU): the XCD-aware block order is a
 // permutation of the blocks for every block count and chunk size the
-// library uses; the velocity grid's node layout is a bijection; the P2G and
+// library uses, and so is the box-first dispatch order for every box; the velocity grid's node layout is a bijection; the P2G and
 // G2P LDS tile layouts keep every channel of every tile node inside the
 // tile and apart from every other; every tile node the scatter or gather
 // can touch lies in the tile; and the grid update's gather finds, for every
@@ -41,6 +41,49 @@ static void check_xcd_block()
                 if (b >= 0 && b < n) seen[b]++;
             }
             for (int b = 0; b < n; ++b) CHECK(seen[b] == 1, "n=%d C=%d block %d taken %d times", n, C, b, seen[b]);
+        }
+    }
+}
+
+// The box-first dispatch order is a permutation of the grid's blocks for
+// boxes anywhere inside grids of several shapes, the whole grid, one block
+// and an empty box included, and it takes the box's blocks first.
+static void check_box_first()
+{
+    const int grids[][3] = {{32, 32, 8}, {7, 5, 3}, {1, 1, 1}, {4, 9, 2}, {13, 1, 6}};
+    for (const auto &g : grids) {
+        const int nb0 = g[0], nb1 = g[1], nb2 = g[2], n = nb0 * nb1 * nb2;
+        std::vector<int> boxes;  // x0, y0, z0, xn, yn, zn
+        for (int x0 = 0; x0 < nb0; x0 += (nb0 > 6 ? 3 : 1))
+            for (int xn = 0; x0 + xn <= nb0; xn += (nb0 > 6 ? 5 : 1))
+                for (int y0 = 0; y0 < nb1; y0 += (nb1 > 6 ? 4 : 1))
+                    for (int yn = 1; y0 + yn <= nb1; yn += (nb1 > 6 ? 7 : 1))
+                        for (int z0 = 0; z0 < nb2; ++z0)
+                            for (int zn = 1; z0 + zn <= nb2; zn += 2) {
+                                const int bx[6] = {x0, y0, z0, xn, yn, zn};
+                                boxes.insert(boxes.end(), bx, bx + 6);
+                            }
+        const int full[6] = {0, 0, 0, nb0, nb1, nb2};
+        boxes.insert(boxes.end(), full, full + 6);
+        for (size_t q = 0; q < boxes.size(); q += 6) {
+            const int *bx = &boxes[q];
+            const int nbox = bx[3] * bx[4] * bx[5];
+            std::vector<int> seen(n, 0);
+            for (int i = 0; i < n; ++i) {
+                const int b = box_first_block(i, nb0, nb1, nb2, bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], 3 * bx[3]);
+                CHECK(b >= 0 && b < n, "grid %dx%dx%d box (%d,%d,%d)+(%d,%d,%d) i=%d -> %d", nb0, nb1, nb2, bx[0], bx[1],
+                      bx[2], bx[3], bx[4], bx[5], i, b);
+                if (b < 0 || b >= n) continue;
+                seen[b]++;
+                const int x = b % nb0, y = (b / nb0) % nb1, z = b / (nb0 * nb1);
+                const bool in = x >= bx[0] && x < bx[0] + bx[3] && y >= bx[1] && y < bx[1] + bx[4] && z >= bx[2] &&
+                                z < bx[2] + bx[5];
+                CHECK(in == (i < nbox), "grid %dx%dx%d box (%d,%d,%d)+(%d,%d,%d): i=%d -> block %d inside=%d", nb0, nb1,
+                      nb2, bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], i, b, (int)in);
+            }
+            for (int b = 0; b < n; ++b)
+                CHECK(seen[b] == 1, "grid %dx%dx%d box (%d,%d,%d)+(%d,%d,%d): block %d taken %d times", nb0, nb1, nb2,
+                      bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], b, seen[b]);
         }
     }
 }
@@ -138,6 +181,7 @@ static void check_tiles()
 int main()
 {
     check_xcd_block();
+    check_box_first();
     check_node_layout<4>();
     check_node_layout<8>();
     check_tiles<4>();
