@@ -300,6 +300,25 @@ tacchi_status batch_make_contact(tacchi_batch *bt, int i, int tile)
     return TACCHI_OK;
 }
 
+// Work items of the contacts `ids`: every grid block of every contact, the
+// blocks that hold a contact's particles at rest first (contact by contact),
+// then the other blocks of each, so that the workgroups of blocks without
+// particles, which exit after reading their count, wait in the launch's tail
+// instead of between the live ones.
+void batch_push_items(const tacchi_batch *bt, const std::vector<int> &ids, std::vector<BatchItem> &out)
+{
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i : ids) {
+            const Derived &d = bt->sims[i]->d;
+            int lo[3], n[3];
+            rest_block_box(d, lo, n);
+            const int nbox = n[0] * n[1] * n[2];
+            const int b0 = pass == 0 ? 0 : nbox, b1 = pass == 0 ? nbox : d.nblk;
+            for (int k = b0; k < b1; ++k)
+                out.push_back({i, box_first_block(k, d.nb[0], d.nb[1], d.nb[2], lo[0], lo[1], lo[2], n[0], n[1], n[2], 1)});
+        }
+}
+
 // Work items of one group: every grid block of every contact in it.
 tacchi_status batch_build_groups(tacchi_batch *bt)
 {
@@ -313,8 +332,7 @@ tacchi_status batch_build_groups(tacchi_batch *bt)
     std::vector<std::pair<size_t, size_t>> ranges;
     for (auto &kv : by_key) {
         const size_t start = all.size();
-        for (int i : kv.second)
-            for (int b = 0; b < bt->sims[i]->d.nblk; ++b) all.push_back({i, b});
+        batch_push_items(bt, kv.second, all);
         const int i0 = kv.second[0];
         bt->groups.push_back({bt->tile[i0], bt->wg[i0], bt->ipw[i0], bt->cfgs[i0].mat.model, nullptr,
                               (int)(all.size() - start)});
@@ -351,8 +369,8 @@ tacchi_status batch_time_setting(tacchi_batch *bt, const std::vector<int> &ids, 
     for (int i : ids) {
         tacchi_status st = batch_make_contact(bt, i, tile);
         if (st) return st;
-        for (int b = 0; b < bt->sims[i]->d.nblk; ++b) its.push_back({i, b});
     }
+    batch_push_items(bt, ids, its);
     TC_HIP(hipMemcpyAsync(bt->items, its.data(), its.size() * sizeof(BatchItem), hipMemcpyHostToDevice, bt->stream));
     tacchi_status st = batch_reset_step(bt);
     if (st) return st;

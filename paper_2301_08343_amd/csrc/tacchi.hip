@@ -347,6 +347,21 @@ struct KernelTimer {
     }
 };
 
+// The box of grid blocks that hold the particles at rest: blocks lo[a] ..
+// lo[a] + n[a] - 1 per axis (block_key of the first and last lattice
+// position).
+void rest_block_box(const Derived &d, int lo[3], int n[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const auto blk = [&](double x) {
+            const int cell = std::min(std::max((int)std::floor(x), 0), d.g[a] - 1);
+            return std::min(cell / d.B, d.nb[a] - 1);
+        };
+        lo[a] = blk(d.xr[a]);
+        n[a] = blk(d.xr[a] + (d.n[a] - 1) * d.h[a] / d.dx) - lo[a] + 1;
+    }
+}
+
 template <typename T>
 SimDev<T> make_simdev(tacchi_sim *s)
 {
@@ -359,18 +374,10 @@ SimDev<T> make_simdev(tacchi_sim *s)
     S.g0 = d.g[0]; S.g1 = d.g[1]; S.g2 = d.g[2];
     S.nb0 = d.nb[0]; S.nb1 = d.nb[1]; S.nb2 = d.nb[2];
     S.nblk = d.nblk;
-    // the blocks that hold the particles at rest (block_key of the first and
-    // last lattice position per axis) are dispatched first
+    // the blocks that hold the particles at rest are dispatched first
     {
         int lo[3], n[3];
-        for (int a = 0; a < 3; ++a) {
-            const auto blk = [&](double x) {
-                const int cell = std::min(std::max((int)std::floor(x), 0), d.g[a] - 1);
-                return std::min(cell / d.B, d.nb[a] - 1);
-            };
-            lo[a] = blk(d.xr[a]);
-            n[a] = blk(d.xr[a] + (d.n[a] - 1) * d.h[a] / d.dx) - lo[a] + 1;
-        }
+        rest_block_box(d, lo, n);
         S.bx0 = lo[0]; S.by0 = lo[1]; S.bz0 = lo[2];
         S.bxn = n[0]; S.byn = n[1]; S.bzn = n[2];
         S.box_chunk = 3 * n[0];
