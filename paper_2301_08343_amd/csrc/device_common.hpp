@@ -67,6 +67,9 @@ struct SimDev {
     int bx0, by0, bz0;     // first block of the box that holds the particles at rest
     int bxn, byn, bzn;     // its extent in blocks (dispatched first, box_first_block)
     int box_chunk;         // XCD chunk within that box
+    int hx0, hy0, hz0;     // that box grown by one block (clamped to the grid): the grid
+    int hxn, hyn, hzn;     // update's nodes there take the particles' halo, so it goes first
+    int halo_chunk;
     int ts0, ts1, ts2;     // lattice index i lies in tile (i + ts) / B
     int nt0, nt1, nt2;     // tiles per axis
     FastDiv div_nt0, div_nt1, div_n0, div_n1;
@@ -189,6 +192,13 @@ template <typename T>
 __device__ __forceinline__ int dispatch_block(const SimDev<T> &S, int i)
 {
     return box_first_block(i, S.nb0, S.nb1, S.nb2, S.bx0, S.by0, S.bz0, S.bxn, S.byn, S.bzn, S.box_chunk);
+}
+
+// The grid update's order: the particle box grown by one block first.
+template <typename T>
+__device__ __forceinline__ int dispatch_halo_block(const SimDev<T> &S, int i)
+{
+    return box_first_block(i, S.nb0, S.nb1, S.nb2, S.hx0, S.hy0, S.hz0, S.hxn, S.hyn, S.hzn, S.halo_chunk);
 }
 
 template <int B>

@@ -614,7 +614,7 @@ __device__ __forceinline__ void grid_block(const SimDev<T> &S, const int b, cons
 template <typename T, int B, int CONTACT>
 __global__ void __launch_bounds__(kWG) k_grid(SimDev<T> S, IndenterDev<double> I, T dt)
 {
-    grid_block<T, B, kWG, CONTACT>(S, dispatch_block(S, (int)blockIdx.x), I, dt);
+    grid_block<T, B, kWG, CONTACT>(S, dispatch_halo_block(S, (int)blockIdx.x), I, dt);
 }
 
 // Zeroes MI over the node box lo..hi (inclusive; x fastest in MI).

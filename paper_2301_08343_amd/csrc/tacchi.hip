@@ -381,6 +381,14 @@ SimDev<T> make_simdev(tacchi_sim *s)
         S.bx0 = lo[0]; S.by0 = lo[1]; S.bz0 = lo[2];
         S.bxn = n[0]; S.byn = n[1]; S.bzn = n[2];
         S.box_chunk = 3 * n[0];
+        int hl[3], hn[3];
+        for (int a = 0; a < 3; ++a) {
+            hl[a] = std::max(lo[a] - 1, 0);
+            hn[a] = std::min(lo[a] + n[a] + 1, d.nb[a]) - hl[a];
+        }
+        S.hx0 = hl[0]; S.hy0 = hl[1]; S.hz0 = hl[2];
+        S.hxn = hn[0]; S.hyn = hn[1]; S.hzn = hn[2];
+        S.halo_chunk = 3 * hn[0];
     }
     S.ts0 = d.ts[0]; S.ts1 = d.ts[1]; S.ts2 = d.ts[2];
     S.nt0 = d.nt[0]; S.nt1 = d.nt[1]; S.nt2 = d.nt[2];
