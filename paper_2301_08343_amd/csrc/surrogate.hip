@@ -1079,12 +1079,21 @@ __global__ void __launch_bounds__(256) k_mse_partial(const float *pred, const fl
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_mse_final(const float *part, int nparts, float scale, float *loss)
+// 64 lanes: lane l adds partial sums l, l + 64, ... in order (eight loads in
+// flight), then lane 0 adds the 64 lane sums in lane order: a fixed order.
+__global__ void __launch_bounds__(64) k_mse_final(const float *part, int nparts, float scale, float *loss)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ float red[64];
     float s = 0.0f;
-    for (int k = 0; k < nparts; ++k) s += part[k];
-    *loss = s * scale;
+#pragma unroll 8
+    for (int k = (int)threadIdx.x; k < nparts; k += 64) s += part[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int l = 0; l < 64; ++l) t += red[l];
+        *loss = t * scale;
+    }
 }
 
 __global__ void k_adamw(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
