@@ -766,6 +766,58 @@ __global__ void k_head_wgrad(const uint16_t *in, int npix, int in_ld, int in_off
 
 constexpr int kHeadSplits = 4096;
 
+__device__ __forceinline__ void unpack8(uint4 v, float f[8]);
+
+// The same partial sums with 16-byte input loads, for inputs whose channels
+// come in G groups of 8 (cin = 8 G) and CO <= 4 outputs: thread (rs, g)
+// takes rows r0 + rs, r0 + rs + RS, ... (RS = 256 / G row slots) and sums,
+// for its 8 channels and every output, the products (and, for g = 0, the
+// output gradients: the bias), in row order; the RS slots of each value are
+// then added in slot order through LDS. Same partial layout as k_head_wgrad.
+template <int G, int CO>
+__global__ void __launch_bounds__(256) k_head_wgrad_v8(const uint16_t *in, int npix, int in_ld, int in_off,
+                                                       const float *dout, int rows_per_split, float *part)
+{
+    constexpr int RS = 256 / G, CIN = 8 * G, NV = CO * (CIN + 1);
+    __shared__ float red[RS * NV];
+    const int t = threadIdx.x, g = t % G, rs = t / G;
+    const int split = blockIdx.x;
+    const int r0 = split * rows_per_split, r1 = min(npix, r0 + rows_per_split);
+    float acc[CO][8], bacc[CO];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) {
+        bacc[co] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[co][k] = 0.0f;
+    }
+    if (rs < RS) {
+#pragma unroll 4
+        for (int r = r0 + rs; r < r1; r += RS) {
+            float x[8];
+            unpack8(*(const uint4 *)(in + (int64_t)r * in_ld + in_off + g * 8), x);
+#pragma unroll
+            for (int co = 0; co < CO; ++co) {
+                const float gg = dout[(int64_t)r * CO + co];
+                bacc[co] += gg;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc[co][k] += gg * x[k];
+            }
+        }
+#pragma unroll
+        for (int co = 0; co < CO; ++co) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) red[rs * NV + co * (CIN + 1) + g * 8 + k] = acc[co][k];
+            if (g == 0) red[rs * NV + co * (CIN + 1) + CIN] = bacc[co];
+        }
+    }
+    __syncthreads();
+    for (int v = t; v < NV; v += 256) {
+        float sum = 0.0f;
+        for (int q = 0; q < RS; ++q) sum += red[q * NV + v];
+        part[(int64_t)split * NV + v] = sum;
+    }
+}
+
 // Fixed-order sum of the head partials into dw [cout][cin] and db [cout]:
 // one workgroup per value, each thread a strided share of the splits, then a
 // tree in LDS.
@@ -1397,11 +1449,36 @@ tsg_status tsg_conv_wgrad_f32(const uint16_t *in, int32_t n, int32_t h, int32_t 
     if (scratch_bytes < tsg_head_scratch_bytes(cout, cin)) return fail(-1, "tsg_conv_wgrad_f32: scratch too small");
     hipStream_t st = (hipStream_t)stream;
     const int nval = cout * (cin + 1);
-    const int rps = (int)((npix + kHeadSplits - 1) / kHeadSplits);
-    hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadSplits), dim3(((nval + 63) / 64) * 64), 0, st, in, (int)npix, in_ld,
-                       in_off, cin, dout, cout, rps, scratch);
+    int splits = kHeadSplits;
+    if (cin % 8 == 0 && cin <= 32 && cout <= 4 && v8_ok(in, cin, in_ld, in_off)) {
+        // 16-byte loads; at least 16 rows per thread (fewer, larger splits)
+        const int G = cin / 8, RS = 256 / G;
+        splits = (int)std::max<int64_t>(1, std::min<int64_t>(kHeadSplits, npix / (16 * RS)));
+        const int rps = (int)((npix + splits - 1) / splits);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(splits), dim3(256), 0, st, in, (int)npix, in_ld, in_off, dout, rps, scratch);
+        };
+#define TSG_HEAD_V8(GG)                                                      \
+    case GG:                                                                 \
+        if (cout == 1) go(k_head_wgrad_v8<GG, 1>);                           \
+        else if (cout == 2) go(k_head_wgrad_v8<GG, 2>);                      \
+        else if (cout == 3) go(k_head_wgrad_v8<GG, 3>);                      \
+        else go(k_head_wgrad_v8<GG, 4>);                                     \
+        break;
+        switch (G) {
+            TSG_HEAD_V8(1)
+            TSG_HEAD_V8(2)
+            TSG_HEAD_V8(3)
+            default: TSG_HEAD_V8(4)
+        }
+#undef TSG_HEAD_V8
+    } else {
+        const int rps = (int)((npix + kHeadSplits - 1) / kHeadSplits);
+        hipLaunchKernelGGL(k_head_wgrad, dim3(kHeadSplits), dim3(((nval + 63) / 64) * 64), 0, st, in, (int)npix, in_ld,
+                           in_off, cin, dout, cout, rps, scratch);
+    }
     TSG_LAUNCHED();
-    hipLaunchKernelGGL(k_head_reduce, dim3(nval), dim3(256), 0, st, scratch, kHeadSplits, cout, cin, dw, db);
+    hipLaunchKernelGGL(k_head_reduce, dim3(nval), dim3(256), 0, st, scratch, splits, cout, cin, dw, db);
     TSG_LAUNCHED();
     return 0;
 }
